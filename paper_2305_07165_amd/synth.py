@@ -1,0 +1,348 @@
+"""Seeded synthetic inputs for the continuous (box) Gauss transform.
+
+This module builds inputs only.  It holds none of the transform's arithmetic:
+no plane waves, no Gaussian integrals, no tables.  It
+
+* builds a level-restricted adaptive tree that resolves a density
+  (the refinement test of Algorithm 3 of the paper, Eq. (funerr)), followed by
+  2:1 balancing with corner adjacency (Definition treedefs: leaves that share a
+  boundary point differ by at most one level);
+* samples densities at the tensor-product Gauss-Legendre nodes of every leaf,
+  with the node multi-index (i_1..i_d) stored at i_1 + p*i_2 + p^2*i_3;
+* draws the random parameters of the synthetic workloads from a seeded numpy
+  PCG64 generator.
+
+Gauss-Legendre nodes come from numpy's own rule, so neither the oracle nor the
+GPU path shares code with this module: both receive its arrays as inputs.
+
+A tree is a pair of integer arrays: ``levels[nleaves]`` and
+``coords[nleaves, d]``; leaf ``i`` is the box of side ``2**-levels[i]`` whose
+lower corner is ``-1/2 + coords[i] * 2**-levels[i]`` on every axis.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import itertools
+import math
+
+import numpy as np
+from numpy.polynomial import legendre as npleg
+
+# ----------------------------------------------------------------------------
+# geometry of leaves and nodes
+
+
+def gl_nodes(p: int) -> np.ndarray:
+    """Ascending Gauss-Legendre nodes on [-1, 1] (numpy's rule)."""
+    return npleg.leggauss(p)[0]
+
+
+def leaf_centers(levels: np.ndarray, coords: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Centers ``[n, d]`` and side lengths ``[n]`` of the leaves."""
+    L = np.ldexp(1.0, -np.asarray(levels, dtype=np.int64).astype(np.int32))
+    c = -0.5 + (np.asarray(coords, dtype=np.float64) + 0.5) * L[:, None]
+    return c, L
+
+
+def node_offsets(p: int, d: int) -> np.ndarray:
+    """Reference-box node coordinates ``[p**d, d]`` in [-1,1]^d, axis 1 fastest."""
+    eta = gl_nodes(p)
+    f = np.arange(p ** d)
+    return np.stack([eta[(f // p ** a) % p] for a in range(d)], axis=-1)
+
+
+def leaf_points(levels, coords, p: int) -> np.ndarray:
+    """Physical node coordinates of every leaf, ``[n, p**d, d]``."""
+    c, L = leaf_centers(levels, coords)
+    off = node_offsets(p, c.shape[1])
+    return c[:, None, :] + 0.5 * L[:, None, None] * off[None, :, :]
+
+
+def sample(levels, coords, p: int, func, chunk: int = 4096) -> np.ndarray:
+    """Density values at the nodes of every leaf, ``[n, p**d]`` float64."""
+    n = len(levels)
+    d = np.asarray(coords).shape[1]
+    out = np.empty((n, p ** d), dtype=np.float64)
+    for s in range(0, n, chunk):
+        pts = leaf_points(levels[s:s + chunk], coords[s:s + chunk], p)
+        out[s:s + chunk] = func(pts)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# densities
+
+
+@dataclasses.dataclass
+class GaussianSum:
+    """sigma(x) = sum_i a_i exp(-|x - c_i|^2 / w_i^2)  (w is a length)."""
+
+    centers: np.ndarray  # [n, d]
+    widths: np.ndarray   # [n]
+    amps: np.ndarray     # [n]
+    periodic: bool = False  # if True, the blobs are periodized over Z^d
+
+    def __call__(self, x: np.ndarray) -> np.ndarray:
+        x = np.asarray(x, dtype=np.float64)
+        d = x.shape[-1]
+        out = np.zeros(x.shape[:-1])
+        shifts = [np.zeros(d)]
+        if self.periodic:
+            shifts = [np.array(s, dtype=np.float64)
+                      for s in itertools.product((-1, 0, 1), repeat=d)]
+        for c, w, a in zip(self.centers, self.widths, self.amps):
+            for sh in shifts:
+                r2 = np.sum((x - (c + sh)) ** 2, axis=-1)
+                out += a * np.exp(-r2 / (w * w))
+        return out
+
+    def l2norm(self) -> float:
+        """(integral over R^d of sigma^2)^(1/2); the blobs sit well inside B."""
+        d = self.centers.shape[1]
+        s = 0.0
+        for i in range(len(self.amps)):
+            for j in range(len(self.amps)):
+                wi2, wj2 = self.widths[i] ** 2, self.widths[j] ** 2
+                r2 = float(np.sum((self.centers[i] - self.centers[j]) ** 2))
+                s += (self.amps[i] * self.amps[j]
+                      * (math.pi * wi2 * wj2 / (wi2 + wj2)) ** (d / 2)
+                      * math.exp(-r2 / (wi2 + wj2)))
+        return math.sqrt(max(s, 1e-300))
+
+
+@dataclasses.dataclass
+class SinCosProduct:
+    """The periodic density of Eq. (sigmap): sin on odd axes, cos on even
+    axes, all at frequency nu (the paper's n_p in that equation)."""
+
+    nu: int
+    d: int
+
+    def __call__(self, x: np.ndarray) -> np.ndarray:
+        x = np.asarray(x, dtype=np.float64)
+        out = np.ones(x.shape[:-1])
+        for a in range(self.d):
+            f = np.sin if a % 2 == 0 else np.cos
+            out = out * f(2.0 * math.pi * self.nu * x[..., a])
+        return out
+
+    def l2norm(self) -> float:
+        return 0.5 ** (self.d / 2)
+
+
+class Constant:
+    def __init__(self, value: float = 1.0):
+        self.value = value
+
+    def __call__(self, x):
+        return np.full(np.asarray(x).shape[:-1], self.value)
+
+    def l2norm(self) -> float:
+        return abs(self.value)
+
+
+# ----------------------------------------------------------------------------
+# trees
+
+
+def uniform_tree(d: int, level: int) -> tuple[np.ndarray, np.ndarray]:
+    n = 2 ** level
+    grid = np.stack(np.meshgrid(*([np.arange(n)] * d), indexing="ij"), -1)
+    coords = grid.reshape(-1, d)[:, ::-1].copy()  # axis 1 fastest in leaf order
+    levels = np.full(len(coords), level, dtype=np.int32)
+    return levels, coords.astype(np.int32)
+
+
+def _tail_mask(p: int, d: int) -> np.ndarray:
+    """Multi-indices alpha (reference order [a_d,...,a_1]) of the l2 tail
+    ||alpha||_2 >= p used by Eq. (funerr); the last shell when d == 1."""
+    idx = np.stack(np.meshgrid(*([np.arange(p)] * d), indexing="ij"), -1)
+    n2 = np.sqrt(np.sum(idx.astype(np.float64) ** 2, axis=-1))
+    if d == 1:
+        return idx[..., 0] >= p - 2
+    return n2 >= p
+
+
+def _coefficients(vals: np.ndarray, p: int, d: int) -> np.ndarray:
+    """Legendre coefficients of the interpolant on each box: ``vals[nb, p**d]``
+    -> ``[nb, p, ..., p]`` (numpy's Vandermonde solve, axis by axis)."""
+    eta = gl_nodes(p)
+    Vinv = np.linalg.inv(npleg.legvander(eta, p - 1))  # coef = Vinv @ values
+    t = vals.reshape((vals.shape[0],) + (p,) * d)      # [nb, i_d, ..., i_1]
+    for ax in range(1, d + 1):
+        t = np.moveaxis(np.tensordot(Vinv, t, axes=([1], [ax])), 0, ax)
+    return t
+
+
+def resolve_tree(func, d: int, p: int, eps: float, norm: float | None = None,
+                 max_level: int = 12, min_level: int = 0,
+                 periodic: bool = False, chunk: int = 2048):
+    """Adaptive tree that resolves ``func`` (Algorithm 3): a box is split when
+    the RMS of its Legendre tail exceeds eps*||sigma||_2, then the tree is
+    2:1 balanced.  Returns (levels, coords)."""
+    if norm is None:
+        norm = func.l2norm()
+    thr = eps * norm
+    mask = _tail_mask(p, d)
+    leaves_l, leaves_c = [], []
+    boxes = uniform_tree(d, min_level)[1]
+    level = min_level
+    while len(boxes):
+        split = np.zeros(len(boxes), dtype=bool)
+        if level < max_level:
+            for s in range(0, len(boxes), chunk):
+                b = boxes[s:s + chunk]
+                vals = sample(np.full(len(b), level), b, p, func)
+                coef = _coefficients(vals, p, d)
+                e = np.sqrt(np.mean(coef[:, mask] ** 2, axis=1))
+                split[s:s + chunk] = e > thr
+        keep = boxes[~split]
+        leaves_l.append(np.full(len(keep), level, dtype=np.int32))
+        leaves_c.append(keep)
+        parents = boxes[split]
+        kids = [2 * parents + np.array(o, dtype=np.int32)
+                for o in itertools.product((0, 1), repeat=d)]
+        boxes = np.concatenate(kids, 0) if len(parents) else np.zeros((0, d), np.int32)
+        level += 1
+    levels = np.concatenate(leaves_l)
+    coords = np.concatenate(leaves_c, 0).astype(np.int32)
+    return balance(levels, coords, periodic=periodic)
+
+
+def balance(levels, coords, periodic: bool = False):
+    """2:1 balance with corner adjacency: split coarse leaves until every pair
+    of leaves that share a boundary point differs by at most one level."""
+    d = np.asarray(coords).shape[1]
+    leaf = {(int(l), tuple(int(v) for v in c)) for l, c in zip(levels, coords)}
+    dirs = [np.array(o) for o in itertools.product((-1, 0, 1), repeat=d) if any(o)]
+    maxl = max(l for l, _ in leaf)
+
+    def covering(l, q):
+        for ll in range(l, -1, -1):
+            key = (ll, tuple(v >> (l - ll) for v in q))
+            if key in leaf:
+                return key
+        return None
+
+    for l in range(maxl, 1, -1):
+        work = [c for (ll, c) in leaf if ll == l]
+        for c in work:
+            n = 1 << l
+            for o in dirs:
+                q = np.array(c) + o
+                if periodic:
+                    q %= n
+                elif np.any(q < 0) or np.any(q >= n):
+                    continue
+                q = tuple(int(v) for v in q)
+                while True:
+                    key = covering(l, q)
+                    if key is None or key[0] >= l - 1:
+                        break
+                    kl, kc = key
+                    leaf.discard(key)
+                    for b in itertools.product((0, 1), repeat=d):
+                        leaf.add((kl + 1, tuple(2 * kc[a] + b[a] for a in range(d))))
+    items = sorted(leaf)
+    lv = np.array([l for l, _ in items], dtype=np.int32)
+    cs = np.array([c for _, c in items], dtype=np.int32).reshape(-1, d)
+    return lv, cs
+
+
+def is_balanced(levels, coords, periodic: bool = False) -> bool:
+    lv2, _ = balance(levels, coords, periodic)
+    return len(lv2) == len(levels)
+
+
+# ----------------------------------------------------------------------------
+# workloads
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    d: int
+    p: int
+    delta: float
+    tol: float
+    periodic: bool
+    levels: np.ndarray
+    coords: np.ndarray
+    sigma: np.ndarray
+    density: object
+
+    @property
+    def npoints(self) -> int:
+        return int(self.sigma.size)
+
+
+def _blobs(rng, n, d, lo, hi, wlo, whi, log_widths):
+    centers = rng.uniform(lo, hi, size=(n, d))
+    if log_widths:
+        widths = 10.0 ** rng.uniform(math.log10(wlo), math.log10(whi), size=n)
+    else:
+        widths = rng.uniform(wlo, whi, size=n)
+    amps = rng.uniform(-1.0, 1.0, size=n)
+    return centers, widths, amps
+
+
+def small_2d(seed: int = 0) -> Problem:
+    """2D free space, uniform level-3 tree (64 leaves) on [-1/2,1/2]^2, p=8
+    (4096 points), delta=1e-3, four Gaussians with centers U[-0.3,0.3]^2,
+    widths U[0.01,0.05], amplitudes U(-1,1); tol 1e-6."""
+    rng = np.random.default_rng(seed)
+    dens = GaussianSum(*_blobs(rng, 4, 2, -0.3, 0.3, 1e-2, 5e-2, False))
+    lv, cs = uniform_tree(2, 3)
+    return Problem("2d-uniform-l3-p8", 2, 8, 1e-3, 1e-6, False, lv, cs,
+                   sample(lv, cs, 8, dens), dens)
+
+
+def adaptive_3d(seed: int = 0, periodic: bool = False, eps: float = 1e-9,
+                max_level: int = 7, delta: float = 1e-4, tol: float = 1e-10,
+                nblobs: int = 8, wrap_blobs: bool = False) -> Problem:
+    """3D adaptive tree, p=16, resolving sigma = sum of 8 Gaussians (widths
+    log-uniform in [1e-3,1e-2], centers U[-0.4,0.4]^3, amplitudes U(-1,1)) to
+    a Legendre-tail RMS of eps*||sigma||_2, levels capped at max_level."""
+    rng = np.random.default_rng(seed)
+    lo, hi = (-0.5, 0.5) if wrap_blobs else (-0.4, 0.4)
+    dens = GaussianSum(*_blobs(rng, nblobs, 3, lo, hi, 1e-3, 1e-2, True),
+                       periodic=wrap_blobs)
+    lv, cs = resolve_tree(dens, 3, 16, eps, max_level=max_level, periodic=periodic)
+    name = f"3d-adaptive-p16-{'periodic' if periodic else 'free'}"
+    return Problem(name, 3, 16, delta, tol, periodic, lv, cs,
+                   sample(lv, cs, 16, dens), dens)
+
+
+def random_problem(rng, d: int, p: int, delta: float, tol: float, max_level: int,
+                   nblobs: int, periodic: bool = False, eps: float = 1e-9,
+                   min_level: int = 0) -> Problem:
+    """A Gaussian-sum density as in the small 2D workload (centers
+    U[-0.3,0.3]^d, widths U[0.01,0.05], amplitudes U(-1,1)) resolved on an
+    adaptive tree capped at max_level."""
+    dens = GaussianSum(*_blobs(rng, nblobs, d, -0.3, 0.3, 1e-2, 5e-2, False))
+    lv, cs = resolve_tree(dens, d, p, eps, max_level=max_level,
+                          min_level=min_level, periodic=periodic)
+    return Problem(f"{d}d-adaptive-p{p}", d, p, delta, tol, periodic, lv, cs,
+                   sample(lv, cs, p, dens), dens)
+
+
+def point_refined_tree(d: int, point, max_level: int, periodic: bool = False):
+    """Tree refined around one point down to max_level, then 2:1 balanced:
+    a small mixed-level tree for tests."""
+    point = np.asarray(point, dtype=np.float64)
+    leaves = []
+    boxes = [(0, (0,) * d)]
+    while boxes:
+        l, c = boxes.pop()
+        L = 2.0 ** -l
+        lo = -0.5 + np.array(c) * L
+        inside = np.all(point >= lo) and np.all(point < lo + L)
+        if inside and l < max_level:
+            for o in itertools.product((0, 1), repeat=d):
+                boxes.append((l + 1, tuple(2 * c[a] + o[a] for a in range(d))))
+        else:
+            leaves.append((l, c))
+    lv = np.array([l for l, _ in leaves], dtype=np.int32)
+    cs = np.array([c for _, c in leaves], dtype=np.int32).reshape(-1, d)
+    return balance(lv, cs, periodic=periodic)
