@@ -1,0 +1,115 @@
+"""ctypes declarations of the C ABI in include/fgt.h (argument marshalling only).
+
+Every step of the transform runs in libfgt.so's HIP kernels; there is no CPU
+fallback.  If the library is missing this module raises on first use.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfgt.so")
+
+FGT_OK = 0
+FGT_ERR_INVALID_ARG = -1
+FGT_ERR_NOT_TILING = -2
+FGT_ERR_NOT_BALANCED = -3
+FGT_ERR_OOM = -4
+FGT_ERR_UNSUPPORTED = -5
+FGT_ERR_HIP = -6
+FGT_FREE = 0
+FGT_PERIODIC = 1
+FGT_FP64 = 0
+FGT_FP32 = 1
+
+EXPORTED = ["fgt_plan", "fgt_execute", "fgt_sync", "fgt_plan_info", "fgt_stage_times",
+            "fgt_destroy", "fgt_strerror", "fgt_last_error", "fgt_pw_terms",
+            "fgt_periodic_terms", "fgt_plan_array"]
+
+
+class fgt_tree_t(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nleaves", ctypes.c_int64),
+                ("level", ctypes.POINTER(ctypes.c_int32)),
+                ("coord", ctypes.POINTER(ctypes.c_int32))]
+
+
+class fgt_opts_t(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("eps_internal", ctypes.c_double),
+                ("force_lc", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("own_stream", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("host_only", ctypes.c_int32)]
+
+
+class fgt_info_t(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("p", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("lc", ctypes.c_int32),
+                ("lmin", ctypes.c_int32), ("lmax", ctypes.c_int32),
+                ("nf", ctypes.c_int32), ("nr", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("tol", ctypes.c_double), ("eps", ctypes.c_double),
+                ("D0", ctypes.c_double), ("R", ctypes.c_double), ("h", ctypes.c_double),
+                ("nleaves", ctypes.c_int64), ("npoints", ctypes.c_int64),
+                ("n_pwbox", ctypes.c_int64), ("n_pwleaf", ctypes.c_int64),
+                ("n_plist", ctypes.c_int64), ("n_near_target", ctypes.c_int64),
+                ("n_near_pair", ctypes.c_int64),
+                ("flops_form", ctypes.c_double), ("flops_eval", ctypes.c_double),
+                ("flops_translate", ctypes.c_double), ("flops_near", ctypes.c_double),
+                ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libfgt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the transform has no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.fgt_plan.restype = ctypes.c_int
+        L.fgt_plan.argtypes = [ctypes.POINTER(fgt_tree_t), ctypes.c_int, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int, ctypes.POINTER(fgt_opts_t),
+                               ctypes.POINTER(vp)]
+        L.fgt_execute.restype = ctypes.c_int
+        L.fgt_execute.argtypes = [vp, vp, vp]
+        L.fgt_sync.restype = ctypes.c_int
+        L.fgt_sync.argtypes = [vp]
+        L.fgt_plan_info.restype = ctypes.c_int
+        L.fgt_plan_info.argtypes = [vp, ctypes.POINTER(fgt_info_t)]
+        L.fgt_stage_times.restype = ctypes.c_int
+        L.fgt_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        L.fgt_destroy.restype = None
+        L.fgt_destroy.argtypes = [vp]
+        L.fgt_strerror.restype = ctypes.c_char_p
+        L.fgt_strerror.argtypes = [ctypes.c_int]
+        L.fgt_last_error.restype = ctypes.c_char_p
+        L.fgt_last_error.argtypes = []
+        L.fgt_pw_terms.restype = ctypes.c_int
+        L.fgt_pw_terms.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.fgt_periodic_terms.restype = ctypes.c_int
+        L.fgt_periodic_terms.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.fgt_plan_array.restype = ctypes.c_int64
+        L.fgt_plan_array.argtypes = [vp, ctypes.c_char_p, vp, ctypes.c_int64]
+        _lib = L
+    return _lib
+
+
+class FgtError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        L = lib()
+        detail = L.fgt_last_error().decode()
+        super().__init__(f"{what}: {L.fgt_strerror(code).decode()} ({code}): {detail}")
+        self.code = code
+
+
+def check(code: int, what: str) -> int:
+    if code < 0:
+        raise FgtError(code, what)
+    return code

@@ -1,0 +1,171 @@
+"""Python binding of the C ABI (include/fgt.h), argument marshalling only.
+
+Functions carry the C names (``fgt_plan``, ``fgt_execute``, ...).  ``Plan`` is
+a small owner object on top of them.  sigma/u are torch tensors on the GPU
+(or anything with ``data_ptr()``); no arithmetic of the transform happens here.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import FGT_FP32, FGT_FP64, FGT_FREE, FGT_PERIODIC, FgtError, check
+
+_PRECISION = {"fp64": FGT_FP64, "fp32": FGT_FP32}
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def fgt_plan(levels, coords, p: int, delta: float, tol: float, bc: int = FGT_FREE,
+             precision: int = FGT_FP64, eps_internal: float = 0.0, force_lc: int = -1,
+             stream: int = 0, profile: bool = False, host_only: bool = False,
+             own_stream: bool = False) -> int:
+    """Plans a transform; returns the opaque plan handle (an int)."""
+    L = _lib.lib()
+    levels = np.ascontiguousarray(levels, dtype=np.int32)
+    coords = np.ascontiguousarray(coords, dtype=np.int32)
+    if coords.ndim != 2 or coords.shape[0] != levels.shape[0]:
+        raise ValueError("coords must be [nleaves, dim] matching levels")
+    tree = _lib.fgt_tree_t(coords.shape[1], levels.shape[0],
+                           levels.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           coords.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    opts = _lib.fgt_opts_t(int(precision), float(eps_internal), int(force_lc),
+                           ctypes.c_void_p(int(stream) or None), int(bool(own_stream)),
+                           int(bool(profile)), int(bool(host_only)))
+    h = ctypes.c_void_p()
+    check(L.fgt_plan(ctypes.byref(tree), int(p), float(delta), float(tol), int(bc),
+                     ctypes.byref(opts), ctypes.byref(h)), "fgt_plan")
+    return h.value
+
+
+def fgt_execute(plan: int, sigma, u) -> None:
+    check(_lib.lib().fgt_execute(plan, _ptr(sigma), _ptr(u)), "fgt_execute")
+
+
+def fgt_sync(plan: int) -> None:
+    check(_lib.lib().fgt_sync(plan), "fgt_sync")
+
+
+def fgt_plan_info(plan: int) -> dict:
+    info = _lib.fgt_info_t()
+    check(_lib.lib().fgt_plan_info(plan, ctypes.byref(info)), "fgt_plan_info")
+    return info.as_dict()
+
+
+STAGES = ("form_leaf", "form_box", "translate", "eval_box", "eval_leaf", "near")
+
+
+def fgt_stage_times(plan: int) -> dict:
+    ms = (ctypes.c_double * 6)()
+    n = check(_lib.lib().fgt_stage_times(plan, ms, 6), "fgt_stage_times")
+    return {STAGES[i]: ms[i] for i in range(n)}
+
+
+def fgt_destroy(plan: int) -> None:
+    if plan:
+        _lib.lib().fgt_destroy(plan)
+
+
+def fgt_strerror(code: int) -> str:
+    return _lib.lib().fgt_strerror(code).decode()
+
+
+def fgt_pw_terms(eps: float, r_over_d0: float) -> int:
+    return check(_lib.lib().fgt_pw_terms(eps, r_over_d0), "fgt_pw_terms")
+
+
+def fgt_periodic_terms(eps: float, delta: float) -> int:
+    return check(_lib.lib().fgt_periodic_terms(eps, delta), "fgt_periodic_terms")
+
+
+_DOUBLE_ARRAYS = {"F", "E", "V", "rot"}
+
+
+def fgt_plan_array(plan: int, name: str) -> np.ndarray:
+    L = _lib.lib()
+    n = check(L.fgt_plan_array(plan, name.encode(), None, 0), "fgt_plan_array")
+    dt = np.float64 if name in _DOUBLE_ARRAYS else np.int32
+    out = np.zeros(n, dtype=dt)
+    if n:
+        check(L.fgt_plan_array(plan, name.encode(), out.ctypes.data, n), "fgt_plan_array")
+    return out
+
+
+class Plan:
+    """Owns one plan.  ``execute(sigma)`` returns u (a new tensor like sigma).
+
+    By default the plan runs on torch's current stream of the current device,
+    so it is ordered with the torch work that produces sigma and consumes u.
+    """
+
+    def __init__(self, levels, coords, p: int, delta: float, tol: float,
+                 periodic: bool = False, precision: str = "fp64", eps_internal: float = 0.0,
+                 force_lc: int = -1, stream=None, profile: bool = False,
+                 host_only: bool = False, own_stream: bool = False):
+        if stream is None and not host_only and not own_stream:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        self.p = int(p)
+        self.dim = int(np.asarray(coords).shape[1])
+        self.nleaves = int(np.asarray(levels).shape[0])
+        self.handle = 0
+        self.handle = fgt_plan(levels, coords, p, delta, tol,
+                               FGT_PERIODIC if periodic else FGT_FREE,
+                               _PRECISION[precision], eps_internal, force_lc,
+                               int(stream or 0), profile, host_only, own_stream)
+
+    def execute(self, sigma, u=None):
+        if u is None:
+            import torch
+            u = torch.empty_like(sigma)
+        expect = (self.nleaves, self.p ** self.dim)
+        for name, t in (("sigma", sigma), ("u", u)):
+            if hasattr(t, "shape"):
+                if tuple(t.shape) != expect:
+                    raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {expect}")
+                if str(getattr(t, "dtype", "torch.float64")) != "torch.float64":
+                    raise ValueError(f"{name} must be float64")
+                if hasattr(t, "is_cuda") and not t.is_cuda:
+                    raise ValueError(f"{name} must be a device tensor")
+                if hasattr(t, "is_contiguous") and not t.is_contiguous():
+                    raise ValueError(f"{name} must be contiguous")
+        fgt_execute(self.handle, sigma, u)
+        return u
+
+    def sync(self):
+        fgt_sync(self.handle)
+
+    def info(self) -> dict:
+        return fgt_plan_info(self.handle)
+
+    def stage_times(self) -> dict:
+        return fgt_stage_times(self.handle)
+
+    def array(self, name: str) -> np.ndarray:
+        return fgt_plan_array(self.handle, name)
+
+    def close(self):
+        if self.handle:
+            fgt_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

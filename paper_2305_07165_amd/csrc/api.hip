@@ -1,0 +1,346 @@
+// C ABI of the box Gauss transform: plan lifecycle, upload, execution.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fgt_host.h"
+#include "kernels.h"
+#include "../../include/fgt.h"
+
+struct fgt_plan {
+  fgt::HostPlan hp;
+  bool host_only = true;
+  int device = -1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool profile = false;
+  bool ev_ready = false;
+  hipEvent_t ev[7] = {};
+  std::vector<void*> allocs;
+  int64_t device_bytes = 0;
+  fgt::DeviceArgs args;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return FGT_ERR_HIP;
+}
+
+template <typename X>
+int upload(fgt_plan_t* pl, const X* src, size_t n, void** out) {
+  *out = nullptr;
+  if (n == 0) return FGT_OK;
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, n * sizeof(X));
+  if (e != hipSuccess) return fail(FGT_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  pl->allocs.push_back(d);
+  pl->device_bytes += (int64_t)(n * sizeof(X));
+  e = hipMemcpy(d, src, n * sizeof(X), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  *out = d;
+  return FGT_OK;
+}
+
+int alloc(fgt_plan_t* pl, size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) return FGT_OK;
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return fail(FGT_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  pl->allocs.push_back(d);
+  pl->device_bytes += (int64_t)bytes;
+  *out = d;
+  return FGT_OK;
+}
+
+int upload_i32(fgt_plan_t* pl, const std::vector<int32_t>& v, const int32_t** out) {
+  void* d;
+  int rc = upload(pl, v.data(), v.size(), &d);
+  *out = static_cast<const int32_t*>(d);
+  return rc;
+}
+
+int upload_table(fgt_plan_t* pl, const std::vector<double>& v, bool fp32, const void** out) {
+  void* d;
+  int rc;
+  if (fp32) {
+    std::vector<float> f(v.size());
+    for (size_t i = 0; i < v.size(); i++) f[i] = (float)v[i];  // rounded once
+    rc = upload(pl, f.data(), f.size(), &d);
+  } else {
+    rc = upload(pl, v.data(), v.size(), &d);
+  }
+  *out = d;
+  return rc;
+}
+
+double ipowd(double b, int e) {
+  double r = 1;
+  for (int i = 0; i < e; i++) r *= b;
+  return r;
+}
+
+int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
+  fgt::HostPlan& hp = pl->hp;
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const bool fp32 = hp.precision == FGT_FP32;
+  const size_t ts = fp32 ? sizeof(float) : sizeof(double);
+  int lds_max = 0;
+  e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  size_t need = std::max(fgt::lds_form_leaf(hp.d, hp.p, hp.nr, ts),
+                         std::max(fgt::lds_eval_leaf(hp.d, hp.p, hp.nr, ts), fgt::lds_near(hp.d, hp.p, ts)));
+  if (need > (size_t)lds_max)
+    return fail(FGT_ERR_UNSUPPORTED, "stage needs " + std::to_string(need) + " bytes of LDS, device allows " +
+                                         std::to_string(lds_max));
+  fgt::DeviceArgs& a = pl->args;
+  a.d = hp.d;
+  a.p = hp.p;
+  a.nr = hp.nr;
+  a.M = hp.pw.M;
+  a.fp32 = fp32;
+  a.nA = hp.n_pwbox();
+  a.nL = hp.n_pwleaf();
+  a.nE = (int64_t)hp.echunk.size() / 3;
+  a.nT = hp.n_near_tgt();
+  int rc;
+  if ((rc = upload_table(pl, hp.F, fp32, &a.F)) || (rc = upload_table(pl, hp.E, fp32, &a.E)) ||
+      (rc = upload_table(pl, hp.V, fp32, &a.V)) || (rc = upload_table(pl, hp.rot, fp32, &a.rot)))
+    return rc;
+  if ((rc = upload_i32(pl, hp.pw_start, &a.pw_start)) || (rc = upload_i32(pl, hp.pwleaf_id, &a.pwleaf_id)) ||
+      (rc = upload_i32(pl, hp.pwleaf_tab, &a.pwleaf_tab)) ||
+      (rc = upload_i32(pl, hp.plist_start, &a.plist_start)) ||
+      (rc = upload_i32(pl, hp.plist_src, &a.plist_src)) || (rc = upload_i32(pl, hp.plist_dir, &a.plist_dir)) ||
+      (rc = upload_i32(pl, hp.echunk, &a.echunk)) || (rc = upload_i32(pl, hp.near_tgt, &a.near_tgt)) ||
+      (rc = upload_i32(pl, hp.near_haspw, &a.near_haspw)) ||
+      (rc = upload_i32(pl, hp.near_start, &a.near_start)) || (rc = upload_i32(pl, hp.near_src, &a.near_src)) ||
+      (rc = upload_i32(pl, hp.near_tab, &a.near_tab)))
+    return rc;
+  const size_t n2 = (size_t)ipowd(hp.nr, hp.d - 1);
+  const size_t ncoef = n2 * hp.nr;
+  if ((rc = alloc(pl, (size_t)a.nL * hp.p * n2 * ts, &a.Y)) ||
+      (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.phi)) || (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.psi)))
+    return rc;
+  if (opts && opts->own_stream) {
+    e = hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    pl->own_stream = true;
+  } else {
+    pl->stream = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+  }
+  if (pl->profile) {
+    for (int i = 0; i < 7; i++) {
+      e = hipEventCreate(&pl->ev[i]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    pl->ev_ready = true;
+  }
+  pl->host_only = false;
+  return FGT_OK;
+}
+
+void release(fgt_plan_t* pl) {
+  if (!pl) return;
+  if (!pl->host_only || !pl->allocs.empty()) {
+    if (pl->device >= 0) (void)hipSetDevice(pl->device);
+    (void)hipStreamSynchronize(pl->stream);
+  }
+  if (pl->ev_ready)
+    for (int i = 0; i < 7; i++) (void)hipEventDestroy(pl->ev[i]);
+  for (void* p : pl->allocs) (void)hipFree(p);
+  if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
+  delete pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fgt_plan(const fgt_tree_t* tree, int p, double delta, double tol, int bc, const fgt_opts_t* opts,
+             fgt_plan_t** out) {
+  if (!out) return fail(FGT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!tree) return fail(FGT_ERR_INVALID_ARG, "tree is NULL");
+  fgt_opts_t o{};
+  o.force_lc = -1;
+  if (opts) o = *opts;
+  fgt_plan_t* pl = new (std::nothrow) fgt_plan_t();
+  if (!pl) return fail(FGT_ERR_OOM, "host allocation");
+  pl->profile = o.profile != 0;
+  std::string err;
+  int rc;
+  try {
+    rc = fgt::build_host_plan(tree->dim, tree->nleaves, tree->level, tree->coord, p, delta, tol, bc,
+                              o.precision, o.eps_internal, o.force_lc, pl->hp, err);
+  } catch (const std::bad_alloc&) {
+    rc = FGT_ERR_OOM;
+    err = "host allocation";
+  } catch (...) {
+    rc = FGT_ERR_INVALID_ARG;
+    err = "unexpected exception while planning";
+  }
+  if (rc != FGT_OK) {
+    delete pl;
+    return fail(rc, err);
+  }
+  if (!o.host_only) {
+    rc = setup_device(pl, &o);
+    if (rc != FGT_OK) {
+      std::string keep = g_err;
+      release(pl);
+      return fail(rc, keep);
+    }
+  }
+  *out = pl;
+  return FGT_OK;
+}
+
+int fgt_execute(fgt_plan_t* pl, const double* sigma, double* u) {
+  if (!pl) return fail(FGT_ERR_INVALID_ARG, "plan is NULL");
+  if (pl->host_only) return fail(FGT_ERR_INVALID_ARG, "host-only plan cannot execute");
+  if (!sigma || !u) return fail(FGT_ERR_INVALID_ARG, "sigma/u is NULL");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = fgt::launch_transform(pl->args, sigma, u, pl->stream, pl->profile ? pl->ev : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return FGT_OK;
+}
+
+int fgt_sync(fgt_plan_t* pl) {
+  if (!pl) return fail(FGT_ERR_INVALID_ARG, "plan is NULL");
+  if (pl->host_only) return FGT_OK;
+  hipError_t e = hipSetDevice(pl->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return FGT_OK;
+}
+
+int fgt_stage_times(const fgt_plan_t* pl, double* ms, int n) {
+  if (!pl || !ms) return fail(FGT_ERR_INVALID_ARG, "NULL argument");
+  if (!pl->ev_ready) return 0;
+  int k = 0;
+  for (int i = 0; i < 6 && k < n; i++, k++) {
+    float t = 0;
+    hipError_t e = hipEventElapsedTime(&t, pl->ev[i], pl->ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    ms[k] = t;
+  }
+  return k;
+}
+
+int fgt_plan_info(const fgt_plan_t* pl, fgt_info_t* info) {
+  if (!pl || !info) return fail(FGT_ERR_INVALID_ARG, "NULL argument");
+  const fgt::HostPlan& hp = pl->hp;
+  std::memset(info, 0, sizeof(*info));
+  info->dim = hp.d;
+  info->p = hp.p;
+  info->bc = hp.bc;
+  info->precision = hp.precision;
+  info->lc = hp.lc;
+  info->lmin = hp.lmin;
+  info->lmax = hp.lmax;
+  info->nf = 2 * hp.pw.M;
+  info->nr = hp.nr;
+  info->delta = hp.delta;
+  info->tol = hp.tol;
+  info->eps = hp.pw.eps;
+  info->D0 = hp.pw.D0;
+  info->R = hp.pw.R;
+  info->h = hp.pw.h;
+  info->nleaves = hp.nleaves;
+  const double pd = ipowd(hp.p, hp.d);
+  info->npoints = (int64_t)(hp.nleaves * pd);
+  info->n_pwbox = hp.n_pwbox();
+  info->n_pwleaf = hp.n_pwleaf();
+  info->n_plist = hp.n_plist();
+  info->n_near_target = hp.n_near_tgt();
+  info->n_near_pair = hp.n_near_pair();
+  double per_leaf = 0;
+  for (int a = 1; a <= hp.d; a++) per_leaf += 2.0 * ipowd(hp.nr, a) * ipowd(hp.p, hp.d - a + 1);
+  info->flops_form = per_leaf * hp.n_pwleaf();
+  info->flops_eval = per_leaf * hp.n_pwleaf();
+  info->flops_translate = (3.0 * hp.d + 1.0) * ipowd(hp.nr, hp.d) * hp.n_plist();
+  info->flops_near = 2.0 * hp.d * ipowd(hp.p, hp.d + 1) * hp.n_near_pair();
+  const double ts = hp.precision == FGT_FP32 ? 4.0 : 8.0;
+  info->bytes_min = 16.0 * hp.nleaves * pd + 4.0 * ts * ipowd(hp.nr, hp.d) * hp.n_pwbox();
+  info->device_bytes = pl->device_bytes;
+  return FGT_OK;
+}
+
+void fgt_destroy(fgt_plan_t* pl) { release(pl); }
+
+const char* fgt_strerror(int code) {
+  switch (code) {
+    case FGT_OK: return "ok";
+    case FGT_ERR_INVALID_ARG: return "invalid argument";
+    case FGT_ERR_NOT_TILING: return "leaves do not tile the unit box";
+    case FGT_ERR_NOT_BALANCED: return "tree is not level-restricted";
+    case FGT_ERR_OOM: return "out of memory";
+    case FGT_ERR_UNSUPPORTED: return "unsupported configuration";
+    case FGT_ERR_HIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+const char* fgt_last_error(void) { return g_err.c_str(); }
+
+int fgt_pw_terms(double eps, double r_over_d0) {
+  if (!(eps > 0 && eps < 0.1) || !(r_over_d0 >= 1.0)) return FGT_ERR_INVALID_ARG;
+  const double D0 = std::sqrt(std::log(3.0 / eps));
+  return 2 * fgt::pw_params(eps, r_over_d0 * D0).M;
+}
+
+int fgt_periodic_terms(double eps, double delta) {
+  if (!(eps > 0 && eps < 1) || !(delta > 0)) return FGT_ERR_INVALID_ARG;
+  return (int)std::ceil(std::sqrt(std::log(1.0 / eps)) / (M_PI * std::sqrt(delta)));
+}
+
+int64_t fgt_plan_array(const fgt_plan_t* pl, const char* name, void* dst, int64_t cap) {
+  if (!pl || !name) return fail(FGT_ERR_INVALID_ARG, "NULL argument");
+  const fgt::HostPlan& hp = pl->hp;
+  const std::vector<double>* dv = nullptr;
+  const std::vector<int32_t>* iv = nullptr;
+  std::string n(name);
+  if (n == "F") dv = &hp.F;
+  else if (n == "E") dv = &hp.E;
+  else if (n == "V") dv = &hp.V;
+  else if (n == "rot") dv = &hp.rot;
+  else if (n == "pwbox_isleaf") iv = &hp.pwbox_isleaf;
+  else if (n == "pw_start") iv = &hp.pw_start;
+  else if (n == "pwleaf_id") iv = &hp.pwleaf_id;
+  else if (n == "pwleaf_tab") iv = &hp.pwleaf_tab;
+  else if (n == "plist_start") iv = &hp.plist_start;
+  else if (n == "plist_src") iv = &hp.plist_src;
+  else if (n == "plist_dir") iv = &hp.plist_dir;
+  else if (n == "echunk") iv = &hp.echunk;
+  else if (n == "near_tgt") iv = &hp.near_tgt;
+  else if (n == "near_haspw") iv = &hp.near_haspw;
+  else if (n == "near_start") iv = &hp.near_start;
+  else if (n == "near_src") iv = &hp.near_src;
+  else if (n == "near_tab") iv = &hp.near_tab;
+  else if (n == "ftab_meta") iv = &hp.ftab_meta;
+  else if (n == "vtab_meta") iv = &hp.vtab_meta;
+  else return fail(FGT_ERR_INVALID_ARG, "unknown array name");
+  if (dv) {
+    if (dst && cap > 0) std::memcpy(dst, dv->data(), sizeof(double) * std::min<int64_t>(cap, dv->size()));
+    return (int64_t)dv->size();
+  }
+  if (dst && cap > 0) std::memcpy(dst, iv->data(), sizeof(int32_t) * std::min<int64_t>(cap, iv->size()));
+  return (int64_t)iv->size();
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Host-side plan of the box Gauss transform: parameters, flat tree lists and
+// the FP64 one-dimensional tables.  Built once by fgt_plan(), then uploaded.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fgt {
+
+constexpr int kMaxDim = 3;
+constexpr int kMaxP = 16;      // nodes per axis handled by the kernels
+constexpr int kMaxModes = 128; // real plane-wave modes per axis (2M-1)
+
+// Plane-wave parameters of Theorem 1 for tolerance eps and range R (units of
+// sqrt(delta)): D0 = sqrt(log(3/eps)), h = 2 pi/(R + D0), M = ceil(D0 (R+D0)/pi).
+struct PwParams {
+  double eps = 0, D0 = 0, R = 0, h = 0;
+  int M = 0;
+};
+PwParams pw_params(double eps, double R);
+
+struct HostPlan {
+  // problem
+  int d = 0, p = 0, bc = 0, precision = 0;
+  double delta = 0, tol = 0;
+  int64_t nleaves = 0;
+  std::vector<int32_t> level, coord;  // caller order, coord[i*d+a]
+  int lmin = 0, lmax = 0;
+
+  // method parameters
+  int lc = 0;          // cutoff level
+  double Llc = 1;      // side of a cutoff-level box
+  PwParams pw;         // eps, D0, R, h, M
+  int nr = 0;          // real modes per axis, 2M-1
+  double sqrt_delta = 0;
+
+  // plane-wave boxes (cutoff level, f = 1), Morton order
+  std::vector<int32_t> pwbox_isleaf;  // [nA]
+  std::vector<int32_t> pw_start;      // [nA+1] ranges of pw leaves per box
+  std::vector<int32_t> pwleaf_id;     // [nL] caller leaf index
+  std::vector<int32_t> pwleaf_tab;    // [nL*d] form/eval table id per axis
+  std::vector<int32_t> plist_start;   // [nA+1]
+  std::vector<int32_t> plist_src;     // [nP] plane-wave box index
+  std::vector<int32_t> plist_dir;     // [nP] sum_a (dir_a+1) 3^a, dir = src - dst
+  // evaluation work items: (box, first pw leaf, count) with count*p <= 64 rows
+  std::vector<int32_t> echunk;        // [nE*3]
+
+  // near field: targets at level <= lc, gather lists
+  std::vector<int32_t> near_tgt;      // [nT] caller leaf index
+  std::vector<int32_t> near_haspw;    // [nT] 1 if the leaf also receives a pw evaluation
+  std::vector<int32_t> near_start;    // [nT+1]
+  std::vector<int32_t> near_src;      // [nN] caller leaf index
+  std::vector<int32_t> near_tab;      // [nN*d] near table id per axis
+
+  // tables (FP64; rounded once to the compute precision on upload)
+  int nftab = 0, nvtab = 0;
+  std::vector<int32_t> ftab_meta;     // [2*nftab] level of each form/eval table, then its position
+  std::vector<int32_t> vtab_meta;     // [2*nvtab] source level of each near table, then its type (0..10)
+  std::vector<double> F;              // [nftab][nr][p]  leaf values -> cutoff-box pw moments
+  std::vector<double> E;              // [nftab][p][nr]  cutoff-box pw moments -> leaf values
+  std::vector<double> V;              // [nvtab][p][p]   source values -> target values
+  std::vector<double> rot;            // [M][2]  cos, sin of k_m * Llc
+
+  // counts for reporting
+  int64_t n_pwbox() const { return (int64_t)pwbox_isleaf.size(); }
+  int64_t n_pwleaf() const { return (int64_t)pwleaf_id.size(); }
+  int64_t n_plist() const { return (int64_t)plist_src.size(); }
+  int64_t n_near_tgt() const { return (int64_t)near_tgt.size(); }
+  int64_t n_near_pair() const { return (int64_t)near_src.size(); }
+};
+
+// Validates the tree and fills every field above.  Returns an FGT_* code.
+int build_host_plan(int dim, int64_t nleaves, const int32_t* level, const int32_t* coord,
+                    int p, double delta, double tol, int bc, int precision,
+                    double eps_internal, int force_lc, HostPlan& hp, std::string& err);
+
+// Tables (tables.cpp)
+void gauss_legendre(int n, double* x, double* w);
+void build_tables(HostPlan& hp);
+
+}  // namespace fgt

@@ -1,0 +1,415 @@
+// Host plan of the box Gauss transform: tree validation, the cutoff level and
+// plane-wave parameters (Theorem 1), and the flat lists that drive the device
+// stages of Algorithm 4 (f-flags, P-lists, D-lists; Section 4.2).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+#include "fgt_host.h"
+#include "../../include/fgt.h"
+
+namespace fgt {
+
+PwParams pw_params(double eps, double R) {
+  PwParams q;
+  q.eps = eps;
+  q.D0 = std::sqrt(std::log(3.0 / eps));
+  q.R = R;
+  q.h = 2.0 * M_PI / (R + q.D0);
+  q.M = (int)std::ceil(q.D0 * (R + q.D0) / M_PI);
+  return q;
+}
+
+namespace {
+
+int max_level_for_dim(int d) { return d == 3 ? 19 : (d == 2 ? 28 : 30); }
+
+// Unique 64-bit key of a box (level, coords).
+struct KeyMaker {
+  int d, bits;
+  explicit KeyMaker(int dim) : d(dim), bits(58 / dim) {}
+  uint64_t operator()(int l, const int32_t* c) const {
+    uint64_t k = (uint64_t)l << 58;
+    for (int a = 0; a < d; a++) k |= (uint64_t)(uint32_t)c[a] << (a * bits);
+    return k;
+  }
+};
+
+uint64_t morton(const int32_t* c, int d, int shift) {
+  // interleave the bits of coords scaled by 2^shift (up to 21 bits per axis)
+  uint64_t m = 0;
+  uint64_t v[3] = {0, 0, 0};
+  for (int a = 0; a < d; a++) v[a] = (uint64_t)(uint32_t)c[a] << shift;
+  for (int b = 0; b < 21; b++)
+    for (int a = 0; a < d; a++) m |= ((v[a] >> b) & 1ull) << (b * d + a);
+  return m;
+}
+
+int ipow3(int d) { return d == 1 ? 3 : (d == 2 ? 9 : 27); }
+
+void dir_of(int code, int d, int* dir) {
+  for (int a = 0; a < d; a++) {
+    dir[a] = code % 3 - 1;
+    code /= 3;
+  }
+}
+
+}  // namespace
+
+int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord, int p,
+                    double delta, double tol, int bc, int precision, double eps_internal,
+                    int force_lc, HostPlan& hp, std::string& err) {
+  if (d < 1 || d > kMaxDim) { err = "dim must be 1, 2 or 3"; return FGT_ERR_INVALID_ARG; }
+  if (n < 1 || !level || !coord) { err = "empty tree"; return FGT_ERR_INVALID_ARG; }
+  if (p < 1 || p > kMaxP) { err = "p must be in [1,16]"; return FGT_ERR_INVALID_ARG; }
+  if (!(delta > 0) || !std::isfinite(delta)) { err = "delta must be > 0"; return FGT_ERR_INVALID_ARG; }
+  if (!(tol > 0 && tol < 0.1)) { err = "tol must be in (0, 0.1) (Theorem 1 needs eps < 0.1)"; return FGT_ERR_INVALID_ARG; }
+  if (bc != FGT_FREE && bc != FGT_PERIODIC) { err = "bc must be FGT_FREE or FGT_PERIODIC"; return FGT_ERR_INVALID_ARG; }
+  if (precision != FGT_FP64 && precision != FGT_FP32) { err = "precision must be FGT_FP64 or FGT_FP32"; return FGT_ERR_INVALID_ARG; }
+  if (eps_internal < 0 || eps_internal >= 0.1) { err = "eps_internal must be 0 or in (0, 0.1)"; return FGT_ERR_INVALID_ARG; }
+  const bool periodic = bc == FGT_PERIODIC;
+
+  hp = HostPlan();
+  hp.d = d; hp.p = p; hp.bc = bc; hp.precision = precision;
+  hp.delta = delta; hp.tol = tol; hp.nleaves = n;
+  hp.level.assign(level, level + n);
+  hp.coord.assign(coord, coord + n * d);
+  hp.sqrt_delta = std::sqrt(delta);
+
+  // ---- tree validation: ranges, tiling, 2:1 balance
+  const int maxlev = max_level_for_dim(d);
+  int lmin = 1 << 30, lmax = 0;
+  for (int64_t i = 0; i < n; i++) {
+    int l = level[i];
+    if (l < 0 || l > maxlev) { err = "leaf level out of range for this dimension"; return FGT_ERR_INVALID_ARG; }
+    for (int a = 0; a < d; a++) {
+      int32_t c = coord[i * d + a];
+      if (c < 0 || (int64_t)c >= ((int64_t)1 << l)) { err = "leaf coordinate outside [0, 2^level)"; return FGT_ERR_NOT_TILING; }
+    }
+    lmin = std::min(lmin, l);
+    lmax = std::max(lmax, l);
+  }
+  hp.lmin = lmin; hp.lmax = lmax;
+  KeyMaker key(d);
+  std::unordered_map<uint64_t, int32_t> leafmap;
+  leafmap.reserve((size_t)n * 2);
+  unsigned __int128 vol = 0;
+  for (int64_t i = 0; i < n; i++) {
+    if (!leafmap.emplace(key(level[i], &coord[i * d]), (int32_t)i).second) {
+      err = "duplicate leaf"; return FGT_ERR_NOT_TILING;
+    }
+    vol += (unsigned __int128)1 << (d * (lmax - level[i]));
+  }
+  if (vol != ((unsigned __int128)1 << (d * lmax))) { err = "leaves do not cover the unit box exactly"; return FGT_ERR_NOT_TILING; }
+  for (int64_t i = 0; i < n; i++) {
+    int32_t c[3];
+    for (int l = level[i] - 1; l >= 0; l--) {
+      for (int a = 0; a < d; a++) c[a] = coord[i * d + a] >> (level[i] - l);
+      if (leafmap.count(key(l, c))) { err = "a leaf contains another leaf"; return FGT_ERR_NOT_TILING; }
+    }
+  }
+  // covering leaf of box (l, q): the leaf at level <= l that contains it, or -1
+  auto covering = [&](int l, const int32_t* q, int* lev_out) -> int32_t {
+    int32_t c[3];
+    for (int ll = l; ll >= 0; ll--) {
+      for (int a = 0; a < d; a++) c[a] = q[a] >> (l - ll);
+      auto it = leafmap.find(key(ll, c));
+      if (it != leafmap.end()) { *lev_out = ll; return it->second; }
+    }
+    return -1;
+  };
+  // wrap (periodic) or reject (free) a neighbor coordinate at level l
+  auto neighbor = [&](int l, const int32_t* c, const int* dir, int32_t* q, int* shift) -> bool {
+    int64_t nb = (int64_t)1 << l;
+    for (int a = 0; a < d; a++) {
+      int64_t v = (int64_t)c[a] + dir[a];
+      int s = 0;
+      if (v < 0) { v += nb; s = -1; }
+      else if (v >= nb) { v -= nb; s = 1; }
+      if (s != 0 && !periodic) return false;
+      q[a] = (int32_t)v;
+      if (shift) shift[a] = s;
+    }
+    return true;
+  };
+  const int n3 = ipow3(d);
+  for (int64_t i = 0; i < n; i++) {
+    int l = level[i];
+    if (l < 2) continue;
+    for (int code = 0; code < n3; code++) {
+      int dir[3];
+      dir_of(code, d, dir);
+      bool zero = true;
+      for (int a = 0; a < d; a++) zero = zero && dir[a] == 0;
+      if (zero) continue;
+      int32_t q[3];
+      if (!neighbor(l, &coord[i * d], dir, q, nullptr)) continue;
+      int lv;
+      if (covering(l, q, &lv) >= 0 && lv < l - 1) {
+        err = "tree is not level-restricted (2:1 balance with corner adjacency)";
+        return FGT_ERR_NOT_BALANCED;
+      }
+    }
+  }
+
+  // ---- method parameters: eps, cutoff level, range R, modes (Theorem 1)
+  const double eps = eps_internal > 0 ? eps_internal : tol;
+  const double D0 = std::sqrt(std::log(3.0 / eps));
+  const double cut = D0 * hp.sqrt_delta;  // cutoff length D0 sqrt(delta)
+  int lc_auto = cut >= 1.0 ? 0 : (int)std::floor(std::log2(1.0 / cut));
+  // guard the floor against rounding: the box side must not be below the cutoff length
+  while (lc_auto > 0 && std::ldexp(1.0, -lc_auto) < cut) lc_auto--;
+  while (std::ldexp(1.0, -(lc_auto + 1)) >= cut) lc_auto++;
+  int lc = lc_auto;
+  if (force_lc >= 0) {
+    if (force_lc > lc_auto) { err = "force_lc finer than the automatic cutoff level would drop interactions"; return FGT_ERR_INVALID_ARG; }
+    lc = force_lc;
+  }
+  if (lc > maxlev) lc = maxlev;
+  if (periodic && lc <= 1) {
+    err = "periodic transforms with cutoff level <= 1 (large delta) are not implemented";
+    return FGT_ERR_UNSUPPORTED;
+  }
+  hp.lc = lc;
+  hp.Llc = std::ldexp(1.0, -lc);
+  // largest per-axis separation between a target in a cutoff box and a source
+  // in one of its colleagues (or the box itself when the root is the only box)
+  double R = (lc == 0 ? 1.0 : 2.0 * hp.Llc) / hp.sqrt_delta;
+  if (R < D0) R = D0;
+  hp.pw = pw_params(eps, R);
+  hp.nr = 2 * hp.pw.M - 1;
+  if (hp.nr > kMaxModes) { err = "too many plane-wave modes for this build (nr > 128)"; return FGT_ERR_UNSUPPORTED; }
+
+  // ---- cutoff-level boxes and f-flags (Definition fflagdef)
+  struct LcBox { int32_t c[3]; int isleaf; int f; int32_t idx; };
+  std::unordered_map<uint64_t, int32_t> lcmap;
+  std::vector<LcBox> lcbox;
+  for (int64_t i = 0; i < n; i++) {
+    int l = level[i];
+    if (l < lc) continue;
+    LcBox b{};
+    for (int a = 0; a < d; a++) b.c[a] = coord[i * d + a] >> (l - lc);
+    uint64_t k = key(lc, b.c);
+    auto it = lcmap.find(k);
+    if (it == lcmap.end()) {
+      b.isleaf = (l == lc);
+      b.f = 0;
+      b.idx = -1;
+      lcmap.emplace(k, (int32_t)lcbox.size());
+      lcbox.push_back(b);
+    }
+  }
+  for (auto& b : lcbox) {
+    if (!b.isleaf) { b.f = 1; continue; }
+    for (int code = 0; code < n3 && !b.f; code++) {
+      int dir[3];
+      dir_of(code, d, dir);
+      int32_t q[3];
+      if (!neighbor(lc, b.c, dir, q, nullptr)) continue;
+      auto it = lcmap.find(key(lc, q));
+      if (it != lcmap.end() && !lcbox[it->second].isleaf) b.f = 1;
+    }
+  }
+  std::vector<int32_t> pwb;
+  for (int32_t i = 0; i < (int32_t)lcbox.size(); i++)
+    if (lcbox[i].f) pwb.push_back(i);
+  std::sort(pwb.begin(), pwb.end(), [&](int32_t x, int32_t y) {
+    return morton(lcbox[x].c, d, 0) < morton(lcbox[y].c, d, 0);
+  });
+  for (int32_t a = 0; a < (int32_t)pwb.size(); a++) lcbox[pwb[a]].idx = a;
+  const int32_t nA = (int32_t)pwb.size();
+  hp.pwbox_isleaf.resize(nA);
+  for (int32_t a = 0; a < nA; a++) hp.pwbox_isleaf[a] = lcbox[pwb[a]].isleaf;
+
+  // ---- plane-wave leaves grouped by their cutoff box; form/eval table ids
+  struct PwLeaf { int32_t box; uint64_t m; int32_t id; };
+  std::vector<PwLeaf> pl;
+  for (int64_t i = 0; i < n; i++) {
+    int l = level[i];
+    if (l < lc) continue;
+    int32_t c[3];
+    for (int a = 0; a < d; a++) c[a] = coord[i * d + a] >> (l - lc);
+    const LcBox& b = lcbox[lcmap[key(lc, c)]];
+    if (!b.f) continue;
+    pl.push_back({b.idx, morton(&coord[i * d], d, lmax - l), (int32_t)i});
+  }
+  std::sort(pl.begin(), pl.end(), [](const PwLeaf& x, const PwLeaf& y) {
+    return x.box != y.box ? x.box < y.box : x.m < y.m;
+  });
+  std::unordered_map<uint64_t, int32_t> ftab;  // (level, pos) -> id
+  std::vector<int32_t> ftab_lv, ftab_pos;
+  hp.pw_start.assign(nA + 1, 0);
+  hp.pwleaf_id.resize(pl.size());
+  hp.pwleaf_tab.resize(pl.size() * d);
+  for (size_t s = 0; s < pl.size(); s++) {
+    int32_t i = pl[s].id;
+    int l = level[i];
+    hp.pwleaf_id[s] = i;
+    hp.pw_start[pl[s].box + 1]++;
+    for (int a = 0; a < d; a++) {
+      int32_t pos = coord[i * d + a] - ((coord[i * d + a] >> (l - lc)) << (l - lc));
+      uint64_t k = ((uint64_t)l << 32) | (uint32_t)pos;
+      auto it = ftab.find(k);
+      int32_t id;
+      if (it == ftab.end()) {
+        id = (int32_t)ftab_lv.size();
+        ftab.emplace(k, id);
+        ftab_lv.push_back(l);
+        ftab_pos.push_back(pos);
+      } else {
+        id = it->second;
+      }
+      hp.pwleaf_tab[s * d + a] = id;
+    }
+  }
+  for (int32_t a = 0; a < nA; a++) hp.pw_start[a + 1] += hp.pw_start[a];
+  hp.nftab = (int)ftab_lv.size();
+  hp.ftab_meta = ftab_lv;
+  hp.ftab_meta.insert(hp.ftab_meta.end(), ftab_pos.begin(), ftab_pos.end());
+
+  // evaluation chunks: up to 64 stacked rows (count*p) of one box
+  const int per = std::max(1, 64 / p);
+  for (int32_t a = 0; a < nA; a++)
+    for (int32_t s = hp.pw_start[a]; s < hp.pw_start[a + 1]; s += per) {
+      hp.echunk.push_back(a);
+      hp.echunk.push_back(s);
+      hp.echunk.push_back(std::min(per, hp.pw_start[a + 1] - s));
+    }
+
+  // ---- P-lists (Definition before Algorithm 4, read for every box with f = 1):
+  // colleagues with f = 1 (images included when periodic), excluding pairs of
+  // two leaves, which the near field handles.
+  hp.plist_start.assign(nA + 1, 0);
+  for (int32_t a = 0; a < nA; a++) {
+    const LcBox& A = lcbox[pwb[a]];
+    for (int code = 0; code < n3; code++) {
+      int dir[3];
+      dir_of(code, d, dir);
+      int32_t q[3];
+      if (!neighbor(lc, A.c, dir, q, nullptr)) continue;
+      auto it = lcmap.find(key(lc, q));
+      if (it == lcmap.end()) continue;
+      const LcBox& B = lcbox[it->second];
+      if (!B.f || (A.isleaf && B.isleaf)) continue;
+      hp.plist_src.push_back(B.idx);
+      hp.plist_dir.push_back(code);  // dir = B - A per axis
+    }
+    hp.plist_start[a + 1] = (int32_t)hp.plist_src.size();
+  }
+
+  // ---- D-lists: every leaf at level <= lc gathers from its leaf neighbors at
+  // levels <= lc (colleagues, coarse and fine neighbors; images if periodic).
+  std::unordered_map<uint64_t, int32_t> vtab;  // (source level, type) -> id
+  std::vector<int32_t> vtab_lv, vtab_ty;
+  std::vector<std::pair<int64_t, int32_t>> tgt;  // (morton, leaf)
+  for (int64_t i = 0; i < n; i++)
+    if (level[i] <= lc) tgt.push_back({(int64_t)morton(&coord[i * d], d, lmax - level[i]), (int32_t)i});
+  std::sort(tgt.begin(), tgt.end());
+  hp.near_start.push_back(0);
+  for (auto& tt : tgt) {
+    const int32_t T = tt.second;
+    const int l = level[T];
+    const int32_t* cT = &coord[T * d];
+    struct Ent { int32_t S; int shift[3]; };
+    std::vector<Ent> ents;
+    auto add = [&](int32_t S, const int* shift) {
+      for (auto& e : ents) {
+        bool same = e.S == S;
+        for (int a = 0; a < d && same; a++) same = e.shift[a] == shift[a];
+        if (same) return;
+      }
+      Ent e{S, {0, 0, 0}};
+      for (int a = 0; a < d; a++) e.shift[a] = shift[a];
+      ents.push_back(e);
+    };
+    for (int code = 0; code < n3; code++) {
+      int dir[3];
+      dir_of(code, d, dir);
+      int32_t q[3];
+      int shift[3] = {0, 0, 0};
+      if (!neighbor(l, cT, dir, q, shift)) continue;
+      // same level
+      auto it = leafmap.find(key(l, q));
+      if (it != leafmap.end()) { add(it->second, shift); continue; }
+      // coarser leaf containing the neighbor box
+      if (l >= 1) {
+        int32_t par[3];
+        for (int a = 0; a < d; a++) par[a] = q[a] >> 1;
+        auto ip = leafmap.find(key(l - 1, par));
+        if (ip != leafmap.end()) { add(ip->second, shift); continue; }
+      }
+      // finer leaves (children of the neighbor box that touch T)
+      if (l + 1 <= lc) {
+        int nb = 1 << d;
+        for (int b = 0; b < nb; b++) {
+          int32_t ch[3];
+          bool ok = true;
+          for (int a = 0; a < d; a++) {
+            int bit = (b >> a) & 1;
+            if (dir[a] == -1 && bit == 0) ok = false;
+            if (dir[a] == 1 && bit == 1) ok = false;
+            ch[a] = 2 * q[a] + bit;
+          }
+          if (!ok) continue;
+          auto ic = leafmap.find(key(l + 1, ch));
+          if (ic != leafmap.end()) add(ic->second, shift);
+        }
+      }
+    }
+    std::sort(ents.begin(), ents.end(), [&](const Ent& x, const Ent& y) {
+      if (x.S != y.S) return x.S < y.S;
+      for (int a = 0; a < d; a++) if (x.shift[a] != y.shift[a]) return x.shift[a] < y.shift[a];
+      return false;
+    });
+    for (auto& e : ents) {
+      const int lS = level[e.S];
+      if (lS > lc) continue;
+      const int lF = std::max(l, lS);
+      hp.near_src.push_back(e.S);
+      for (int a = 0; a < d; a++) {
+        // centers in units of 2^-(lF+1); S shifted by its image
+        int64_t cTu = (2 * (int64_t)cT[a] + 1) << (lF - l);
+        int64_t cSu = ((2 * (int64_t)coord[e.S * d + a] + 1) << (lF - lS)) + ((int64_t)e.shift[a] << (lF + 1));
+        int64_t diff = cTu - cSu;
+        int64_t LS = (int64_t)1 << (lF + 1 - lS);
+        int64_t rel4 = 4 * diff / LS;  // 4 (c_T - c_S)/L_S
+        int type = -1;
+        if (l == lS) type = rel4 == -4 ? 0 : rel4 == 0 ? 1 : rel4 == 4 ? 2 : -1;
+        else if (l == lS + 1) type = rel4 == -3 ? 3 : rel4 == -1 ? 4 : rel4 == 1 ? 5 : rel4 == 3 ? 6 : -1;
+        else if (l == lS - 1) type = rel4 == -6 ? 7 : rel4 == -2 ? 8 : rel4 == 2 ? 9 : rel4 == 6 ? 10 : -1;
+        if (type < 0 || 4 * diff % LS != 0) { err = "internal: unexpected neighbor geometry"; return FGT_ERR_INVALID_ARG; }
+        uint64_t k = ((uint64_t)lS << 32) | (uint32_t)type;
+        auto iv = vtab.find(k);
+        int32_t id;
+        if (iv == vtab.end()) {
+          id = (int32_t)vtab_lv.size();
+          vtab.emplace(k, id);
+          vtab_lv.push_back(lS);
+          vtab_ty.push_back(type);
+        } else {
+          id = iv->second;
+        }
+        hp.near_tab.push_back(id);
+      }
+    }
+    hp.near_tgt.push_back(T);
+    int haspw = 0;
+    if (l == lc) {
+      auto it = lcmap.find(key(lc, cT));
+      haspw = (it != lcmap.end() && lcbox[it->second].f) ? 1 : 0;
+    }
+    hp.near_haspw.push_back(haspw);
+    hp.near_start.push_back((int32_t)hp.near_src.size());
+  }
+  hp.nvtab = (int)vtab_lv.size();
+  hp.vtab_meta = vtab_lv;
+  hp.vtab_meta.insert(hp.vtab_meta.end(), vtab_ty.begin(), vtab_ty.end());
+
+  build_tables(hp);
+  return FGT_OK;
+}
+
+}  // namespace fgt

@@ -1,0 +1,132 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: relative l2 error over all returned nodes below the requested tol
+(the accuracy the method promises, Theorem 1 applied in Algorithm 4).  For
+FP64 plans the device result must also equal the test-only numpy walk of the
+same host plan to rounding (1e-12 relative): the kernels implement exactly the
+stages the plan describes.
+"""
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import host_exec
+import oracle
+from paper_2305_07165_amd import api, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+def _run(lv, cs, p, delta, tol, sig, periodic=False, precision="fp64", force_lc=-1,
+         eps_internal=0.0):
+    pl = api.Plan(lv, cs, p, delta, tol, periodic=periodic, precision=precision,
+                  force_lc=force_lc, eps_internal=eps_internal)
+    s = torch.from_numpy(np.ascontiguousarray(sig)).cuda()
+    u = pl.execute(s)
+    torch.cuda.synchronize()
+    pl.sync()
+    return u.cpu().numpy(), pl
+
+
+def _adaptive_2d(periodic=False, p=8, widths=(0.01, 0.03), maxl=8):
+    c = [[0.46, -0.17], [-0.2, 0.49]] if periodic else [[0.11, -0.17], [-0.2, 0.05]]
+    dens = synth.GaussianSum(np.array(c), np.array(widths), np.array([0.7, -0.4]),
+                             periodic=periodic)
+    lv, cs = synth.resolve_tree(dens, 2, p, 1e-10, max_level=maxl, periodic=periodic)
+    return lv, cs, synth.sample(lv, cs, p, dens)
+
+
+def _adaptive_3d(periodic=False, p=6, maxl=5):
+    dens = synth.GaussianSum(np.array([[0.1, -0.12, 0.05], [-0.3, 0.2, 0.1]]),
+                             np.array([0.02, 0.05]), np.array([1.0, -0.6]))
+    lv, cs = synth.resolve_tree(dens, 3, p, 1e-8, max_level=maxl, periodic=periodic)
+    return lv, cs, synth.sample(lv, cs, p, dens)
+
+
+CASES = [
+    # name, builder, p, delta, tol, periodic, force_lc
+    ("2d-uniform-direct", lambda: (synth.small_2d(0).levels, synth.small_2d(0).coords, synth.small_2d(0).sigma), 8, 1e-3, 1e-6, False, -1),
+    ("2d-uniform-pw-lc2", lambda: (synth.small_2d(0).levels, synth.small_2d(0).coords, synth.small_2d(0).sigma), 8, 1e-3, 1e-6, False, 2),
+    ("2d-uniform-pw-lc1", lambda: (synth.small_2d(0).levels, synth.small_2d(0).coords, synth.small_2d(0).sigma), 8, 1e-3, 1e-6, False, 1),
+    ("2d-adaptive-free-1e-6", lambda: _adaptive_2d(False), 8, 1e-3, 1e-6, False, -1),
+    ("2d-adaptive-free-1e-10", lambda: _adaptive_2d(False), 8, 1e-4, 1e-10, False, -1),
+    ("2d-adaptive-periodic-1e-6", lambda: _adaptive_2d(True), 8, 1e-3, 1e-6, True, -1),
+    ("2d-adaptive-periodic-1e-10", lambda: _adaptive_2d(True), 8, 1e-4, 1e-10, True, -1),
+    ("2d-adaptive-p5-ragged", lambda: _adaptive_2d(False, p=5, widths=(0.02, 0.04), maxl=7), 5, 2e-3, 1e-8, False, -1),
+    ("2d-adaptive-p16", lambda: _adaptive_2d(False, p=16, widths=(0.01, 0.03), maxl=7), 16, 1e-3, 1e-10, False, -1),
+    ("3d-adaptive-free-p6", lambda: _adaptive_3d(False), 6, 1e-3, 1e-6, False, -1),
+    ("3d-adaptive-periodic-p6", lambda: _adaptive_3d(True), 6, 1e-3, 1e-6, True, -1),
+    ("3d-adaptive-free-p6-1e-10", lambda: _adaptive_3d(False), 6, 1e-3, 1e-10, False, -1),
+    ("3d-adaptive-free-p16", lambda: _adaptive_3d(False, p=16, maxl=4), 16, 1e-3, 1e-10, False, -1),
+    ("1d-adaptive", lambda: (lambda t: (t[0], t[1], synth.sample(t[0], t[1], 9, synth.GaussianSum(np.array([[0.13]]), np.array([0.01]), np.array([1.0])))))(synth.resolve_tree(synth.GaussianSum(np.array([[0.13]]), np.array([0.01]), np.array([1.0])), 1, 9, 1e-12, max_level=9)), 9, 1e-4, 1e-10, False, -1),
+]
+
+
+@pytest.mark.parametrize("name,build,p,delta,tol,periodic,force_lc", CASES, ids=[c[0] for c in CASES])
+def test_parity_fp64(name, build, p, delta, tol, periodic, force_lc):
+    lv, cs, sig = build()
+    _say(f"{name}: nleaves={len(lv)} p={p} delta={delta} tol={tol} periodic={periodic} force_lc={force_lc}")
+    uo = oracle.oracle_u(lv, cs, p, delta, sig, periodic=periodic)
+    ug, pl = _run(lv, cs, p, delta, tol, sig, periodic=periodic, force_lc=force_lc)
+    info = pl.info()
+    err = cf.rel_l2(ug, uo)
+    _say(f"{name}: lc={info['lc']} nr={info['nr']} pwleaves={info['n_pwleaf']} near={info['n_near_pair']} rel_l2={err:.3e}")
+    assert np.all(np.isfinite(ug))
+    assert err < tol
+    hp = api.Plan(lv, cs, p, delta, tol, periodic=periodic, force_lc=force_lc, host_only=True)
+    uh = host_exec.run(hp, sig)
+    assert cf.rel_l2(ug, uh) < 1e-12
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6])
+@pytest.mark.parametrize("shape", ["2d", "3d"])
+def test_parity_fp32(shape, tol):
+    if shape == "2d":
+        lv, cs, sig = _adaptive_2d(False)
+        p, delta = 8, 1e-3
+    else:
+        lv, cs, sig = _adaptive_3d(False)
+        p, delta = 6, 1e-3
+    _say(f"fp32 {shape} tol={tol}")
+    uo = oracle.oracle_u(lv, cs, p, delta, sig)
+    ug, _ = _run(lv, cs, p, delta, tol, sig, precision="fp32")
+    err = cf.rel_l2(ug, uo)
+    _say(f"fp32 {shape} tol={tol}: rel_l2={err:.3e}")
+    assert err < tol
+
+
+def test_deterministic_and_reusable():
+    lv, cs, sig = _adaptive_2d(False)
+    pl = api.Plan(lv, cs, 8, 1e-3, 1e-6)
+    s = torch.from_numpy(sig).cuda()
+    u1 = pl.execute(s).clone()
+    u2 = pl.execute(s)
+    s2 = 2.0 * s
+    u3 = pl.execute(s2)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
+    assert torch.allclose(u3, 2.0 * u1, rtol=1e-13, atol=0)
+
+
+def test_single_leaf_root():
+    lv = np.array([0], dtype=np.int32)
+    cs = np.zeros((1, 2), dtype=np.int32)
+    sig = np.ones((1, 64))
+    uo = oracle.oracle_u(lv, cs, 8, 0.02, sig)
+    ug, _ = _run(lv, cs, 8, 0.02, 1e-8, sig)
+    assert cf.rel_l2(ug, uo) < 1e-8
+    x = synth.leaf_points(lv, cs, 8)
+    assert cf.rel_l2(ug, cf.const_free(x, 0.02)) < 1e-8
+
+
+def test_errors_surface():
+    lv = np.array([1, 1, 1, 2, 2, 2, 2, 2], dtype=np.int32)  # not a tiling
+    cs = np.array([[1, 0], [0, 1], [1, 1], [0, 0], [1, 0], [0, 1], [1, 1], [1, 1]], dtype=np.int32)
+    with pytest.raises(api.FgtError):
+        api.Plan(lv, cs, 4, 1e-3, 1e-6)
