@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the tol=1e-10 and FP32 lines")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps of the headline plan only (for rocprofv3)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="with --profile-only: also run a 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -150,6 +152,13 @@ def main():
         f"translations={info['n_plist']} near_pairs={info['n_near_pair']} plan_ms={plan_ms:.1f}")
     if args.profile_only:
         timed_steps(plan, s, u, args.steps, args.warmup, torch)
+        if args.calib_copy:
+            # a plain device copy of known size: 1 GiB read + 1 GiB written,
+            # to scale the FETCH_SIZE / WRITE_SIZE counters
+            x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+            y = torch.empty_like(x)
+            y.copy_(x)
+            torch.cuda.synchronize()
         log("profile-only run done")
         return
 

@@ -117,15 +117,19 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   a.nL = hp.n_pwleaf();
   a.nE = (int64_t)hp.echunk.size() / 3;
   a.nT = hp.n_near_tgt();
+  a.nFI = (int64_t)hp.fitem.size() / 4;
+  a.nFR = (int64_t)hp.fred.size() / 3;
   int rc;
   if ((rc = upload_table(pl, hp.F, fp32, &a.F)) || (rc = upload_table(pl, hp.E, fp32, &a.E)) ||
       (rc = upload_table(pl, hp.V, fp32, &a.V)) || (rc = upload_table(pl, hp.rot, fp32, &a.rot)))
     return rc;
   if ((rc = upload_i32(pl, hp.pw_start, &a.pw_start)) || (rc = upload_i32(pl, hp.pwleaf_id, &a.pwleaf_id)) ||
-      (rc = upload_i32(pl, hp.pwleaf_tab, &a.pwleaf_tab)) ||
+      (rc = upload_i32(pl, hp.pwleaf_tab, &a.pwleaf_tab)) || (rc = upload_i32(pl, hp.pwleaf_box, &a.pwleaf_box)) ||
+      (rc = upload_i32(pl, hp.box_order, &a.box_order)) ||
       (rc = upload_i32(pl, hp.plist_start, &a.plist_start)) ||
       (rc = upload_i32(pl, hp.plist_src, &a.plist_src)) || (rc = upload_i32(pl, hp.plist_dir, &a.plist_dir)) ||
       (rc = upload_i32(pl, hp.echunk, &a.echunk)) || (rc = upload_i32(pl, hp.near_tgt, &a.near_tgt)) ||
+      (rc = upload_i32(pl, hp.fitem, &a.fitem)) || (rc = upload_i32(pl, hp.fred, &a.fred)) ||
       (rc = upload_i32(pl, hp.near_haspw, &a.near_haspw)) ||
       (rc = upload_i32(pl, hp.near_start, &a.near_start)) || (rc = upload_i32(pl, hp.near_src, &a.near_src)) ||
       (rc = upload_i32(pl, hp.near_tab, &a.near_tab)))
@@ -133,7 +137,8 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   const size_t n2 = (size_t)ipowd(hp.nr, hp.d - 1);
   const size_t ncoef = n2 * hp.nr;
   if ((rc = alloc(pl, (size_t)a.nL * hp.p * n2 * ts, &a.Y)) ||
-      (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.phi)) || (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.psi)))
+      (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.phi)) || (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.psi)) ||
+      (rc = alloc(pl, (size_t)hp.nslots * ncoef * ts, &a.partial)))
     return rc;
   if (opts && opts->own_stream) {
     e = hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking);
@@ -323,10 +328,14 @@ int64_t fgt_plan_array(const fgt_plan_t* pl, const char* name, void* dst, int64_
   else if (n == "pw_start") iv = &hp.pw_start;
   else if (n == "pwleaf_id") iv = &hp.pwleaf_id;
   else if (n == "pwleaf_tab") iv = &hp.pwleaf_tab;
+  else if (n == "pwleaf_box") iv = &hp.pwleaf_box;
+  else if (n == "box_order") iv = &hp.box_order;
   else if (n == "plist_start") iv = &hp.plist_start;
   else if (n == "plist_src") iv = &hp.plist_src;
   else if (n == "plist_dir") iv = &hp.plist_dir;
   else if (n == "echunk") iv = &hp.echunk;
+  else if (n == "fitem") iv = &hp.fitem;
+  else if (n == "fred") iv = &hp.fred;
   else if (n == "near_tgt") iv = &hp.near_tgt;
   else if (n == "near_haspw") iv = &hp.near_haspw;
   else if (n == "near_start") iv = &hp.near_start;

@@ -11,6 +11,7 @@ namespace fgt {
 constexpr int kMaxDim = 3;
 constexpr int kMaxP = 16;      // nodes per axis handled by the kernels
 constexpr int kMaxModes = 128; // real plane-wave modes per axis (2M-1)
+constexpr int kFormLeaves = 8; // leaves per formation work item
 
 // Plane-wave parameters of Theorem 1 for tolerance eps and range R (units of
 // sqrt(delta)): D0 = sqrt(log(3/eps)), h = 2 pi/(R + D0), M = ceil(D0 (R+D0)/pi).
@@ -40,18 +41,28 @@ struct HostPlan {
   std::vector<int32_t> pw_start;      // [nA+1] ranges of pw leaves per box
   std::vector<int32_t> pwleaf_id;     // [nL] caller leaf index
   std::vector<int32_t> pwleaf_tab;    // [nL*d] form/eval table id per axis
+  std::vector<int32_t> pwleaf_box;    // [nL] cutoff box of each pw leaf
+  std::vector<int32_t> box_order;     // [nA] pw boxes by decreasing leaf count (dispatch order)
   std::vector<int32_t> plist_start;   // [nA+1]
   std::vector<int32_t> plist_src;     // [nP] plane-wave box index
   std::vector<int32_t> plist_dir;     // [nP] sum_a (dir_a+1) 3^a, dir = src - dst
   // evaluation work items: (box, first pw leaf, count) with count*p <= 64 rows
   std::vector<int32_t> echunk;        // [nE*3]
+  // formation work items: (box, first pw leaf, end pw leaf, partial slot or -1);
+  // boxes with more than kFormLeaves leaves are split, their partial sums
+  // reduced in item order by (box, first slot, slot count) records
+  std::vector<int32_t> fitem;         // [nFI*4]
+  std::vector<int32_t> fred;          // [nFR*3]
+  int32_t nslots = 0;
 
   // near field: targets at level <= lc, gather lists
   std::vector<int32_t> near_tgt;      // [nT] caller leaf index
   std::vector<int32_t> near_haspw;    // [nT] 1 if the leaf also receives a pw evaluation
   std::vector<int32_t> near_start;    // [nT+1]
   std::vector<int32_t> near_src;      // [nN] caller leaf index
-  std::vector<int32_t> near_tab;      // [nN*d] near table id per axis
+  std::vector<int32_t> near_tab;      // [nN*d] near table id per axis; a target's sources
+                                      // are sorted by tables: (axis 3, axis 1, axis 2) for
+                                      // d = 3, (axis 2, axis 1) for d = 2
 
   // tables (FP64; rounded once to the compute precision on upload)
   int nftab = 0, nvtab = 0;

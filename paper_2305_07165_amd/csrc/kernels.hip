@@ -22,27 +22,9 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "mfma.h"
 
 namespace fgt {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  typedef d4 acc;
-  static __device__ __forceinline__ acc step(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lk, int t) { return 4 * t + lk; }
-};
-template <> struct Mfma<float> {
-  typedef f4 acc;
-  static __device__ __forceinline__ acc step(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lk, int t) { return 4 * lk + t; }
-};
 
 template <typename A> __device__ __forceinline__ void zero(A& a) {
   a[0] = 0; a[1] = 0; a[2] = 0; a[3] = 0;
@@ -210,23 +192,36 @@ __global__ __launch_bounds__(256) void k_form_box(const T* __restrict__ Y,
 // ---------------------------------------------------------------------------
 // translate: psi_A = sum_{(B,dir) in P(A)} Rot(dir * L_c) phi_B.  One thread per
 // mode multi-index (m_1..m_d); it owns the 2^#(m_a>0) (cos/sin) coefficients.
+// R2F: the tensors are stored [r3][r1][r2] (r2 fastest, the d = 3 layout of
+// kernels_fast.hip) instead of [r3][r2][r1]; threads then run along m_2.
 
-template <typename T, int D>
+template <typename T, int D, bool R2F>
 __global__ __launch_bounds__(256) void k_translate(const T* __restrict__ phi,
                                                    const int32_t* __restrict__ plist_start,
                                                    const int32_t* __restrict__ plist_src,
                                                    const int32_t* __restrict__ plist_dir,
                                                    const T* __restrict__ rot, int M, int nr,
-                                                   int nchunks, T* __restrict__ psi) {
-  const int A = blockIdx.x / nchunks;
-  const int b = (blockIdx.x % nchunks) * blockDim.x + threadIdx.x;
+                                                   int nA, T* __restrict__ psi) {
+  // Every XCD owns a contiguous (Morton) range of nbx target boxes and walks
+  // it chunk of modes by chunk of modes, so a source's slice is fetched into
+  // that XCD's L2 once and reused by all its neighbors in the range.
+  const int nbx = (nA + kXcds - 1) / kXcds;
+  const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+  const int A = xcd * nbx + local % nbx;
+  const int b = (local / nbx) * blockDim.x + threadIdx.x;
   int nblk = 1;
   for (int a = 0; a < D; a++) nblk *= M;
-  if (b >= nblk) return;
+  if (A >= nA || b >= nblk) return;
   int m[3] = {0, 0, 0};
   {
     int q = b;
-    for (int a = 0; a < D; a++) { m[a] = q % M; q /= M; }
+    if (R2F) {
+      m[1] = q % M; q /= M;
+      m[0] = q % M; q /= M;
+      m[2] = q;
+    } else {
+      for (int a = 0; a < D; a++) { m[a] = q % M; q /= M; }
+    }
   }
   // coefficient indices of this block: idx[a][0] = cos (or the single m = 0 mode), idx[a][1] = sin
   int ix[3][2], cnt[3];
@@ -234,13 +229,13 @@ __global__ __launch_bounds__(256) void k_translate(const T* __restrict__ phi,
     if (a < D && m[a] > 0) { ix[a][0] = 2 * m[a] - 1; ix[a][1] = 2 * m[a]; cnt[a] = 2; }
     else { ix[a][0] = 0; ix[a][1] = 0; cnt[a] = 1; }
   }
-  int64_t stride[3] = {1, nr, (int64_t)nr * nr};
+  const int64_t stride[3] = {R2F ? nr : 1, R2F ? 1 : nr, (int64_t)nr * nr};
   int64_t off[8];
   int nv = 0;
   constexpr int NV = 1 << D;
   for (int v = 0; v < NV; v++) {
     int c0 = v & 1, c1 = (v >> 1) & 1, c2 = (v >> 2) & 1;
-    int64_t o = ix[0][c0];
+    int64_t o = stride[0] * ix[0][c0];
     if (D > 1) o += stride[1] * ix[1][c1];
     if (D > 2) o += stride[2] * ix[2][c2];
     off[v] = o;
@@ -671,10 +666,7 @@ static hipError_t launch_all(const DeviceArgs& a, const double* sigma, double* u
     hipLaunchKernelGGL((k_form_box<T, D>), dim3((unsigned)(a.nA * ncol)), dim3(256), 0, st, Y,
                        a.pw_start, a.pwleaf_tab, F, p, nr, ncol, phi);
     rec(2);
-    const int nblk = ipow(a.M, D);
-    const int nchunk = (nblk + 255) / 256;
-    hipLaunchKernelGGL((k_translate<T, D>), dim3((unsigned)(a.nA * nchunk)), dim3(256), 0, st,
-                       phi, a.plist_start, a.plist_src, a.plist_dir, rot, a.M, nr, nchunk, psi);
+    launch_translate<T>(a, st);
     rec(3);
     hipLaunchKernelGGL((k_eval_box<T, D>), dim3((unsigned)(a.nE * ncol)), dim3(256), 0, st, psi,
                        a.echunk, a.pwleaf_tab, E, p, nr, ncol, Y);
@@ -695,20 +687,38 @@ static hipError_t launch_all(const DeviceArgs& a, const double* sigma, double* u
   return hipGetLastError();
 }
 
+template <typename T>
+void launch_translate(const DeviceArgs& a, hipStream_t st) {
+  const int nblk = ipow(a.M, a.d);
+  const int64_t nbx = (a.nA + kXcds - 1) / kXcds;  // boxes per XCD (see k_translate)
+  const unsigned grid = (unsigned)(kXcds * nbx * ((nblk + 255) / 256));
+  const T* phi = static_cast<const T*>(a.phi);
+  const T* rot = static_cast<const T*>(a.rot);
+  T* psi = static_cast<T*>(a.psi);
+  const int nA = (int)a.nA;
+  switch (a.d) {
+    case 1:
+      hipLaunchKernelGGL((k_translate<T, 1, false>), dim3(grid), dim3(256), 0, st, phi, a.plist_start,
+                         a.plist_src, a.plist_dir, rot, a.M, a.nr, nA, psi);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_translate<T, 2, false>), dim3(grid), dim3(256), 0, st, phi, a.plist_start,
+                         a.plist_src, a.plist_dir, rot, a.M, a.nr, nA, psi);
+      break;
+    default:
+      hipLaunchKernelGGL((k_translate<T, 3, true>), dim3(grid), dim3(256), 0, st, phi, a.plist_start,
+                         a.plist_src, a.plist_dir, rot, a.M, a.nr, nA, psi);
+      break;
+  }
+}
+template void launch_translate<double>(const DeviceArgs&, hipStream_t);
+template void launch_translate<float>(const DeviceArgs&, hipStream_t);
+
 hipError_t launch_transform(const DeviceArgs& a, const double* sigma, double* u, hipStream_t st,
                             hipEvent_t* ev) {
-  if (a.fp32) {
-    switch (a.d) {
-      case 1: return launch_all<float, 1>(a, sigma, u, st, ev);
-      case 2: return launch_all<float, 2>(a, sigma, u, st, ev);
-      default: return launch_all<float, 3>(a, sigma, u, st, ev);
-    }
-  }
-  switch (a.d) {
-    case 1: return launch_all<double, 1>(a, sigma, u, st, ev);
-    case 2: return launch_all<double, 2>(a, sigma, u, st, ev);
-    default: return launch_all<double, 3>(a, sigma, u, st, ev);
-  }
+  if (a.d >= 2) return launch_fast(a, sigma, u, st, ev);
+  if (a.fp32) return launch_all<float, 1>(a, sigma, u, st, ev);
+  return launch_all<double, 1>(a, sigma, u, st, ev);
 }
 
 }  // namespace fgt

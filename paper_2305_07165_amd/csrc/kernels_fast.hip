@@ -1,0 +1,739 @@
+// Tuned device stages of the box Gauss transform for d = 2 and d = 3.
+//
+// Tile counts are compile time: NT = ceil(nr/16) mode tiles per axis and
+// KS = ceil(p/4) node steps (FP32 always runs 4 node steps, see mfma.h).
+// Node axes are padded to 16 inside a tile.  Chained contractions pass result
+// tiles from one matrix-core product to the next in registers (mfma.h); LDS is
+// used only where a contraction runs across the tiles held by different waves.
+//
+// d = 3:
+//   form3_leaf  Y_s[j3][r1][r2] = sum_j1 F1[r1][j1] (sum_j2 sigma_s[j3][j2][j1] F2[r2][j2])
+//   form_box    phi_A[r3][c]    = sum_{s in A} sum_j3 F3_s[r3][j3] Y_s[j3][c]
+//   translate   psi_A = sum_{B in P(A)} Rot(c_B - c_A) phi_B        (kernels.hip)
+//   eval_box    Z_s[i3][c]      = sum_r3 E3_s[i3][r3] psi_A[r3][c]
+//   eval3_leaf  u_s[i3][i2][i1] = sum_r2 E2[i2][r2] (sum_r1 Z_s[i3][r1][r2] E1[i1][r1])
+//   near3       u_T (+)= sum_S (V3 (x) V2 (x) V1) sigma_S, grouped by tables
+// The mode tensors phi, psi, Y, Z of d = 3 are stored with the r2 index fastest
+// ([r3][r1][r2]), so that every global operand load runs along a contiguous axis.
+// d = 2 fuses formation and evaluation per box / per leaf (no intermediate).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "kernels.h"
+#include "mfma.h"
+
+namespace fgt {
+
+__device__ __forceinline__ int lane_of() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_of() { return threadIdx.x >> 6; }
+
+template <typename T, int KS>
+struct Steps {
+  static constexpr int value = std::is_same<T, float>::value ? 4 : KS;
+};
+
+// ---------------------------------------------------------------------------
+// d = 3 formation, axes 2 and 1, one leaf per workgroup, one j3 slice per wave.
+// Mode tensors are stored [r3][r1][r2] (r2 fastest).  Per slice:
+//   X^T[j1][r2] = sum_j2 sigma[j3][j2][j1] F2[r2][j2]   (lanes run along j1: coalesced)
+//   Y[r1][r2]   = sum_j1 F1[r1][j1] X^T[j1][r2]        (B operand chained from X^T)
+
+template <typename T, int NT, int KS>
+__global__ __launch_bounds__(256) void form3_leaf(const double* __restrict__ sigma,
+                                                  const int32_t* __restrict__ leaf_id,
+                                                  const int32_t* __restrict__ leaf_tab,
+                                                  const T* __restrict__ F, int p, int nr,
+                                                  T* __restrict__ Y) {
+  typedef Mfma<T> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<T, KS>::value;
+  const int s = blockIdx.x;
+  const int leaf = leaf_id[s];
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const T* F1 = F + (int64_t)leaf_tab[s * 3 + 0] * nr * p;
+  const T* F2 = F + (int64_t)leaf_tab[s * 3 + 1] * nr * p;
+  T a1[NT][S], b2[NT][S];
+#pragma unroll
+  for (int t = 0; t < NT; t++)
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      const int k = M::kidx(kk, lk), r = 16 * t + lr;
+      const bool ok = r < nr && k < p;
+      a1[t][kk] = ok ? F1[r * p + k] : (T)0;  // A[r1][j1]
+      b2[t][kk] = ok ? F2[r * p + k] : (T)0;  // B[j2][r2] = F2[r2][j2]
+    }
+  const double* sg = sigma + (int64_t)leaf * p * p * p;
+  T* Ys = Y + (int64_t)s * p * nr * nr;
+  for (int j3 = w; j3 < p; j3 += 4) {
+    T av[S];
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      const int k = M::kidx(kk, lk);
+      av[kk] = (lr < p && k < p) ? (T)sg[(j3 * p + k) * p + lr] : (T)0;  // A[j1][j2]
+    }
+    acc_t x[NT];  // X^T, rows j1, columns r2 (tile ti)
+#pragma unroll
+    for (int ti = 0; ti < NT; ti++) {
+      zero4(x[ti]);
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) x[ti] = M::step(av[kk], b2[ti][kk], x[ti]);
+    }
+#pragma unroll
+    for (int tj = 0; tj < NT; tj++) {
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++) {
+        acc_t y;  // rows r1 (tile tj), columns r2 (tile ti)
+        zero4(y);
+#pragma unroll
+        for (int kk = 0; kk < S; kk++) y = M::step(a1[tj][kk], x[ti][kk], y);
+        const int r2 = 16 * ti + lr;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int r1 = 16 * tj + M::row(lk, t);
+          if (r1 < nr && r2 < nr) Ys[((int64_t)j3 * nr + r1) * nr + r2] = y[t];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// last-axis formation merged over the leaves of a cutoff box (a grouped GEMM)
+
+template <typename T, int D, int NT, int KS>
+__global__ __launch_bounds__(256) void form_box(const T* __restrict__ Y,
+                                                const int32_t* __restrict__ fitem,
+                                                const int32_t* __restrict__ leaf_tab,
+                                                const T* __restrict__ F, int p, int nr,
+                                                int ncoltiles, T* __restrict__ phi,
+                                                T* __restrict__ partial) {
+  // one work item (<= kFormLeaves leaves of a box) x 128 columns per workgroup;
+  // every wave owns two 16-column slabs, sharing the table operand between them
+  typedef Mfma<T> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<T, KS>::value;
+  const int item = blockIdx.x / ncoltiles;
+  const int ct = blockIdx.x % ncoltiles;
+  const int A = fitem[4 * item], slot = fitem[4 * item + 3];
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int N2 = D == 3 ? nr * nr : nr;
+  int col[2];
+  bool colok[2];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    col[h] = ct * 128 + w * 32 + 16 * h + lr;
+    colok[h] = col[h] < N2;
+  }
+  acc_t acc[NT][2];
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++) {
+    zero4(acc[ti][0]);
+    zero4(acc[ti][1]);
+  }
+  const int s0 = fitem[4 * item + 1], s1 = fitem[4 * item + 2];
+  T a[NT][S], b[S][2];
+  auto load = [&](int s, T (&aa)[NT][S], T (&bb)[S][2]) {
+    const T* Fs = F + (int64_t)leaf_tab[s * D + (D - 1)] * nr * p;
+    const T* Ys = Y + (int64_t)s * p * N2;
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      const int k = M::kidx(kk, lk);
+#pragma unroll
+      for (int h = 0; h < 2; h++) bb[kk][h] = (k < p && colok[h]) ? Ys[(int64_t)k * N2 + col[h]] : (T)0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++) {
+        const int r = 16 * ti + lr;
+        aa[ti][kk] = (r < nr && k < p) ? Fs[r * p + k] : (T)0;
+      }
+    }
+  };
+  if (s0 < s1) load(s0, a, b);
+  for (int s = s0; s < s1; s++) {
+    T an[NT][S], bn[S][2];
+    if (s + 1 < s1) load(s + 1, an, bn);
+#pragma unroll
+    for (int kk = 0; kk < S; kk++)
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) acc[ti][h] = M::step(a[ti][kk], b[kk][h], acc[ti][h]);
+    if (s + 1 < s1) {
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) {
+        b[kk][0] = bn[kk][0];
+        b[kk][1] = bn[kk][1];
+#pragma unroll
+        for (int ti = 0; ti < NT; ti++) a[ti][kk] = an[ti][kk];
+      }
+    }
+  }
+  // a box's only item writes phi; items of a split box write partial sums
+  T* out = slot < 0 ? phi + (int64_t)A * nr * N2 : partial + (int64_t)slot * nr * N2;
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int r = 16 * ti + M::row(lk, t);
+#pragma unroll
+      for (int h = 0; h < 2; h++)
+        if (r < nr && colok[h]) out[(int64_t)r * N2 + col[h]] = acc[ti][h][t];
+    }
+}
+
+// phi_A = sum of the partial sums of a split box, in item order (deterministic)
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_partials(const T* __restrict__ partial,
+                                                       const int32_t* __restrict__ fred,
+                                                       int64_t ncoef, int nchunk,
+                                                       T* __restrict__ phi) {
+  const int r = blockIdx.x / nchunk;
+  const int64_t i = (int64_t)(blockIdx.x % nchunk) * blockDim.x + threadIdx.x;
+  if (i >= ncoef) return;
+  const int A = fred[3 * r], slot0 = fred[3 * r + 1], n = fred[3 * r + 2];
+  T s = 0;
+  for (int k = 0; k < n; k++) s += partial[(int64_t)(slot0 + k) * ncoef + i];
+  phi[(int64_t)A * ncoef + i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// first evaluation contraction: Z rows of every leaf of one box for one tile of
+// 64 columns.  The box's psi columns stay in registers while the workgroup
+// walks the stacked leaf rows (s*p + i) two 16-row tiles at a time.  Boxes are
+// visited in the order box_order (most leaves first).
+
+template <typename T, int D, int NT>
+__global__ __launch_bounds__(256) void eval_box(const T* __restrict__ psi,
+                                                const int32_t* __restrict__ box_order,
+                                                const int32_t* __restrict__ pw_start,
+                                                const int32_t* __restrict__ leaf_tab,
+                                                const T* __restrict__ E, int p, int nr,
+                                                int ncoltiles, uint32_t pmagic,
+                                                T* __restrict__ Z) {
+  typedef Mfma<T> M;
+  typedef typename M::acc acc_t;
+  constexpr int Q = 4 * NT;
+  const int A = box_order[blockIdx.x / ncoltiles];
+  const int ct = blockIdx.x % ncoltiles;
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int N2 = D == 3 ? nr * nr : nr;
+  const int col = ct * 64 + w * 16 + lr;
+  const bool colok = col < N2;
+  const T* P = psi + (int64_t)A * nr * N2;
+  T b[Q];
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+    b[q] = (k < nr && colok) ? P[(int64_t)k * N2 + col] : (T)0;
+  }
+  const int s0 = pw_start[A];
+  const int rows = (pw_start[A + 1] - s0) * p;
+  T* Zb = Z + (int64_t)s0 * p * N2;
+  for (int rt = 0; rt < rows; rt += 32) {
+    acc_t acc[2];
+    int eoff[2];
+    bool ok[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      zero4(acc[h]);
+      const int row = rt + 16 * h + lr;
+      const int ls = (int)__umulhi((uint32_t)row, pmagic);  // row / p
+      ok[h] = row < rows;
+      eoff[h] = ok[h] ? (leaf_tab[(s0 + ls) * D + (D - 1)] * p + (row - ls * p)) * nr : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const T a = (ok[h] && k < nr) ? E[eoff[h] + k] : (T)0;
+        acc[h] = M::step(a, b[q], acc[h]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int r = rt + 16 * h + M::row(lk, t);
+        if (r < rows && colok) Zb[(int64_t)r * N2 + col] = acc[h][t];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// d = 3 evaluation, axes 1 and 2, one leaf per workgroup, one i3 slice per wave.
+// Z_s is stored [i3][r1][r2] (r2 fastest).  Per slice:
+//   W^T[r2][i1] = sum_r1 Z[r1][r2] E1[i1][r1]           (lanes run along r2: coalesced)
+//   u[i2][i1]   = sum_r2 E2[i2][r2] W^T[r2][i1]         (B operand chained from W^T)
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void eval3_leaf(const T* __restrict__ Z,
+                                                  const int32_t* __restrict__ leaf_id,
+                                                  const int32_t* __restrict__ leaf_tab,
+                                                  const T* __restrict__ E, int p, int nr,
+                                                  double* __restrict__ u) {
+  typedef Mfma<T> M;
+  typedef typename M::acc acc_t;
+  constexpr int Q = 4 * NT;
+  const int s = blockIdx.x;
+  const int leaf = leaf_id[s];
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const T* E1 = E + (int64_t)leaf_tab[s * 3 + 0] * p * nr;
+  const T* E2 = E + (int64_t)leaf_tab[s * 3 + 1] * p * nr;
+  T b1[Q], a2[Q];
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+    const bool ok = lr < p && k < nr;
+    b1[q] = ok ? E1[lr * nr + k] : (T)0;  // B[r1][i1] = E1[i1][r1]
+    a2[q] = ok ? E2[lr * nr + k] : (T)0;  // A[i2][r2]
+  }
+  double* ul = u + (int64_t)leaf * p * p * p;
+  for (int i3 = w; i3 < p; i3 += 4) {
+    const T* Zs = Z + ((int64_t)s * p + i3) * nr * nr;
+    acc_t wt[NT];  // W^T, rows r2 (tile ti), columns i1
+#pragma unroll
+    for (int ti = 0; ti < NT; ti++) {
+      zero4(wt[ti]);
+      const int r2 = 16 * ti + lr;
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);  // r1
+        const T a = (r2 < nr && k < nr) ? Zs[k * nr + r2] : (T)0;
+        wt[ti] = M::step(a, b1[q], wt[ti]);
+      }
+    }
+    acc_t uu;
+    zero4(uu);
+#pragma unroll
+    for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) uu = M::step(a2[4 * ti + kk], wt[ti][kk], uu);
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int i2 = M::row(lk, t);
+      if (i2 < p && lr < p) ul[((int64_t)i3 * p + i2) * p + lr] = (double)uu[t];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// d = 3 near field, one target leaf per workgroup.  A target's sources are
+// sorted by (V3, V1, V2): axis 2 is contracted per source, axis 1 once per
+// (V3, V1) run and axis 3 once per V3 run (separability, Remark dircost).
+//   level A  T^T[j3][j1][i2] += sum_j2 sigma[j3][j2][j1] V2[i2][j2]  (lanes along j1)
+//   level B  U[j3][i1][i2]   += sum_j1 V1[i1][j1] T^T[j3][j1][i2]    (chained)
+//   level C  u[i3][i2][i1]   += sum_j3 V3[i3][j3] U[j3][i1][i2]      (j3 spans waves: LDS)
+
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void near3(const double* __restrict__ sigma,
+                                             const int32_t* __restrict__ near_tgt,
+                                             const int32_t* __restrict__ near_haspw,
+                                             const int32_t* __restrict__ near_start,
+                                             const int32_t* __restrict__ near_src,
+                                             const int32_t* __restrict__ near_tab,
+                                             const T* __restrict__ V, int p,
+                                             double* __restrict__ u) {
+  typedef Mfma<T> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<T, KS>::value;
+  constexpr int RS = 17;            // padded i2 stride of the LDS tile
+  constexpr int US = 16 * RS + 4;   // padded j3 stride
+  __shared__ T Us[16 * US];         // U[j3][i2][i1]
+  const int t = blockIdx.x;
+  const int Tleaf = near_tgt[t];
+  const bool add = near_haspw[t] != 0;
+  const int q0 = near_start[t], q1 = near_start[t + 1];
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int pp = p * p;
+  acc_t tacc[4], uacc[4], oacc[4];
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    zero4(tacc[c]);
+    zero4(uacc[c]);
+    zero4(oacc[c]);
+  }
+  for (int q = q0; q < q1; q++) {
+    const int t1 = near_tab[q * 3 + 0], t2 = near_tab[q * 3 + 1], t3 = near_tab[q * 3 + 2];
+    const double* sg = sigma + (int64_t)near_src[q] * pp * p;
+    const T* V2 = V + (int64_t)t2 * pp;
+    T b2[S];
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      const int k = M::kidx(kk, lk);
+      b2[kk] = (lr < p && k < p) ? V2[lr * p + k] : (T)0;  // B[j2][i2] = V2[i2][j2]
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const int j3 = w + 4 * c;
+      if (j3 < p) {
+#pragma unroll
+        for (int kk = 0; kk < S; kk++) {
+          const int k = M::kidx(kk, lk);
+          const T a = (lr < p && k < p) ? (T)sg[(j3 * p + k) * p + lr] : (T)0;  // A[j1][j2]
+          tacc[c] = M::step(a, b2[kk], tacc[c]);
+        }
+      }
+    }
+    const bool last = q + 1 == q1;
+    const bool end1 = last || near_tab[q * 3 + 5] != t3 || near_tab[q * 3 + 3] != t1;
+    const bool end3 = last || near_tab[q * 3 + 5] != t3;
+    if (end1) {
+      const T* V1 = V + (int64_t)t1 * pp;
+      T a1[S];
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) {
+        const int k = M::kidx(kk, lk);
+        a1[kk] = (lr < p && k < p) ? V1[lr * p + k] : (T)0;  // A[i1][j1]
+      }
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        if (w + 4 * c < p) {
+#pragma unroll
+          for (int kk = 0; kk < S; kk++) uacc[c] = M::step(a1[kk], tacc[c][kk], uacc[c]);
+        }
+        zero4(tacc[c]);
+      }
+    }
+    if (end3) {
+      __syncthreads();  // previous readers of Us are done
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const int j3 = w + 4 * c;
+        if (j3 < p) {
+#pragma unroll
+          for (int tt = 0; tt < 4; tt++) Us[j3 * US + lr * RS + M::row(lk, tt)] = uacc[c][tt];
+        }
+        zero4(uacc[c]);
+      }
+      __syncthreads();
+      const T* V3 = V + (int64_t)t3 * pp;
+      T a3[S];
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) {
+        const int k = M::kidx(kk, lk);
+        a3[kk] = (lr < p && k < p) ? V3[lr * p + k] : (T)0;  // A[i3][j3]
+      }
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const int i2 = w + 4 * c;  // column tile (i2, i1 = lr)
+        if (i2 < p) {
+#pragma unroll
+          for (int kk = 0; kk < S; kk++) {
+            const int j3 = M::kidx(kk, lk);
+            const T b = j3 < p ? Us[j3 * US + i2 * RS + lr] : (T)0;
+            oacc[c] = M::step(a3[kk], b, oacc[c]);
+          }
+        }
+      }
+    }
+  }
+  double* ut = u + (int64_t)Tleaf * pp * p;
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    const int i2 = w + 4 * c;
+    if (i2 < p && lr < p) {
+#pragma unroll
+      for (int tt = 0; tt < 4; tt++) {
+        const int i3 = M::row(lk, tt);
+        if (i3 < p) {
+          const int64_t o = ((int64_t)i3 * p + i2) * p + lr;
+          ut[o] = add ? ut[o] + (double)oacc[c][tt] : (double)oacc[c][tt];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// d = 2: formation of a whole cutoff box, both axes, leaves in sequence.
+// Waves split the r1 tiles; every wave keeps all r2 tiles of its columns.
+
+template <typename T, int NT, int KS>
+__global__ __launch_bounds__(256) void form2_box(const double* __restrict__ sigma,
+                                                 const int32_t* __restrict__ fitem,
+                                                 const int32_t* __restrict__ leaf_id,
+                                                 const int32_t* __restrict__ leaf_tab,
+                                                 const T* __restrict__ F, int p, int nr,
+                                                 T* __restrict__ phi, T* __restrict__ partial) {
+  typedef Mfma<T> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<T, KS>::value;
+  constexpr int TW = (NT + 3) / 4;  // r1 tiles per wave
+  const int item = blockIdx.x;
+  const int A = fitem[4 * item], slot = fitem[4 * item + 3];
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  acc_t acc[NT][TW];
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+    for (int c = 0; c < TW; c++) zero4(acc[ti][c]);
+  const int s0 = fitem[4 * item + 1], s1 = fitem[4 * item + 2];
+  for (int s = s0; s < s1; s++) {
+    const T* F1 = F + (int64_t)leaf_tab[s * 2 + 0] * nr * p;
+    const T* F2 = F + (int64_t)leaf_tab[s * 2 + 1] * nr * p;
+    const double* sg = sigma + (int64_t)leaf_id[s] * p * p;
+    T av[S], a2[NT][S];
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      const int k = M::kidx(kk, lk);
+      av[kk] = (lr < p && k < p) ? (T)sg[lr * p + k] : (T)0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++) {
+        const int r = 16 * ti + lr;
+        a2[ti][kk] = (r < nr && k < p) ? F2[r * p + k] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < TW; c++) {
+      const int tj = w + 4 * c;
+      if (tj < NT) {
+        // X[j2][r1] = sum_j1 sigma[j2][j1] F1[r1][j1]
+        acc_t x;
+        zero4(x);
+#pragma unroll
+        for (int kk = 0; kk < S; kk++) {
+          const int k = M::kidx(kk, lk), r = 16 * tj + lr;
+          const T b = (r < nr && k < p) ? F1[r * p + k] : (T)0;
+          x = M::step(av[kk], b, x);
+        }
+        // phi[r2][r1] += sum_j2 F2[r2][j2] X[j2][r1]
+#pragma unroll
+        for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+          for (int kk = 0; kk < S; kk++) acc[ti][c] = M::step(a2[ti][kk], x[kk], acc[ti][c]);
+      }
+    }
+  }
+  T* out = slot < 0 ? phi + (int64_t)A * nr * nr : partial + (int64_t)slot * nr * nr;
+#pragma unroll
+  for (int c = 0; c < TW; c++) {
+    const int tj = w + 4 * c;
+    const int r1 = 16 * tj + lr;
+    if (tj < NT && r1 < nr) {
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int r2 = 16 * ti + M::row(lk, t);
+          if (r2 < nr) out[r2 * nr + r1] = acc[ti][c][t];
+        }
+    }
+  }
+}
+
+// d = 2: evaluation of one leaf per wave from its box's incoming expansion.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void eval2_leaf(const T* __restrict__ psi,
+                                                  const int32_t* __restrict__ leaf_box,
+                                                  const int32_t* __restrict__ leaf_id,
+                                                  const int32_t* __restrict__ leaf_tab,
+                                                  const T* __restrict__ E, int p, int nr,
+                                                  int nleaf, double* __restrict__ u) {
+  typedef Mfma<T> M;
+  typedef typename M::acc acc_t;
+  constexpr int Q = 4 * NT;
+  const int lane = lane_of(), w = wave_of();
+  const int s = blockIdx.x * 4 + w;
+  if (s >= nleaf) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  const T* E1 = E + (int64_t)leaf_tab[s * 2 + 0] * p * nr;
+  const T* E2 = E + (int64_t)leaf_tab[s * 2 + 1] * p * nr;
+  const T* P = psi + (int64_t)leaf_box[s] * nr * nr;
+  // W[r2][i1] = sum_r1 psi[r2][r1] E1[i1][r1]
+  acc_t wt[NT];
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++) zero4(wt[ti]);
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+    const T b = (lr < p && k < nr) ? E1[lr * nr + k] : (T)0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ti++) {
+      const int r2 = 16 * ti + lr;
+      const T a = (r2 < nr && k < nr) ? P[r2 * nr + k] : (T)0;
+      wt[ti] = M::step(a, b, wt[ti]);
+    }
+  }
+  // u[i2][i1] = sum_r2 E2[i2][r2] W[r2][i1]
+  acc_t uu;
+  zero4(uu);
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+    for (int kk = 0; kk < 4; kk++) {
+      const int k = 16 * ti + M::kidx(kk, lk);
+      const T a = (lr < p && k < nr) ? E2[lr * nr + k] : (T)0;
+      uu = M::step(a, wt[ti][kk], uu);
+    }
+  double* ul = u + (int64_t)leaf_id[s] * p * p;
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    const int i2 = M::row(lk, t);
+    if (i2 < p && lr < p) ul[i2 * p + lr] = (double)uu[t];
+  }
+}
+
+// d = 2 near field: one target per wave; sources sorted by (V2, V1): axis 1
+// per source, axis 2 once per V2 group.
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void near2(const double* __restrict__ sigma,
+                                             const int32_t* __restrict__ near_tgt,
+                                             const int32_t* __restrict__ near_haspw,
+                                             const int32_t* __restrict__ near_start,
+                                             const int32_t* __restrict__ near_src,
+                                             const int32_t* __restrict__ near_tab,
+                                             const T* __restrict__ V, int p, int ntgt,
+                                             double* __restrict__ u) {
+  typedef Mfma<T> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<T, KS>::value;
+  const int lane = lane_of(), w = wave_of();
+  const int t = blockIdx.x * 4 + w;
+  if (t >= ntgt) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int pp = p * p;
+  const int q0 = near_start[t], q1 = near_start[t + 1];
+  acc_t tacc, oacc;
+  zero4(tacc);
+  zero4(oacc);
+  for (int q = q0; q < q1; q++) {
+    const int t1 = near_tab[q * 2 + 0], t2 = near_tab[q * 2 + 1];
+    const double* sg = sigma + (int64_t)near_src[q] * pp;
+    const T* V1 = V + (int64_t)t1 * pp;
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      const int k = M::kidx(kk, lk);
+      const T a = (lr < p && k < p) ? (T)sg[lr * p + k] : (T)0;
+      const T b = (lr < p && k < p) ? V1[lr * p + k] : (T)0;
+      tacc = M::step(a, b, tacc);  // T[j2][i1]
+    }
+    if (q + 1 == q1 || near_tab[q * 2 + 3] != t2) {
+      const T* V2 = V + (int64_t)t2 * pp;
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) {
+        const int k = M::kidx(kk, lk);
+        const T a = (lr < p && k < p) ? V2[lr * p + k] : (T)0;
+        oacc = M::step(a, tacc[kk], oacc);  // u[i2][i1] += V2[i2][j2] T[j2][i1]
+      }
+      zero4(tacc);
+    }
+  }
+  double* ut = u + (int64_t)near_tgt[t] * pp;
+  const bool add = near_haspw[t] != 0;
+#pragma unroll
+  for (int tt = 0; tt < 4; tt++) {
+    const int i2 = M::row(lk, tt);
+    if (i2 < p && lr < p) ut[i2 * p + lr] = add ? ut[i2 * p + lr] + (double)oacc[tt] : (double)oacc[tt];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch
+
+template <typename T>
+static void launch_reduce(const DeviceArgs& a, hipStream_t st) {
+  if (a.nFR == 0) return;
+  int64_t ncoef = a.nr;
+  for (int i = 1; i < a.d; i++) ncoef *= a.nr;
+  const int nchunk = (int)((ncoef + 255) / 256);
+  hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)(a.nFR * nchunk)), dim3(256), 0, st,
+                     static_cast<const T*>(a.partial), a.fred, ncoef, nchunk, static_cast<T*>(a.phi));
+}
+
+template <typename T, int NT, int KS>
+static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipStream_t st,
+                      hipEvent_t* ev, int D) {
+  const int p = a.p, nr = a.nr;
+  const T* F = static_cast<const T*>(a.F);
+  const T* E = static_cast<const T*>(a.E);
+  const T* V = static_cast<const T*>(a.V);
+  T* Y = static_cast<T*>(a.Y);
+  T* phi = static_cast<T*>(a.phi);
+  T* psi = static_cast<T*>(a.psi);
+  auto rec = [&](int i) { if (ev) (void)hipEventRecord(ev[i], st); };
+  rec(0);
+  if (a.nL > 0) {
+    if (D == 3) {
+      const int N2 = nr * nr, ncol = (N2 + 63) / 64, ncol128 = (N2 + 127) / 128;
+      hipLaunchKernelGGL((form3_leaf<T, NT, KS>), dim3(a.nL), dim3(256), 0, st, sigma, a.pwleaf_id,
+                         a.pwleaf_tab, F, p, nr, Y);
+      rec(1);
+      hipLaunchKernelGGL((form_box<T, 3, NT, KS>), dim3((unsigned)(a.nFI * ncol128)), dim3(256), 0, st, Y,
+                         a.fitem, a.pwleaf_tab, F, p, nr, ncol128, phi, static_cast<T*>(a.partial));
+      launch_reduce<T>(a, st);
+      rec(2);
+      launch_translate<T>(a, st);
+      rec(3);
+      const uint32_t pmagic = (uint32_t)((0x100000000ull + p - 1) / p);  // ceil(2^32 / p)
+      hipLaunchKernelGGL((eval_box<T, 3, NT>), dim3((unsigned)(a.nA * ncol)), dim3(256), 0, st, psi,
+                         a.box_order, a.pw_start, a.pwleaf_tab, E, p, nr, ncol, pmagic, Y);
+      rec(4);
+      hipLaunchKernelGGL((eval3_leaf<T, NT>), dim3(a.nL), dim3(256), 0, st, Y, a.pwleaf_id,
+                         a.pwleaf_tab, E, p, nr, u);
+      rec(5);
+    } else {
+      rec(1);
+      hipLaunchKernelGGL((form2_box<T, NT, KS>), dim3(a.nFI), dim3(256), 0, st, sigma, a.fitem,
+                         a.pwleaf_id, a.pwleaf_tab, F, p, nr, phi, static_cast<T*>(a.partial));
+      launch_reduce<T>(a, st);
+      rec(2);
+      launch_translate<T>(a, st);
+      rec(3);
+      rec(4);
+      hipLaunchKernelGGL((eval2_leaf<T, NT>), dim3((unsigned)((a.nL + 3) / 4)), dim3(256), 0, st, psi,
+                         a.pwleaf_box, a.pwleaf_id, a.pwleaf_tab, E, p, nr, (int)a.nL, u);
+      rec(5);
+    }
+  } else {
+    for (int i = 1; i <= 5; i++) rec(i);
+  }
+  if (a.nT > 0) {
+    if (D == 3)
+      hipLaunchKernelGGL((near3<T, KS>), dim3(a.nT), dim3(256), 0, st, sigma, a.near_tgt, a.near_haspw,
+                         a.near_start, a.near_src, a.near_tab, V, p, u);
+    else
+      hipLaunchKernelGGL((near2<T, KS>), dim3((unsigned)((a.nT + 3) / 4)), dim3(256), 0, st, sigma,
+                         a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, V, p,
+                         (int)a.nT, u);
+  }
+  rec(6);
+}
+
+template <typename T, int KS>
+static void launch_ks(const DeviceArgs& a, const double* sigma, double* u, hipStream_t st,
+                      hipEvent_t* ev) {
+  const int nt = (a.nr + 15) / 16;
+  switch (nt) {
+    case 1: launch_nt<T, 1, KS>(a, sigma, u, st, ev, a.d); break;
+    case 2: launch_nt<T, 2, KS>(a, sigma, u, st, ev, a.d); break;
+    case 3: launch_nt<T, 3, KS>(a, sigma, u, st, ev, a.d); break;
+    case 4: launch_nt<T, 4, KS>(a, sigma, u, st, ev, a.d); break;
+    case 5: launch_nt<T, 5, KS>(a, sigma, u, st, ev, a.d); break;
+    case 6: launch_nt<T, 6, KS>(a, sigma, u, st, ev, a.d); break;
+    case 7: launch_nt<T, 7, KS>(a, sigma, u, st, ev, a.d); break;
+    default: launch_nt<T, 8, KS>(a, sigma, u, st, ev, a.d); break;
+  }
+}
+
+hipError_t launch_fast(const DeviceArgs& a, const double* sigma, double* u, hipStream_t st,
+                       hipEvent_t* ev) {
+  const bool ks2 = a.p <= 8;
+  if (a.fp32) {
+    if (ks2) launch_ks<float, 2>(a, sigma, u, st, ev);
+    else launch_ks<float, 4>(a, sigma, u, st, ev);
+  } else {
+    if (ks2) launch_ks<double, 2>(a, sigma, u, st, ev);
+    else launch_ks<double, 4>(a, sigma, u, st, ev);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fgt

@@ -244,10 +244,12 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
   hp.pw_start.assign(nA + 1, 0);
   hp.pwleaf_id.resize(pl.size());
   hp.pwleaf_tab.resize(pl.size() * d);
+  hp.pwleaf_box.resize(pl.size());
   for (size_t s = 0; s < pl.size(); s++) {
     int32_t i = pl[s].id;
     int l = level[i];
     hp.pwleaf_id[s] = i;
+    hp.pwleaf_box[s] = pl[s].box;
     hp.pw_start[pl[s].box + 1]++;
     for (int a = 0; a < d; a++) {
       int32_t pos = coord[i * d + a] - ((coord[i * d + a] >> (l - lc)) << (l - lc));
@@ -269,6 +271,39 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
   hp.nftab = (int)ftab_lv.size();
   hp.ftab_meta = ftab_lv;
   hp.ftab_meta.insert(hp.ftab_meta.end(), ftab_pos.begin(), ftab_pos.end());
+
+  // dispatch order of per-box work: most leaves first (longest work first)
+  hp.box_order.resize(nA);
+  for (int32_t a = 0; a < nA; a++) hp.box_order[a] = a;
+  std::stable_sort(hp.box_order.begin(), hp.box_order.end(), [&](int32_t x, int32_t y) {
+    return hp.pw_start[x + 1] - hp.pw_start[x] > hp.pw_start[y + 1] - hp.pw_start[y];
+  });
+
+  // formation work items: at most kFormLeaves leaves each
+  for (int32_t a = 0; a < nA; a++) {
+    const int32_t s0 = hp.pw_start[a], s1 = hp.pw_start[a + 1];
+    if (s1 - s0 <= kFormLeaves) {
+      hp.fitem.insert(hp.fitem.end(), {a, s0, s1, -1});
+      continue;
+    }
+    const int32_t first = hp.nslots;
+    for (int32_t s = s0; s < s1; s += kFormLeaves)
+      hp.fitem.insert(hp.fitem.end(), {a, s, std::min(s + kFormLeaves, s1), hp.nslots++});
+    hp.fred.insert(hp.fred.end(), {a, first, hp.nslots - first});
+  }
+
+  {
+    const size_t ni = hp.fitem.size() / 4;
+    std::vector<int32_t> ord(ni);
+    for (size_t i = 0; i < ni; i++) ord[i] = (int32_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+      return hp.fitem[4 * x + 2] - hp.fitem[4 * x + 1] > hp.fitem[4 * y + 2] - hp.fitem[4 * y + 1];
+    });
+    std::vector<int32_t> f2;
+    f2.reserve(hp.fitem.size());
+    for (int32_t i : ord) f2.insert(f2.end(), hp.fitem.begin() + 4 * i, hp.fitem.begin() + 4 * i + 4);
+    hp.fitem.swap(f2);
+  }
 
   // evaluation chunks: up to 64 stacked rows (count*p) of one box
   const int per = std::max(1, 64 / p);
@@ -364,11 +399,14 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
       for (int a = 0; a < d; a++) if (x.shift[a] != y.shift[a]) return x.shift[a] < y.shift[a];
       return false;
     });
+    // one row per source: d table ids (axis 1..d) then the source leaf
+    std::vector<std::array<int32_t, kMaxDim + 1>> rows;
     for (auto& e : ents) {
       const int lS = level[e.S];
       if (lS > lc) continue;
       const int lF = std::max(l, lS);
-      hp.near_src.push_back(e.S);
+      std::array<int32_t, kMaxDim + 1> row{};
+      row[kMaxDim] = e.S;
       for (int a = 0; a < d; a++) {
         // centers in units of 2^-(lF+1); S shifted by its image
         int64_t cTu = (2 * (int64_t)cT[a] + 1) << (lF - l);
@@ -392,8 +430,24 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
         } else {
           id = iv->second;
         }
-        hp.near_tab.push_back(id);
+        row[a] = id;
       }
+      rows.push_back(row);
+    }
+    // sort so that runs of equal tables are contiguous: d = 3 by (axis 3,
+    // axis 1, axis 2) -- the kernel contracts axis 2 per source, axis 1 per
+    // run of (axis 3, axis 1) and axis 3 per run of axis 3; d = 2 by (axis 2,
+    // axis 1) -- axis 1 per source, axis 2 per run
+    static const int order3[3] = {2, 0, 1}, order2[2] = {1, 0}, order1[1] = {0};
+    const int* order = d == 3 ? order3 : (d == 2 ? order2 : order1);
+    std::sort(rows.begin(), rows.end(), [&](const std::array<int32_t, kMaxDim + 1>& x,
+                                            const std::array<int32_t, kMaxDim + 1>& y) {
+      for (int i = 0; i < d; i++) if (x[order[i]] != y[order[i]]) return x[order[i]] < y[order[i]];
+      return x[kMaxDim] < y[kMaxDim];
+    });
+    for (auto& row : rows) {
+      hp.near_src.push_back(row[kMaxDim]);
+      for (int a = 0; a < d; a++) hp.near_tab.push_back(row[a]);
     }
     hp.near_tgt.push_back(T);
     int haspw = 0;
@@ -403,6 +457,30 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     }
     hp.near_haspw.push_back(haspw);
     hp.near_start.push_back((int32_t)hp.near_src.size());
+  }
+  {
+    // dispatch order of the near targets: most sources first
+    const int64_t nt = (int64_t)hp.near_tgt.size();
+    std::vector<int32_t> ord(nt);
+    for (int64_t i = 0; i < nt; i++) ord[i] = (int32_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+      return hp.near_start[x + 1] - hp.near_start[x] > hp.near_start[y + 1] - hp.near_start[y];
+    });
+    std::vector<int32_t> tg, hpw, st{0}, src, tab;
+    for (int32_t i : ord) {
+      tg.push_back(hp.near_tgt[i]);
+      hpw.push_back(hp.near_haspw[i]);
+      for (int32_t q = hp.near_start[i]; q < hp.near_start[i + 1]; q++) {
+        src.push_back(hp.near_src[q]);
+        for (int a = 0; a < d; a++) tab.push_back(hp.near_tab[(int64_t)q * d + a]);
+      }
+      st.push_back((int32_t)src.size());
+    }
+    hp.near_tgt.swap(tg);
+    hp.near_haspw.swap(hpw);
+    hp.near_start.swap(st);
+    hp.near_src.swap(src);
+    hp.near_tab.swap(tab);
   }
   hp.nvtab = (int)vtab_lv.size();
   hp.vtab_meta = vtab_lv;
