@@ -249,18 +249,22 @@ __global__ __launch_bounds__(256) void k_translate(const T* __restrict__ phi,
 #pragma unroll
   for (int v = 0; v < NV; v++) acc[v] = 0;
   const int q0 = plist_start[A], q1 = plist_start[A + 1];
-  for (int q = q0; q < q1; q++) {
-    const T* src = phi + (int64_t)plist_src[q] * ncoef;
-    int code = plist_dir[q];
-    T x[NV];
+  bool present[NV];
 #pragma unroll
-    for (int v = 0; v < NV; v++) {
-      bool ok = true;
-      if (cnt[0] == 1 && (v & 1)) ok = false;
-      if (D > 1 && cnt[1] == 1 && ((v >> 1) & 1)) ok = false;
-      if (D > 2 && cnt[2] == 1 && ((v >> 2) & 1)) ok = false;
-      x[v] = ok ? src[off[v]] : (T)0;
-    }
+  for (int v = 0; v < NV; v++) {
+    present[v] = !((cnt[0] == 1 && (v & 1)) || (D > 1 && cnt[1] == 1 && ((v >> 1) & 1)) ||
+                   (D > 2 && cnt[2] == 1 && ((v >> 2) & 1)));
+  }
+  // two sources in flight: the loads of source q+1 are issued before the
+  // rotations of source q
+  auto fetch = [&](int q, T (&x)[NV]) {
+    const bool okq = q < q1;
+    const T* src = phi + (int64_t)(okq ? plist_src[q] : 0) * ncoef;
+#pragma unroll
+    for (int v = 0; v < NV; v++) x[v] = ld0<T>(src, off[v], okq && present[v]);
+  };
+  auto apply = [&](int q, T (&x)[NV]) {
+    int code = plist_dir[q];
 #pragma unroll
     for (int a = 0; a < D; a++) {
       const int dir = code % 3 - 1;
@@ -278,6 +282,16 @@ __global__ __launch_bounds__(256) void k_translate(const T* __restrict__ phi,
     }
 #pragma unroll
     for (int v = 0; v < NV; v++) acc[v] += x[v];
+  };
+  T xa[NV], xb[NV];
+  fetch(q0, xa);
+  for (int q = q0; q < q1; q += 2) {
+    fetch(q + 1, xb);
+    apply(q, xa);
+    if (q + 1 < q1) {
+      fetch(q + 2, xa);
+      apply(q + 1, xb);
+    }
   }
   T* dst = psi + (int64_t)A * ncoef;
 #pragma unroll

@@ -41,7 +41,7 @@ struct Steps {
 //   Y[r1][r2]   = sum_j1 F1[r1][j1] X^T[j1][r2]        (B operand chained from X^T)
 
 template <typename T, int NT, int KS>
-__global__ __launch_bounds__(256) void form3_leaf(const double* __restrict__ sigma,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void form3_leaf(const double* __restrict__ sigma,
                                                   const int32_t* __restrict__ leaf_id,
                                                   const int32_t* __restrict__ leaf_tab,
                                                   const T* __restrict__ F, int p, int nr,
@@ -62,18 +62,24 @@ __global__ __launch_bounds__(256) void form3_leaf(const double* __restrict__ sig
     for (int kk = 0; kk < S; kk++) {
       const int k = M::kidx(kk, lk), r = 16 * t + lr;
       const bool ok = r < nr && k < p;
-      a1[t][kk] = ok ? F1[r * p + k] : (T)0;  // A[r1][j1]
-      b2[t][kk] = ok ? F2[r * p + k] : (T)0;  // B[j2][r2] = F2[r2][j2]
+      a1[t][kk] = ld0<T>(F1, r * p + k, ok);  // A[r1][j1]
+      b2[t][kk] = ld0<T>(F2, r * p + k, ok);  // B[j2][r2] = F2[r2][j2]
     }
   const double* sg = sigma + (int64_t)leaf * p * p * p;
   T* Ys = Y + (int64_t)s * p * nr * nr;
-  for (int j3 = w; j3 < p; j3 += 4) {
-    T av[S];
+  T avs[KS][S];
+#pragma unroll
+  for (int it = 0; it < KS; it++)
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
-      const int k = M::kidx(kk, lk);
-      av[kk] = (lr < p && k < p) ? (T)sg[(j3 * p + k) * p + lr] : (T)0;  // A[j1][j2]
+      const int j3 = w + 4 * it, k = M::kidx(kk, lk);
+      avs[it][kk] = ld0<T>(sg, (j3 * p + k) * p + lr, j3 < p && lr < p && k < p);  // A[j1][j2]
     }
+#pragma unroll
+  for (int it = 0; it < KS; it++) {
+    const int j3 = w + 4 * it;
+    if (j3 >= p) break;
+    const T (&av)[S] = avs[it];
     acc_t x[NT];  // X^T, rows j1, columns r2 (tile ti)
 #pragma unroll
     for (int ti = 0; ti < NT; ti++) {
@@ -135,40 +141,42 @@ __global__ __launch_bounds__(256) void form_box(const T* __restrict__ Y,
     zero4(acc[ti][1]);
   }
   const int s0 = fitem[4 * item + 1], s1 = fitem[4 * item + 2];
-  T a[NT][S], b[S][2];
+  // operands of leaf s; loads are masked, not branched, so that no control-flow
+  // join forces a wait for the prefetched leaf before the current products
   auto load = [&](int s, T (&aa)[NT][S], T (&bb)[S][2]) {
-    const T* Fs = F + (int64_t)leaf_tab[s * D + (D - 1)] * nr * p;
-    const T* Ys = Y + (int64_t)s * p * N2;
+    const bool ls = s < s1;
+    const int sc = ls ? s : s0;
+    const T* Fs = F + (int64_t)leaf_tab[sc * D + (D - 1)] * nr * p;
+    const T* Ys = Y + (int64_t)sc * p * N2;
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
       const int k = M::kidx(kk, lk);
 #pragma unroll
-      for (int h = 0; h < 2; h++) bb[kk][h] = (k < p && colok[h]) ? Ys[(int64_t)k * N2 + col[h]] : (T)0;
+      for (int h = 0; h < 2; h++) bb[kk][h] = ld0<T>(Ys, (int64_t)k * N2 + col[h], ls && k < p && colok[h]);
 #pragma unroll
       for (int ti = 0; ti < NT; ti++) {
         const int r = 16 * ti + lr;
-        aa[ti][kk] = (r < nr && k < p) ? Fs[r * p + k] : (T)0;
+        aa[ti][kk] = ld0<T>(Fs, r * p + k, ls && r < nr && k < p);
       }
     }
   };
-  if (s0 < s1) load(s0, a, b);
+  T a[NT][S], b[S][2];
+  load(s0, a, b);
   for (int s = s0; s < s1; s++) {
     T an[NT][S], bn[S][2];
-    if (s + 1 < s1) load(s + 1, an, bn);
+    load(s + 1, an, bn);
 #pragma unroll
     for (int kk = 0; kk < S; kk++)
 #pragma unroll
       for (int ti = 0; ti < NT; ti++)
 #pragma unroll
         for (int h = 0; h < 2; h++) acc[ti][h] = M::step(a[ti][kk], b[kk][h], acc[ti][h]);
-    if (s + 1 < s1) {
 #pragma unroll
-      for (int kk = 0; kk < S; kk++) {
-        b[kk][0] = bn[kk][0];
-        b[kk][1] = bn[kk][1];
+    for (int kk = 0; kk < S; kk++) {
+      b[kk][0] = bn[kk][0];
+      b[kk][1] = bn[kk][1];
 #pragma unroll
-        for (int ti = 0; ti < NT; ti++) a[ti][kk] = an[ti][kk];
-      }
+      for (int ti = 0; ti < NT; ti++) a[ti][kk] = an[ti][kk];
     }
   }
   // a box's only item writes phi; items of a split box write partial sums
@@ -206,7 +214,7 @@ __global__ __launch_bounds__(256) void reduce_partials(const T* __restrict__ par
 // visited in the order box_order (most leaves first).
 
 template <typename T, int D, int NT>
-__global__ __launch_bounds__(256) void eval_box(const T* __restrict__ psi,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval_box(const T* __restrict__ psi,
                                                 const int32_t* __restrict__ box_order,
                                                 const int32_t* __restrict__ pw_start,
                                                 const int32_t* __restrict__ leaf_tab,
@@ -228,11 +236,16 @@ __global__ __launch_bounds__(256) void eval_box(const T* __restrict__ psi,
 #pragma unroll
   for (int q = 0; q < Q; q++) {
     const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
-    b[q] = (k < nr && colok) ? P[(int64_t)k * N2 + col] : (T)0;
+    b[q] = ld0<T>(P, (int64_t)k * N2 + col, k < nr && colok);
   }
   const int s0 = pw_start[A];
   const int rows = (pw_start[A + 1] - s0) * p;
   T* Zb = Z + (int64_t)s0 * p * N2;
+  auto tab_of = [&](int row) {
+    const int ls = (int)__umulhi((uint32_t)row, pmagic);  // row / p
+    return ld0<int32_t>(leaf_tab, (int64_t)(s0 + ls) * D + (D - 1), row < rows);
+  };
+  int tnext[2] = {tab_of(lr), tab_of(16 + lr)};
   for (int rt = 0; rt < rows; rt += 32) {
     acc_t acc[2];
     int eoff[2];
@@ -241,16 +254,18 @@ __global__ __launch_bounds__(256) void eval_box(const T* __restrict__ psi,
     for (int h = 0; h < 2; h++) {
       zero4(acc[h]);
       const int row = rt + 16 * h + lr;
-      const int ls = (int)__umulhi((uint32_t)row, pmagic);  // row / p
+      const int ls = (int)__umulhi((uint32_t)row, pmagic);
       ok[h] = row < rows;
-      eoff[h] = ok[h] ? (leaf_tab[(s0 + ls) * D + (D - 1)] * p + (row - ls * p)) * nr : 0;
+      eoff[h] = ok[h] ? (tnext[h] * p + (row - ls * p)) * nr : 0;
     }
+    tnext[0] = tab_of(rt + 32 + lr);
+    tnext[1] = tab_of(rt + 48 + lr);
 #pragma unroll
     for (int q = 0; q < Q; q++) {
       const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
 #pragma unroll
       for (int h = 0; h < 2; h++) {
-        const T a = (ok[h] && k < nr) ? E[eoff[h] + k] : (T)0;
+        const T a = ld0<T>(E, eoff[h] + k, ok[h] && k < nr);
         acc[h] = M::step(a, b[q], acc[h]);
       }
     }
@@ -271,7 +286,7 @@ __global__ __launch_bounds__(256) void eval_box(const T* __restrict__ psi,
 //   u[i2][i1]   = sum_r2 E2[i2][r2] W^T[r2][i1]         (B operand chained from W^T)
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void eval3_leaf(const T* __restrict__ Z,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval3_leaf(const T* __restrict__ Z,
                                                   const int32_t* __restrict__ leaf_id,
                                                   const int32_t* __restrict__ leaf_tab,
                                                   const T* __restrict__ E, int p, int nr,
@@ -290,8 +305,8 @@ __global__ __launch_bounds__(256) void eval3_leaf(const T* __restrict__ Z,
   for (int q = 0; q < Q; q++) {
     const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
     const bool ok = lr < p && k < nr;
-    b1[q] = ok ? E1[lr * nr + k] : (T)0;  // B[r1][i1] = E1[i1][r1]
-    a2[q] = ok ? E2[lr * nr + k] : (T)0;  // A[i2][r2]
+    b1[q] = ld0<T>(E1, lr * nr + k, ok);  // B[r1][i1] = E1[i1][r1]
+    a2[q] = ld0<T>(E2, lr * nr + k, ok);  // A[i2][r2]
   }
   double* ul = u + (int64_t)leaf * p * p * p;
   for (int i3 = w; i3 < p; i3 += 4) {
@@ -304,7 +319,7 @@ __global__ __launch_bounds__(256) void eval3_leaf(const T* __restrict__ Z,
 #pragma unroll
       for (int q = 0; q < Q; q++) {
         const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);  // r1
-        const T a = (r2 < nr && k < nr) ? Zs[k * nr + r2] : (T)0;
+        const T a = ld0<T>(Zs, k * nr + r2, r2 < nr && k < nr);
         wt[ti] = M::step(a, b1[q], wt[ti]);
       }
     }
@@ -331,7 +346,7 @@ __global__ __launch_bounds__(256) void eval3_leaf(const T* __restrict__ Z,
 //   level C  u[i3][i2][i1]   += sum_j3 V3[i3][j3] U[j3][i1][i2]      (j3 spans waves: LDS)
 
 template <typename T, int KS>
-__global__ __launch_bounds__(256) void near3(const double* __restrict__ sigma,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void near3(const double* __restrict__ sigma,
                                              const int32_t* __restrict__ near_tgt,
                                              const int32_t* __restrict__ near_haspw,
                                              const int32_t* __restrict__ near_start,
@@ -352,9 +367,9 @@ __global__ __launch_bounds__(256) void near3(const double* __restrict__ sigma,
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
   const int pp = p * p;
-  acc_t tacc[4], uacc[4], oacc[4];
+  acc_t tacc[KS], uacc[KS], oacc[KS];  // tile c <-> j3 (or i2) = w + 4c
 #pragma unroll
-  for (int c = 0; c < 4; c++) {
+  for (int c = 0; c < KS; c++) {
     zero4(tacc[c]);
     zero4(uacc[c]);
     zero4(oacc[c]);
@@ -367,20 +382,22 @@ __global__ __launch_bounds__(256) void near3(const double* __restrict__ sigma,
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
       const int k = M::kidx(kk, lk);
-      b2[kk] = (lr < p && k < p) ? V2[lr * p + k] : (T)0;  // B[j2][i2] = V2[i2][j2]
+      b2[kk] = ld0<T>(V2, lr * p + k, lr < p && k < p);  // B[j2][i2] = V2[i2][j2]
     }
+    T av[KS][S];
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
+    for (int c = 0; c < KS; c++) {
       const int j3 = w + 4 * c;
-      if (j3 < p) {
 #pragma unroll
-        for (int kk = 0; kk < S; kk++) {
-          const int k = M::kidx(kk, lk);
-          const T a = (lr < p && k < p) ? (T)sg[(j3 * p + k) * p + lr] : (T)0;  // A[j1][j2]
-          tacc[c] = M::step(a, b2[kk], tacc[c]);
-        }
+      for (int kk = 0; kk < S; kk++) {
+        const int k = M::kidx(kk, lk);
+        av[c][kk] = ld0<T>(sg, (j3 * p + k) * p + lr, j3 < p && lr < p && k < p);  // A[j1][j2]
       }
     }
+#pragma unroll
+    for (int c = 0; c < KS; c++)
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) tacc[c] = M::step(av[c][kk], b2[kk], tacc[c]);
     const bool last = q + 1 == q1;
     const bool end1 = last || near_tab[q * 3 + 5] != t3 || near_tab[q * 3 + 3] != t1;
     const bool end3 = last || near_tab[q * 3 + 5] != t3;
@@ -390,21 +407,19 @@ __global__ __launch_bounds__(256) void near3(const double* __restrict__ sigma,
 #pragma unroll
       for (int kk = 0; kk < S; kk++) {
         const int k = M::kidx(kk, lk);
-        a1[kk] = (lr < p && k < p) ? V1[lr * p + k] : (T)0;  // A[i1][j1]
+        a1[kk] = ld0<T>(V1, lr * p + k, lr < p && k < p);  // A[i1][j1]
       }
 #pragma unroll
-      for (int c = 0; c < 4; c++) {
-        if (w + 4 * c < p) {
+      for (int c = 0; c < KS; c++) {
 #pragma unroll
-          for (int kk = 0; kk < S; kk++) uacc[c] = M::step(a1[kk], tacc[c][kk], uacc[c]);
-        }
+        for (int kk = 0; kk < S; kk++) uacc[c] = M::step(a1[kk], tacc[c][kk], uacc[c]);
         zero4(tacc[c]);
       }
     }
     if (end3) {
       __syncthreads();  // previous readers of Us are done
 #pragma unroll
-      for (int c = 0; c < 4; c++) {
+      for (int c = 0; c < KS; c++) {
         const int j3 = w + 4 * c;
         if (j3 < p) {
 #pragma unroll
@@ -418,34 +433,39 @@ __global__ __launch_bounds__(256) void near3(const double* __restrict__ sigma,
 #pragma unroll
       for (int kk = 0; kk < S; kk++) {
         const int k = M::kidx(kk, lk);
-        a3[kk] = (lr < p && k < p) ? V3[lr * p + k] : (T)0;  // A[i3][j3]
+        a3[kk] = ld0<T>(V3, lr * p + k, lr < p && k < p);  // A[i3][j3]
       }
 #pragma unroll
-      for (int c = 0; c < 4; c++) {
-        const int i2 = w + 4 * c;  // column tile (i2, i1 = lr)
-        if (i2 < p) {
+      for (int c = 0; c < KS; c++) {
+        const int i2 = w + 4 * c;  // column tile (i2, i1 = lr); rows i2 >= p are never stored
 #pragma unroll
-          for (int kk = 0; kk < S; kk++) {
-            const int j3 = M::kidx(kk, lk);
-            const T b = j3 < p ? Us[j3 * US + i2 * RS + lr] : (T)0;
-            oacc[c] = M::step(a3[kk], b, oacc[c]);
-          }
+        for (int kk = 0; kk < S; kk++) {
+          const int j3 = M::kidx(kk, lk);
+          const T uv = Us[j3 < p && i2 < p ? j3 * US + i2 * RS + lr : 0];  // LDS: select, no branch
+          const T b = j3 < p ? uv : (T)0;
+          oacc[c] = M::step(a3[kk], b, oacc[c]);
         }
       }
     }
   }
   double* ut = u + (int64_t)Tleaf * pp * p;
+  double prev[KS][4];
 #pragma unroll
-  for (int c = 0; c < 4; c++) {
+  for (int c = 0; c < KS; c++)
+#pragma unroll
+    for (int tt = 0; tt < 4; tt++) {
+      const int i2 = w + 4 * c, i3 = M::row(lk, tt);
+      const bool ok = add && i2 < p && lr < p && i3 < p;
+      prev[c][tt] = ld0<double>(ut, ((int64_t)i3 * p + i2) * p + lr, ok);
+    }
+#pragma unroll
+  for (int c = 0; c < KS; c++) {
     const int i2 = w + 4 * c;
     if (i2 < p && lr < p) {
 #pragma unroll
       for (int tt = 0; tt < 4; tt++) {
         const int i3 = M::row(lk, tt);
-        if (i3 < p) {
-          const int64_t o = ((int64_t)i3 * p + i2) * p + lr;
-          ut[o] = add ? ut[o] + (double)oacc[c][tt] : (double)oacc[c][tt];
-        }
+        if (i3 < p) ut[((int64_t)i3 * p + i2) * p + lr] = prev[c][tt] + (double)oacc[c][tt];
       }
     }
   }
@@ -484,11 +504,11 @@ __global__ __launch_bounds__(256) void form2_box(const double* __restrict__ sigm
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
       const int k = M::kidx(kk, lk);
-      av[kk] = (lr < p && k < p) ? (T)sg[lr * p + k] : (T)0;
+      av[kk] = ld0<T>(sg, lr * p + k, lr < p && k < p);
 #pragma unroll
       for (int ti = 0; ti < NT; ti++) {
         const int r = 16 * ti + lr;
-        a2[ti][kk] = (r < nr && k < p) ? F2[r * p + k] : (T)0;
+        a2[ti][kk] = ld0<T>(F2, r * p + k, r < nr && k < p);
       }
     }
 #pragma unroll
@@ -501,7 +521,7 @@ __global__ __launch_bounds__(256) void form2_box(const double* __restrict__ sigm
 #pragma unroll
         for (int kk = 0; kk < S; kk++) {
           const int k = M::kidx(kk, lk), r = 16 * tj + lr;
-          const T b = (r < nr && k < p) ? F1[r * p + k] : (T)0;
+          const T b = ld0<T>(F1, r * p + k, r < nr && k < p);
           x = M::step(av[kk], b, x);
         }
         // phi[r2][r1] += sum_j2 F2[r2][j2] X[j2][r1]
@@ -554,11 +574,11 @@ __global__ __launch_bounds__(256) void eval2_leaf(const T* __restrict__ psi,
 #pragma unroll
   for (int q = 0; q < Q; q++) {
     const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
-    const T b = (lr < p && k < nr) ? E1[lr * nr + k] : (T)0;
+    const T b = ld0<T>(E1, lr * nr + k, lr < p && k < nr);
 #pragma unroll
     for (int ti = 0; ti < NT; ti++) {
       const int r2 = 16 * ti + lr;
-      const T a = (r2 < nr && k < nr) ? P[r2 * nr + k] : (T)0;
+      const T a = ld0<T>(P, r2 * nr + k, r2 < nr && k < nr);
       wt[ti] = M::step(a, b, wt[ti]);
     }
   }
@@ -570,7 +590,7 @@ __global__ __launch_bounds__(256) void eval2_leaf(const T* __restrict__ psi,
 #pragma unroll
     for (int kk = 0; kk < 4; kk++) {
       const int k = 16 * ti + M::kidx(kk, lk);
-      const T a = (lr < p && k < nr) ? E2[lr * nr + k] : (T)0;
+      const T a = ld0<T>(E2, lr * nr + k, lr < p && k < nr);
       uu = M::step(a, wt[ti][kk], uu);
     }
   double* ul = u + (int64_t)leaf_id[s] * p * p;
@@ -611,8 +631,8 @@ __global__ __launch_bounds__(256) void near2(const double* __restrict__ sigma,
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
       const int k = M::kidx(kk, lk);
-      const T a = (lr < p && k < p) ? (T)sg[lr * p + k] : (T)0;
-      const T b = (lr < p && k < p) ? V1[lr * p + k] : (T)0;
+      const T a = ld0<T>(sg, lr * p + k, lr < p && k < p);
+      const T b = ld0<T>(V1, lr * p + k, lr < p && k < p);
       tacc = M::step(a, b, tacc);  // T[j2][i1]
     }
     if (q + 1 == q1 || near_tab[q * 2 + 3] != t2) {
@@ -620,7 +640,7 @@ __global__ __launch_bounds__(256) void near2(const double* __restrict__ sigma,
 #pragma unroll
       for (int kk = 0; kk < S; kk++) {
         const int k = M::kidx(kk, lk);
-        const T a = (lr < p && k < p) ? V2[lr * p + k] : (T)0;
+        const T a = ld0<T>(V2, lr * p + k, lr < p && k < p);
         oacc = M::step(a, tacc[kk], oacc);  // u[i2][i1] += V2[i2][j2] T[j2][i1]
       }
       zero4(tacc);

@@ -46,6 +46,16 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   return x * per + (x < rem ? x : rem) + local;
 }
 
+// Masked load without a branch: the load always reads an in-bounds element
+// (index 0 when masked off) and the value is selected afterwards, so the
+// compiler can issue many such loads back to back instead of guarding each
+// one with a branch and a wait.  base[0] must be valid.
+template <typename T, typename S>
+__device__ __forceinline__ T ld0(const S* __restrict__ base, int64_t idx, bool ok) {
+  const S v = base[ok ? idx : 0];
+  return ok ? (T)v : (T)0;
+}
+
 template <typename A> __device__ __forceinline__ void zero4(A& a) {
   a[0] = 0;
   a[1] = 0;
