@@ -130,3 +130,42 @@ def test_errors_surface():
     cs = np.array([[1, 0], [0, 1], [1, 1], [0, 0], [1, 0], [0, 1], [1, 1], [1, 1]], dtype=np.int32)
     with pytest.raises(api.FgtError):
         api.Plan(lv, cs, 4, 1e-3, 1e-6)
+
+
+# ---------------------------------------------------------------------------
+# full size: the benchmark's 3D adaptive tree (2,661 leaves, N = 10,899,456),
+# the launch configuration bench.py times, checked on a deterministic sample of
+# target leaves that the oracle computes one by one (shallowest and deepest
+# leaves included).
+
+_FULL = {}
+
+
+def _full(periodic):
+    if periodic not in _FULL:
+        _FULL[periodic] = synth.adaptive_3d(0, periodic=periodic, wrap_blobs=periodic)
+    return _FULL[periodic]
+
+
+def _sample(lv, n=48, seed=3):
+    rng = np.random.default_rng(seed)
+    pick = set(rng.choice(len(lv), n, replace=False).tolist())
+    pick.add(int(np.argmin(lv)))
+    pick.add(int(np.argmax(lv)))
+    return np.array(sorted(pick), dtype=np.int64)
+
+
+@pytest.mark.parametrize("periodic,tol,precision", [(False, 1e-6, "fp64"), (False, 1e-10, "fp64"),
+                                                     (False, 1e-6, "fp32"), (True, 1e-6, "fp64"),
+                                                     (True, 1e-10, "fp64")])
+def test_full_size_3d_sampled(periodic, tol, precision):
+    pr = _full(periodic)
+    tg = _sample(pr.levels)
+    _say(f"full-size periodic={periodic} tol={tol} {precision}: N={pr.npoints} sample={len(tg)} leaves")
+    uo = oracle.oracle_u(pr.levels, pr.coords, pr.p, pr.delta, pr.sigma, periodic=periodic, targets=tg)
+    ug, pl = _run(pr.levels, pr.coords, pr.p, pr.delta, tol, pr.sigma, periodic=periodic,
+                  precision=precision)
+    err = cf.rel_l2(ug[tg], uo)
+    _say(f"full-size: lc={pl.info()['lc']} nr={pl.info()['nr']} rel_l2={err:.3e}")
+    assert np.all(np.isfinite(ug))
+    assert err < tol

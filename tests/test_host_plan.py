@@ -1,0 +1,326 @@
+"""CPU tests of the host side of the C ABI: parameters, tables and lists.
+
+No device is touched: plans are built with host_only=1 and inspected through
+fgt_plan_array.  Expected values come from the paper's Tables 1 and 2
+(tests/golden), from the paper's closed forms for the Gaussian-Legendre
+integrals, from independent scipy quadrature, and from the oracle.
+"""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+from scipy import integrate
+from scipy.special import erf
+
+import closed_forms as cf
+import host_exec
+import oracle
+from paper_2305_07165_amd import _lib, api, synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(HERE, "golden", name)) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([float(v) for v in line.split()])
+    return rows
+
+
+def _plan(lv, cs, p, delta, tol, **kw):
+    return api.Plan(lv, cs, p, delta, tol, host_only=True, **kw)
+
+
+# ---------------------------------------------------------------------------
+# the library and its declared symbols
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "fgt.h")).read()
+    declared = set(re.findall(r"\b(fgt_[a-z_]+)\s*\(", header))
+    declared -= {"fgt_tree", "fgt_opts", "fgt_info"}
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert declared == set(_lib.EXPORTED)
+
+
+# ---------------------------------------------------------------------------
+# Theorem 1 and Tables 1-2
+
+
+def test_table1_plane_wave_counts():
+    for eps, d0, n2, n3, n4 in _golden("table1.txt"):
+        assert round(math.sqrt(math.log(3.0 / eps)), 2) == pytest.approx(d0, abs=1e-9)
+        assert [api.fgt_pw_terms(eps, r) for r in (2.0, 3.0, 4.0)] == [n2, n3, n4]
+
+
+def test_table2_periodic_terms():
+    epss = [1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12]
+    for row in _golden("table2.txt"):
+        delta, counts = row[0], row[1:]
+        assert [api.fgt_periodic_terms(e, delta) for e in epss] == counts
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-10])
+@pytest.mark.parametrize("delta", [1e-3, 3e-4, 1e-4])
+def test_theorem1_bound_with_plan_modes(tol, delta):
+    """The plan's modes (symmetric truncation |m| <= M-1, real form) keep the
+    Theorem 1 bound |G(x) - PW(x)| <= eps for |x| <= R sqrt(delta)."""
+    lv, cs = synth.uniform_tree(2, 5)
+    info = _plan(lv, cs, 4, delta, tol).info()
+    eps, h, R, M = info["eps"], info["h"], info["R"], (info["nr"] + 1) // 2
+    assert info["nf"] == 2 * M
+    x = np.linspace(-R, R, 20001)  # units of sqrt(delta)
+    m = np.arange(1, M)
+    w0 = h / (2 * math.sqrt(math.pi))
+    pw = w0 + 2 * w0 * np.sum(np.exp(-(m[:, None] * h) ** 2 / 4) * np.cos(np.outer(m * h, x)), 0)
+    err = np.max(np.abs(np.exp(-x * x) - pw))
+    assert err <= eps
+    # cutoff level: boxes of side >= D0 sqrt(delta), the finest such level
+    L = 2.0 ** -info["lc"]
+    assert L >= info["D0"] * math.sqrt(delta) > L / 2
+    assert 2 * info["D0"] <= R < 4 * info["D0"] + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# near-field tables
+
+
+def _paper_J(nmax, t, lam):
+    """J^paper_n(t), n < nmax, from the closed forms for n <= 3 and the
+    five-term recurrence (Eq. (Jnrecurrence)), with the factor lambda that the
+    printed closed forms omit restored by the caller (J = lambda * J^paper)."""
+    a, b = (-1 - t) / lam, (1 - t) / lam
+    d1 = lam * (math.exp(-b * b) - math.exp(-a * a))
+    d2 = lam * (math.exp(-b * b) + math.exp(-a * a))
+    J = [0.0] * max(nmax, 4)
+    J[0] = 0.5 * math.sqrt(math.pi) * (erf(b) - erf(a))
+    J[1] = -0.5 * d1 + t * J[0]
+    J[2] = 0.75 * (-d2 - t * d1 + (lam ** 2 - 2.0 / 3 + 2 * t * t) * J[0])
+    J[3] = 0.625 * (-d1 + 2 * t * (4 * J[2] - J[0]) / 3 - (0.4 - 4 * lam ** 2) * J[1])
+    for n in range(2, nmax - 2):
+        J[n + 2] = ((2 * n + 3) / (n + 2)) * (
+            t * (J[n + 1] - J[n - 1]) + (n - 1) / (2 * n - 1) * J[n - 2]
+            + (2 * n + 1) * (lam ** 2 / 2 + 1.0 / ((2 * n + 3) * (2 * n - 1))) * J[n])
+    return np.array(J[:nmax])
+
+
+_REL = {0: -1.0, 1: 0.0, 2: 1.0, 3: -0.75, 4: -0.25, 5: 0.25, 6: 0.75,
+        7: -1.5, 8: -0.5, 9: 0.5, 10: 1.5}
+
+
+def _near_tables(p, delta, lv, cs):
+    pl = _plan(lv, cs, p, delta, 1e-10)
+    V = pl.array("V").reshape(-1, p, p)
+    meta = pl.array("vtab_meta").reshape(2, -1)
+    return V, meta
+
+
+def test_near_tables_match_paper_closed_forms():
+    """sum_j V[i][j] P_n(eta_j) = (L/2) lambda J^paper_n(t_i) with
+    lambda = 2 sqrt(delta)/L (the garbled lambda = 2 delta/L read as
+    2 sqrt(delta)/L, and the printed closed forms multiplied by lambda)."""
+    p, delta = 8, 1e-6
+    lv, cs = synth.point_refined_tree(2, [0.3, -0.2], 3)  # leaves at levels 1..3, all direct
+    V, meta = _near_tables(p, delta, lv, cs)
+    eta = npleg.leggauss(p)[0]
+    Pn = np.stack([npleg.legval(eta, np.eye(p)[n]) for n in range(p)], 1)  # [j][n]
+    checked = 0
+    for tid in range(V.shape[0]):
+        lev, ty = int(meta[0, tid]), int(meta[1, tid])
+        LS = 2.0 ** -lev
+        LT = LS if ty < 3 else (LS / 2 if ty < 7 else 2 * LS)
+        lam = 2 * math.sqrt(delta) / LS
+        if lam > 1.0 / 16:
+            continue  # the recurrence is only stable for small lambda
+        tpot = V[tid] @ Pn
+        for i in range(p):
+            xi = _REL[ty] * LS + 0.5 * LT * eta[i]
+            ref = 0.5 * LS * lam * _paper_J(p, 2 * xi / LS, lam)
+            assert np.max(np.abs(tpot[i] - ref)) < 1e-14 * math.sqrt(math.pi * delta)
+        checked += 1
+    assert checked >= 5
+
+
+def test_near_tables_match_quadrature():
+    p, delta = 6, 2e-3
+    lv, cs = synth.point_refined_tree(2, [0.1, 0.1], 3)
+    V, meta = _near_tables(p, delta, lv, cs)
+    eta = npleg.leggauss(p)[0]
+
+    def lagrange(j, t):
+        return np.prod([(t - eta[m]) / (eta[j] - eta[m]) for m in range(p) if m != j])
+
+    for tid in range(V.shape[0]):
+        lev, ty = int(meta[0, tid]), int(meta[1, tid])
+        LS = 2.0 ** -lev
+        LT = LS if ty < 3 else (LS / 2 if ty < 7 else 2 * LS)
+        for i in (0, p // 2, p - 1):
+            xi = _REL[ty] * LS + 0.5 * LT * eta[i]
+            for j in (0, p - 1):
+                ref, _ = integrate.quad(
+                    lambda y: math.exp(-(xi - y) ** 2 / delta) * lagrange(j, 2 * y / LS),
+                    -LS / 2, LS / 2, points=[min(max(xi, -LS / 2), LS / 2)],
+                    epsabs=1e-15, epsrel=1e-13, limit=200)
+                assert abs(V[tid, i, j] - ref) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# formation / evaluation tables and the rotations
+
+
+def test_form_eval_tables_reproduce_the_1d_kernel():
+    """E_T F_S (same cutoff box) and E_T' Rot F_S (colleague box) give the 1D
+    integral int_S G(x_i - y) l_j(y) dy to the plane-wave tolerance."""
+    p, delta, tol = 8, 1e-3, 1e-8
+    lv, cs = synth.uniform_tree(1, 4)  # 1D, level-4 leaves
+    pl = _plan(lv, cs, p, delta, tol, force_lc=2)
+    info = pl.info()
+    nr, M = info["nr"], (info["nr"] + 1) // 2
+    F = pl.array("F").reshape(-1, nr, p)
+    E = pl.array("E").reshape(-1, p, nr)
+    rot = pl.array("rot").reshape(M, 2)
+    meta = pl.array("ftab_meta").reshape(2, -1)
+    tid = {(int(meta[0, k]), int(meta[1, k])): k for k in range(meta.shape[1])}
+    eta = npleg.leggauss(p)[0]
+    L, Lc = 2.0 ** -4, 2.0 ** -2
+    Vinv = np.linalg.inv(npleg.legvander(eta, p - 1))
+
+    def exact(xt, pos_s, box_shift):
+        cS = -Lc / 2 + L * (pos_s + 0.5)  # relative to its cutoff box center
+        out = np.zeros((p, p))
+        for j in range(p):
+            coef = Vinv[:, j]
+            for i in range(p):
+                val, _ = integrate.quad(
+                    lambda y: math.exp(-(xt[i] - y) ** 2 / delta)
+                    * npleg.legval(2 * (y - cS) / L, coef),
+                    cS - L / 2, cS + L / 2, epsabs=1e-15, epsrel=1e-13)
+                out[i, j] = val
+        return out
+
+    def R(dir_):
+        Rm = np.eye(nr)
+        for m in range(1, M):
+            c, s = rot[m]
+            s *= dir_
+            Rm[2 * m - 1:2 * m + 1, 2 * m - 1:2 * m + 1] = [[c, -s], [s, c]]
+        return Rm
+
+    for pos_s, pos_t in ((0, 1), (3, 0), (2, 2)):
+        FS, ET = F[tid[(4, pos_s)]], E[tid[(4, pos_t)]]
+        xt = -Lc / 2 + L * (pos_t + 0.5) + 0.5 * L * eta  # target nodes, same box
+        assert np.max(np.abs(ET @ FS - exact(xt, pos_s, 0))) < 10 * info["eps"]
+        # target in the colleague box to the right: psi_A' = Rot(c_A - c_A') phi_A,
+        # dir = A - A' = -1 along the axis
+        assert np.max(np.abs(ET @ R(-1) @ FS - exact(xt + Lc, pos_s, 0))) < 10 * info["eps"]
+
+
+# ---------------------------------------------------------------------------
+# validation
+
+
+def _code(fn):
+    with pytest.raises(api.FgtError) as ei:
+        fn()
+    return ei.value.code
+
+
+def test_validation_errors():
+    lv, cs = synth.uniform_tree(2, 2)
+    ok = dict(p=4, delta=1e-3, tol=1e-6)
+    mk = lambda lv_, cs_, **kw: _plan(lv_, cs_, kw.pop("p", 4), kw.pop("delta", 1e-3),
+                                      kw.pop("tol", 1e-6), **kw)
+    assert _code(lambda: mk(lv, cs, tol=0.1)) == _lib.FGT_ERR_INVALID_ARG
+    assert _code(lambda: mk(lv, cs, p=0)) == _lib.FGT_ERR_INVALID_ARG
+    assert _code(lambda: mk(lv, cs, p=17)) == _lib.FGT_ERR_INVALID_ARG
+    assert _code(lambda: mk(lv, cs, delta=0.0)) == _lib.FGT_ERR_INVALID_ARG
+    assert _code(lambda: mk(lv, cs, force_lc=9)) == _lib.FGT_ERR_INVALID_ARG
+    # gap: drop a leaf
+    assert _code(lambda: mk(lv[1:], cs[1:])) == _lib.FGT_ERR_NOT_TILING
+    # duplicate
+    assert _code(lambda: mk(np.r_[lv, lv[:1]], np.r_[cs, cs[:1]])) == _lib.FGT_ERR_NOT_TILING
+    # overlap: a leaf and its parent
+    lv2 = np.r_[lv, [1]].astype(np.int32)
+    cs2 = np.r_[cs, [[0, 0]]].astype(np.int32)
+    assert _code(lambda: mk(lv2, cs2)) == _lib.FGT_ERR_NOT_TILING
+    # out of range coordinate
+    cs3 = cs.copy()
+    cs3[0, 0] = 4
+    assert _code(lambda: mk(lv, cs3)) == _lib.FGT_ERR_NOT_TILING
+    # unbalanced: level-3 leaf (3,3) shares the corner (0,0) with the level-1 leaf (1,1)
+    lvu = [1, 1, 1] + [2] * 3 + [3] * 4
+    csu = [[1, 0], [0, 1], [1, 1], [0, 0], [1, 0], [0, 1], [2, 2], [3, 2], [2, 3], [3, 3]]
+    assert _code(lambda: mk(np.array(lvu, np.int32), np.array(csu, np.int32))) == _lib.FGT_ERR_NOT_BALANCED
+    # periodic with a cutoff level <= 1 (large delta) is not implemented
+    assert _code(lambda: mk(lv, cs, delta=0.05, periodic=True)) == _lib.FGT_ERR_UNSUPPORTED
+    # a valid plan works
+    assert mk(lv, cs).info()["nleaves"] == 16
+    assert ok
+
+
+# ---------------------------------------------------------------------------
+# f-flags, P-lists and D-lists on a hand-drawn tree
+
+
+def test_fflags_plists_dlists_small_tree():
+    # uniform level-2 2D tree with box (1,1) refined to level 3, cutoff forced to 2
+    lv, cs = synth.uniform_tree(2, 2)
+    keep = ~((cs[:, 0] == 1) & (cs[:, 1] == 1))
+    kids = np.array([[2, 2], [3, 2], [2, 3], [3, 3]], dtype=np.int32)
+    lv = np.r_[lv[keep], [3] * 4].astype(np.int32)
+    cs = np.r_[cs[keep], kids].astype(np.int32)
+    pl = _plan(lv, cs, 4, 1e-3, 1e-6, force_lc=2)
+    isleaf = pl.array("pwbox_isleaf")
+    # f = 1: the refined box and its 8 colleagues (all interior neighbors of (1,1))
+    assert len(isleaf) == 9 and isleaf.sum() == 8
+    st, src = pl.array("plist_start"), pl.array("plist_src")
+    nonleaf = int(np.where(isleaf == 0)[0][0])
+    for a in range(9):
+        got = set(src[st[a]:st[a + 1]].tolist())
+        if a == nonleaf:
+            assert got == set(range(9))      # every colleague with f = 1, itself included
+        else:
+            assert got == {nonleaf}          # leaf-leaf pairs are direct
+    # leaves at level 3 have no near list; the 15 level-2 leaves gather directly
+    tg = pl.array("near_tgt")
+    assert sorted(lv[tg].tolist()) == [2] * 15
+    assert pl.array("near_haspw").sum() == 8
+    # every PW leaf maps to exactly one box
+    assert len(pl.array("pwleaf_id")) == 8 + 4
+
+
+# ---------------------------------------------------------------------------
+# the host plan, walked in numpy, against the oracle
+
+
+@pytest.mark.parametrize("case", ["2d-pw", "2d-adaptive", "2d-periodic", "3d"])
+def test_host_plan_matches_oracle(case):
+    if case == "2d-pw":
+        pr = synth.small_2d(0)
+        lv, cs, sig, p, delta, tol, per, flc = pr.levels, pr.coords, pr.sigma, 8, 1e-3, 1e-6, False, 2
+    elif case in ("2d-adaptive", "2d-periodic"):
+        per = case == "2d-periodic"
+        c = [[0.46, -0.17], [-0.2, 0.49]] if per else [[0.11, -0.17], [-0.2, 0.05]]
+        dens = synth.GaussianSum(np.array(c), np.array([0.01, 0.03]), np.array([0.7, -0.4]),
+                                 periodic=per)
+        lv, cs = synth.resolve_tree(dens, 2, 8, 1e-10, max_level=7, periodic=per)
+        sig = synth.sample(lv, cs, 8, dens)
+        p, delta, tol, flc = 8, 1e-4, 1e-10, -1
+    else:
+        dens = synth.GaussianSum(np.array([[0.1, -0.12, 0.05]]), np.array([0.03]), np.array([1.0]))
+        lv, cs = synth.resolve_tree(dens, 3, 5, 1e-7, max_level=4)
+        sig = synth.sample(lv, cs, 5, dens)
+        p, delta, tol, per, flc = 5, 1e-3, 1e-6, False, -1
+    uo = oracle.oracle_u(lv, cs, p, delta, sig, periodic=per)
+    uh = host_exec.run(_plan(lv, cs, p, delta, tol, periodic=per, force_lc=flc), sig)
+    assert cf.rel_l2(uh, uo) < tol
