@@ -45,6 +45,11 @@ def build(verbose: bool = True) -> str:
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
+    # roofline ceilings probe (matrix cores, vector FMA, copy), a separate program
+    exe = os.path.join(HERE, "fgt_ceilings")
+    _run([HIPCC, "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+          "-packed-fp32-ops", "-o", exe + ".tmp", os.path.join(CSRC, "ceilings.hip")])
+    os.replace(exe + ".tmp", exe)
     return LIB
 
 
