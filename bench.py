@@ -106,6 +106,50 @@ def pct(sorted_ms, q):
     return sorted_ms[i]
 
 
+def served_form(seed, nreq, log):
+    """The serving workload: a pool of request types (d ~ U{2,3}, N log-uniform
+    in [1e4, 1e8], delta log-uniform in [1e-6, 1e-2], tol ~ U{1e-3, 1e-6,
+    1e-10}, p ~ U{8, 16}), requests drawn uniformly from the pool.  Reports
+    sequential plain execution, the server's closed-loop capacity, and Poisson
+    arrivals at 30/60/90% of that capacity (latency arrival -> done)."""
+    import numpy as np
+
+    from paper_2305_07165_amd import api, serving, synth
+
+    t0 = time.perf_counter()
+    types = synth.serve_request_types(seed, 12)
+    log(f"served: {len(types)} request types, {sum(t.npoints for t in types)} points in all, "
+        f"generated in {time.perf_counter() - t0:.1f}s")
+    pool = serving.Pool(types)
+    rng = np.random.default_rng(seed + 1)
+    kinds = rng.integers(0, len(types), nreq)
+    out = {"pool": [{"d": t.d, "p": t.p, "npoints": t.npoints, "delta": t.delta, "tol": t.tol,
+                     "precision": t.precision} for t in types], "requests": int(nreq)}
+    seq_s, seq_pts = serving.sequential(pool, kinds)
+    out["sequential_points_per_s"] = seq_pts / seq_s
+    with api.Server(nslots=4, nbuilders=4) as srv:
+        tw = time.perf_counter()
+        serving.warm(srv, pool)
+        out["warm_s"] = time.perf_counter() - tw
+        cl_s, cl_pts, done = serving.closed_loop(srv, pool, kinds)
+        cap = nreq / cl_s
+        out.update({"value": cl_pts / cl_s, "unit": "grid points/s", "capacity_rps": cap,
+                    "speedup_vs_sequential": (cl_pts / cl_s) / (seq_pts / seq_s),
+                    "closed_loop_p50_ms": float(np.percentile([c["total_ms"] for c in done], 50)),
+                    "closed_loop_p99_ms": float(np.percentile([c["total_ms"] for c in done], 99))})
+        log(f"served closed loop: {cap:.1f} req/s, {cl_pts / cl_s:.3e} pts/s "
+            f"(sequential {seq_pts / seq_s:.3e} pts/s)")
+        out["poisson"] = []
+        for frac in (0.3, 0.6, 0.9):
+            r = serving.poisson(srv, pool, kinds, frac * cap, np.random.default_rng(seed + 2))
+            r["load"] = frac
+            out["poisson"].append(r)
+            log(f"served poisson {frac:.0%}: p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms "
+                f"{r['points_per_s']:.3e} pts/s")
+        out["server_stats"] = srv.stats()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +160,8 @@ def main():
     ap.add_argument("--cpu-leaves", type=int, default=1024,
                     help="target leaves in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the tol=1e-10 and FP32 lines")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served form")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps of the headline plan only (for rocprofv3)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -215,6 +261,9 @@ def main():
                            "_u": uf.cpu().numpy()}
             fp.close()
             log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
+
+    if not args.no_serve:
+        forms["served"] = served_form(args.seed + 100, args.serve_requests, log)
 
     cpu = None
     accuracy = {}

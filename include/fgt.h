@@ -82,7 +82,8 @@ typedef struct fgt_info {
   int64_t n_near_target, n_near_pair;
   double flops_form, flops_eval, flops_translate, flops_near; /* algorithmic, per execute */
   double bytes_min;      /* algorithmic minimum HBM bytes per execute */
-  int64_t device_bytes;  /* device memory held by the plan */
+  int64_t device_bytes;  /* device memory held by the plan; for a host-only plan, the
+                            bytes it would hold once on the device (an upper bound) */
 } fgt_info_t;
 
 typedef struct fgt_plan fgt_plan_t;

@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/fgt.h (argument marshalling only).
+"""ctypes declarations of the C ABI in include/fgt.h and include/fgt_serve.h
+(argument marshalling only).
 
 Every step of the transform runs in libfgt.so's HIP kernels; there is no CPU
 fallback.  If the library is missing this module raises on first use.
@@ -26,7 +27,9 @@ FGT_FP32 = 1
 
 EXPORTED = ["fgt_plan", "fgt_execute", "fgt_sync", "fgt_plan_info", "fgt_stage_times",
             "fgt_destroy", "fgt_strerror", "fgt_last_error", "fgt_pw_terms",
-            "fgt_periodic_terms", "fgt_plan_array"]
+            "fgt_periodic_terms", "fgt_plan_array",
+            "fgt_server_create", "fgt_server_submit", "fgt_server_poll", "fgt_server_wait",
+            "fgt_server_drain", "fgt_server_stats", "fgt_server_destroy"]
 
 
 class fgt_tree_t(ctypes.Structure):
@@ -56,6 +59,41 @@ class fgt_info_t(ctypes.Structure):
                 ("flops_form", ctypes.c_double), ("flops_eval", ctypes.c_double),
                 ("flops_translate", ctypes.c_double), ("flops_near", ctypes.c_double),
                 ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class fgt_server_opts_t(ctypes.Structure):
+    _fields_ = [("nslots", ctypes.c_int32), ("nbuilders", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64)]
+
+
+class fgt_request_t(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_int64), ("tree", ctypes.POINTER(fgt_tree_t)),
+                ("p", ctypes.c_int32), ("delta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("bc", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("sigma", ctypes.c_void_p), ("u", ctypes.c_void_p), ("host_io", ctypes.c_int32)]
+
+
+class fgt_completion_t(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("key", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("cache_hit", ctypes.c_int32), ("npoints", ctypes.c_int64),
+                ("queue_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("device_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class fgt_server_stats_t(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("plans_built", ctypes.c_int64),
+                ("plans_uploaded", ctypes.c_int64), ("plans_evicted", ctypes.c_int64),
+                ("workspaces_added", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("peak_resident_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64),
+                ("nslots", ctypes.c_int32), ("running", ctypes.c_int32),
+                ("waiting", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -97,6 +135,22 @@ def lib():
         L.fgt_periodic_terms.argtypes = [ctypes.c_double, ctypes.c_double]
         L.fgt_plan_array.restype = ctypes.c_int64
         L.fgt_plan_array.argtypes = [vp, ctypes.c_char_p, vp, ctypes.c_int64]
+        L.fgt_server_create.restype = ctypes.c_int
+        L.fgt_server_create.argtypes = [ctypes.POINTER(fgt_server_opts_t), ctypes.POINTER(vp)]
+        L.fgt_server_submit.restype = ctypes.c_int
+        L.fgt_server_submit.argtypes = [vp, ctypes.POINTER(fgt_request_t),
+                                        ctypes.POINTER(ctypes.c_int64)]
+        for name in ("fgt_server_poll", "fgt_server_wait"):
+            f = getattr(L, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [vp, ctypes.POINTER(fgt_completion_t), ctypes.c_int32,
+                          ctypes.POINTER(ctypes.c_int32)] + ([ctypes.c_double] if name.endswith("wait") else [])
+        L.fgt_server_drain.restype = ctypes.c_int
+        L.fgt_server_drain.argtypes = [vp]
+        L.fgt_server_stats.restype = ctypes.c_int
+        L.fgt_server_stats.argtypes = [vp, ctypes.POINTER(fgt_server_stats_t)]
+        L.fgt_server_destroy.restype = ctypes.c_int
+        L.fgt_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 

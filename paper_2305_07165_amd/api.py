@@ -169,3 +169,128 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# request loop (include/fgt_serve.h)
+
+
+def fgt_server_create(nslots: int = 0, nbuilders: int = 0, hbm_budget: int = 0) -> int:
+    opts = _lib.fgt_server_opts_t(int(nslots), int(nbuilders), int(hbm_budget))
+    h = ctypes.c_void_p()
+    check(_lib.lib().fgt_server_create(ctypes.byref(opts), ctypes.byref(h)), "fgt_server_create")
+    return h.value
+
+
+def fgt_server_submit(server: int, key: int, sigma, u, p: int, delta: float, tol: float,
+                      bc: int = FGT_FREE, precision: int = FGT_FP64, levels=None, coords=None,
+                      host_io: bool = False) -> int:
+    """Queues one request; returns its id.  levels/coords are needed for the
+    first request of a key only."""
+    tree_p = None
+    keep = None
+    if levels is not None:
+        levels = np.ascontiguousarray(levels, dtype=np.int32)
+        coords = np.ascontiguousarray(coords, dtype=np.int32)
+        if coords.ndim != 2 or coords.shape[0] != levels.shape[0]:
+            raise ValueError("coords must be [nleaves, dim] matching levels")
+        keep = _lib.fgt_tree_t(coords.shape[1], levels.shape[0],
+                               levels.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               coords.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        tree_p = ctypes.pointer(keep)
+    req = _lib.fgt_request_t(int(key), tree_p, int(p), float(delta), float(tol), int(bc),
+                             int(precision), ctypes.c_void_p(_ptr(sigma) or None),
+                             ctypes.c_void_p(_ptr(u) or None), int(bool(host_io)))
+    rid = ctypes.c_int64()
+    check(_lib.lib().fgt_server_submit(server, ctypes.byref(req), ctypes.byref(rid)),
+          "fgt_server_submit")
+    return rid.value
+
+
+def fgt_server_poll(server: int, max_n: int = 256) -> list:
+    buf = (_lib.fgt_completion_t * max_n)()
+    n = ctypes.c_int32()
+    check(_lib.lib().fgt_server_poll(server, buf, max_n, ctypes.byref(n)), "fgt_server_poll")
+    return [buf[i].as_dict() for i in range(n.value)]
+
+
+def fgt_server_wait(server: int, timeout_ms: float = -1.0, max_n: int = 256) -> list:
+    buf = (_lib.fgt_completion_t * max_n)()
+    n = ctypes.c_int32()
+    check(_lib.lib().fgt_server_wait(server, buf, max_n, ctypes.byref(n), float(timeout_ms)),
+          "fgt_server_wait")
+    return [buf[i].as_dict() for i in range(n.value)]
+
+
+def fgt_server_drain(server: int) -> None:
+    check(_lib.lib().fgt_server_drain(server), "fgt_server_drain")
+
+
+def fgt_server_stats(server: int) -> dict:
+    st = _lib.fgt_server_stats_t()
+    check(_lib.lib().fgt_server_stats(server, ctypes.byref(st)), "fgt_server_stats")
+    return st.as_dict()
+
+
+def fgt_server_destroy(server: int) -> None:
+    check(_lib.lib().fgt_server_destroy(server), "fgt_server_destroy")
+
+
+class Server:
+    """Owns one request loop.  Holds a reference to every request's sigma and
+    u until its completion has been collected, so their memory stays valid."""
+
+    def __init__(self, nslots: int = 4, nbuilders: int = 2, hbm_budget: int = 0):
+        self.handle = 0
+        self.handle = fgt_server_create(nslots, nbuilders, hbm_budget)
+        self._live = {}
+
+    def submit(self, key: int, sigma, u, p: int, delta: float, tol: float,
+               periodic: bool = False, precision: str = "fp64", levels=None, coords=None,
+               host_io: bool = False) -> int:
+        rid = fgt_server_submit(self.handle, key, sigma, u, p, delta, tol,
+                                FGT_PERIODIC if periodic else FGT_FREE, _PRECISION[precision],
+                                levels, coords, host_io)
+        self._live[rid] = (sigma, u)
+        return rid
+
+    def _collect(self, done: list) -> list:
+        for c in done:
+            self._live.pop(c["id"], None)
+        return done
+
+    def poll(self) -> list:
+        return self._collect(fgt_server_poll(self.handle))
+
+    def wait(self, timeout_ms: float = -1.0) -> list:
+        return self._collect(fgt_server_wait(self.handle, timeout_ms))
+
+    def drain(self) -> list:
+        fgt_server_drain(self.handle)
+        out = []
+        while True:
+            got = self.poll()
+            if not got:
+                return out
+            out += got
+
+    def stats(self) -> dict:
+        return fgt_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            fgt_server_destroy(self.handle)
+            self.handle = 0
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -10,20 +10,7 @@
 #include "fgt_host.h"
 #include "kernels.h"
 #include "../../include/fgt.h"
-
-struct fgt_plan {
-  fgt::HostPlan hp;
-  bool host_only = true;
-  int device = -1;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  bool profile = false;
-  bool ev_ready = false;
-  hipEvent_t ev[7] = {};
-  std::vector<void*> allocs;
-  int64_t device_bytes = 0;
-  fgt::DeviceArgs args;
-};
+#include "plan_internal.h"
 
 namespace {
 
@@ -92,6 +79,34 @@ double ipowd(double b, int e) {
   for (int i = 0; i < e; i++) r *= b;
   return r;
 }
+
+}  // namespace
+
+int64_t fgt::plan_device_bytes(const HostPlan& hp) {
+  const int64_t ts = hp.precision == FGT_FP32 ? 4 : 8;
+  int64_t n2 = 1;
+  for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
+  const int64_t ncoef = n2 * hp.nr;
+  int64_t b = ts * (int64_t)(hp.F.size() + hp.E.size() + hp.V.size() + hp.rot.size());
+  for (const std::vector<int32_t>* v : {&hp.pw_start, &hp.pwleaf_id, &hp.pwleaf_tab, &hp.pwleaf_box,
+                                        &hp.box_order, &hp.plist_start, &hp.plist_src, &hp.plist_dir,
+                                        &hp.echunk, &hp.near_tgt, &hp.fitem, &hp.fred, &hp.near_haspw,
+                                        &hp.near_start, &hp.near_src, &hp.near_tab})
+    b += 4 * (int64_t)v->size();
+  return b + plan_workspace_bytes(hp);
+}
+
+int64_t fgt::plan_workspace_bytes(const HostPlan& hp) {
+  const int64_t ts = hp.precision == FGT_FP32 ? 4 : 8;
+  int64_t n2 = 1;
+  for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
+  const int64_t ncoef = n2 * hp.nr;
+  const int64_t round = 256 / ts;  // each array starts on a 256-byte boundary
+  auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
+  return ts * (up(hp.n_pwleaf() * hp.p * n2) + 2 * up(hp.n_pwbox() * ncoef) + up((int64_t)hp.nslots * ncoef));
+}
+
+namespace {
 
 int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   fgt::HostPlan& hp = pl->hp;
@@ -172,6 +187,78 @@ void release(fgt_plan_t* pl) {
 }
 
 }  // namespace
+
+int fgt::set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+int fgt::plan_upload(fgt_plan_t* pl, hipStream_t stream) {
+  if (!pl || !pl->host_only) return fail(FGT_ERR_INVALID_ARG, "plan is not host-only");
+  fgt_opts_t o{};
+  o.stream = stream;
+  const int rc = setup_device(pl, &o);
+  if (rc != FGT_OK) {
+    // leave the plan host-only, as it was
+    if (pl->ev_ready)
+      for (int i = 0; i < 7; i++) (void)hipEventDestroy(pl->ev[i]);
+    pl->ev_ready = false;
+    for (void* p : pl->allocs) (void)hipFree(p);
+    pl->allocs.clear();
+    pl->device_bytes = 0;
+    pl->args = fgt::DeviceArgs();
+    pl->stream = nullptr;
+    pl->host_only = true;
+  }
+  return rc;
+}
+
+int fgt::plan_unload(fgt_plan_t* pl) {
+  if (!pl || pl->host_only) return fail(FGT_ERR_INVALID_ARG, "plan is not resident");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (pl->ev_ready)
+    for (int i = 0; i < 7; i++) (void)hipEventDestroy(pl->ev[i]);
+  pl->ev_ready = false;
+  for (void* p : pl->allocs) (void)hipFree(p);
+  pl->allocs.clear();
+  if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
+  pl->own_stream = false;
+  pl->stream = nullptr;
+  pl->device_bytes = 0;
+  pl->args = fgt::DeviceArgs();
+  pl->host_only = true;
+  return FGT_OK;
+}
+
+int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem) {
+  if (!pl || pl->host_only || !args || !mem) return fail(FGT_ERR_INVALID_ARG, "plan is not resident");
+  const fgt::HostPlan& hp = pl->hp;
+  const int64_t ts = hp.precision == FGT_FP32 ? 4 : 8;
+  const int64_t bytes = plan_workspace_bytes(hp);
+  void* m = nullptr;
+  hipError_t e = hipMalloc(&m, (size_t)std::max<int64_t>(bytes, 256));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(FGT_ERR_OOM, "workspace") : hip_fail(e, "hipMalloc");
+  int64_t n2 = 1;
+  for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
+  const int64_t ncoef = n2 * hp.nr, round = 256 / ts;
+  auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
+  char* c = static_cast<char*>(m);
+  *args = pl->args;
+  args->Y = c;
+  c += ts * up(hp.n_pwleaf() * hp.p * n2);
+  args->phi = c;
+  c += ts * up(hp.n_pwbox() * ncoef);
+  args->psi = c;
+  c += ts * up(hp.n_pwbox() * ncoef);
+  args->partial = c;
+  *mem = m;
+  return FGT_OK;
+}
+
+int fgt::execute_args(const DeviceArgs& a, const double* sigma, double* u, hipStream_t stream) {
+  if (!sigma || !u) return fail(FGT_ERR_INVALID_ARG, "sigma or u is NULL");
+  hipError_t e = fgt::launch_transform(a, sigma, u, stream, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return FGT_OK;
+}
 
 extern "C" {
 
@@ -282,7 +369,7 @@ int fgt_plan_info(const fgt_plan_t* pl, fgt_info_t* info) {
   info->flops_near = 2.0 * hp.d * ipowd(hp.p, hp.d + 1) * hp.n_near_pair();
   const double ts = hp.precision == FGT_FP32 ? 4.0 : 8.0;
   info->bytes_min = 16.0 * hp.nleaves * pd + 4.0 * ts * ipowd(hp.nr, hp.d) * hp.n_pwbox();
-  info->device_bytes = pl->device_bytes;
+  info->device_bytes = pl->host_only ? fgt::plan_device_bytes(hp) : pl->device_bytes;
   return FGT_OK;
 }
 

@@ -346,3 +346,194 @@ def point_refined_tree(d: int, point, max_level: int, periodic: bool = False):
     lv = np.array([l for l, _ in leaves], dtype=np.int32)
     cs = np.array([c for _, c in leaves], dtype=np.int32).reshape(-1, d)
     return balance(lv, cs, periodic=periodic)
+
+
+# ----------------------------------------------------------------------------
+# trees of a requested size (serving workload)
+
+
+def _box_center_distance(levels_l: int, coords: np.ndarray, centers: np.ndarray,
+                         periodic: bool) -> np.ndarray:
+    """Euclidean distance from each box (all at one level) to its nearest
+    center; 0 for boxes that contain a center."""
+    L = 2.0 ** -levels_l
+    mid = -0.5 + (coords + 0.5) * L
+    diff = np.abs(mid[:, None, :] - centers[None, :, :])
+    if periodic:
+        diff = np.minimum(diff, 1.0 - diff)
+    gap = np.maximum(diff - 0.5 * L, 0.0)
+    return np.sqrt(np.sum(gap * gap, axis=-1)).min(axis=1)
+
+
+def graded_tree(d: int, centers, lmax: int, r0: float, periodic: bool = False):
+    """Tree graded around `centers`: a box at level l < lmax is split while
+    its distance to the nearest center is below r0 (2^(lmax-l) - 1), so the
+    leaf side grows about linearly with the distance.  With
+    r0 >= 2 sqrt(d) 2^-lmax neighboring leaves differ by at most one level;
+    the result is passed through `balance` only if it is not."""
+    centers = np.asarray(centers, dtype=np.float64).reshape(-1, d)
+    boxes = np.zeros((1, d), dtype=np.int64)
+    lv, cs = [], []
+    for l in range(lmax + 1):
+        if l == lmax:
+            split = np.zeros(len(boxes), dtype=bool)
+        else:
+            split = _box_center_distance(l, boxes, centers, periodic) < r0 * (2.0 ** (lmax - l) - 1.0)
+        keep = boxes[~split]
+        lv.append(np.full(len(keep), l, dtype=np.int32))
+        cs.append(keep)
+        par = boxes[split]
+        if len(par) == 0:
+            break
+        boxes = np.concatenate([2 * par + np.array(o, dtype=np.int64)
+                                for o in itertools.product((0, 1), repeat=d)], 0)
+    return np.concatenate(lv), np.concatenate(cs, 0).astype(np.int32)
+
+
+def sized_tree(d: int, centers, nleaves: int, periodic: bool = False):
+    """A graded tree (`graded_tree`) with about `nleaves` leaves: the finest
+    level is the smallest whose uniform tree has enough leaves, and r0 is
+    found by bisection (the leaf count grows with r0)."""
+    nleaves = max(1, int(nleaves))
+    lmax = 0
+    while 2 ** (d * lmax) < nleaves:
+        lmax += 1
+    if lmax == 0:
+        return uniform_tree(d, 0)
+    r_lo = 2.0 * math.sqrt(d) * 2.0 ** -lmax
+    lo, hi = math.log(r_lo), math.log(4.0)
+    best = None
+    for _ in range(30):
+        mid = 0.5 * (lo + hi)
+        lv, cs = graded_tree(d, centers, lmax, math.exp(mid), periodic)
+        if best is None or abs(len(lv) - nleaves) < abs(len(best[0]) - nleaves):
+            best = (lv, cs)
+        if len(lv) < nleaves:
+            lo = mid
+        else:
+            hi = mid
+        if abs(len(lv) - nleaves) <= 0.02 * nleaves:
+            break
+    return best
+
+
+def sample_separable(levels, coords, p: int, dens: GaussianSum, chunk: int = 8192) -> np.ndarray:
+    """`sample` for a free-space Gaussian sum, built from per-axis factors
+    (each blob is a product of 1D Gaussians): the same values up to rounding,
+    much faster for large trees."""
+    levels = np.asarray(levels)
+    coords = np.asarray(coords)
+    n, d = coords.shape
+    eta = gl_nodes(p)
+    out = np.empty((n, p ** d), dtype=np.float64)
+    for s in range(0, n, chunk):
+        c, L = leaf_centers(levels[s:s + chunk], coords[s:s + chunk])
+        x = c[:, :, None] + 0.5 * L[:, None, None] * eta[None, None, :]  # [m, d, p]
+        # per-axis factors f[m, axis, i, b] of every blob b
+        f = np.exp(-((x[:, :, :, None] - dens.centers.T[None, :, None, :]) ** 2)
+                   / (dens.widths[None, None, None, :] ** 2))
+        a = np.asarray(dens.amps, dtype=np.float64)
+        if d == 1:
+            acc = f[:, 0] @ a
+        elif d == 2:
+            acc = np.einsum("mib,mjb->mij", f[:, 1] * a, f[:, 0])
+        else:
+            g = (f[:, 2, :, None, :] * f[:, 1, None, :, :] * a).reshape(len(c), p * p, -1)
+            acc = np.einsum("mib,mjb->mij", g, f[:, 0])
+        out[s:s + chunk] = acc.reshape(len(c), -1)
+    return out
+
+
+@dataclasses.dataclass
+class RequestType:
+    key: int
+    d: int
+    p: int
+    delta: float
+    tol: float
+    precision: str
+    levels: np.ndarray
+    coords: np.ndarray
+    sigma: np.ndarray
+
+    @property
+    def npoints(self) -> int:
+        return int(self.sigma.size)
+
+
+def serve_request_types(seed: int, ntypes: int, log10_n=(4.0, 8.0), log10_delta=(-6.0, -2.0),
+                        tols=(1e-3, 1e-6, 1e-10), ps=(8, 16), fp32_min_tol: float = 1e-3):
+    """Request types of the serving workload: d ~ U{2,3}, grid points N with
+    log10 N ~ U[log10_n], log10 delta ~ U[log10_delta], tol ~ U{tols},
+    p ~ U{ps}; a graded tree with about N / p^d leaves around 2-16 Gaussian
+    blobs drawn as in the small 2D workload (centers U[-0.3,0.3]^d, widths
+    U[0.01,0.05], amplitudes U(-1,1)), which also give sigma.  Precision is
+    FP32 for tol >= fp32_min_tol, else FP64."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(ntypes):
+        d = int(rng.integers(2, 4))
+        n = 10.0 ** rng.uniform(*log10_n)
+        delta = float(10.0 ** rng.uniform(*log10_delta))
+        tol = float(tols[int(rng.integers(0, len(tols)))])
+        p = int(ps[int(rng.integers(0, len(ps)))])
+        nb = int(rng.integers(2, 17))
+        dens = GaussianSum(*_blobs(rng, nb, d, -0.3, 0.3, 1e-2, 5e-2, False))
+        lv, cs = sized_tree(d, dens.centers, round(n / p ** d))
+        if not is_balanced_fast(lv, cs):
+            lv, cs = balance(lv, cs)
+        out.append(RequestType(k, d, p, delta, tol, "fp32" if tol >= fp32_min_tol else "fp64",
+                               lv, cs, sample_separable(lv, cs, p, dens)))
+    return out
+
+
+def is_balanced_fast(levels, coords, periodic: bool = False) -> bool:
+    """Vectorized 2:1 check with corner adjacency, for trees that tile the box.
+    If leaves A (coarser) and B share a boundary point, B's whole face, edge
+    or corner on that contact lies in A's boundary, so the finest-grid cell
+    just outside B in that direction (at B's lower corner along the other
+    axes) lies in A.  The check therefore asks, for every leaf and each of the
+    3^d - 1 directions, that this cell lies in a leaf at most one level
+    coarser; finer neighbors are covered from their own side."""
+    levels = np.asarray(levels, dtype=np.int64)
+    coords = np.asarray(coords, dtype=np.int64)
+    n, d = coords.shape
+    lmax = int(levels.max())
+    side = 1 << lmax
+
+    def keys(lv, cs):
+        k = lv.copy()
+        for a in range(d):
+            k = k * side + cs[:, a]
+        return k
+
+    table = np.sort(keys(levels, coords))
+
+    def present(lv, cs):
+        k = keys(lv, cs)
+        i = np.minimum(np.searchsorted(table, k), len(table) - 1)
+        return table[i] == k
+
+    sh = lmax - levels
+    base = coords << sh[:, None]
+    step = (np.int64(1) << sh)[:, None]
+    for o in itertools.product((-1, 0, 1), repeat=d):
+        if not any(o):
+            continue
+        o = np.array(o, dtype=np.int64)
+        q = base + np.where(o > 0, step, np.where(o < 0, -1, 0))
+        if periodic:
+            q %= side
+            sel = np.arange(n)
+        else:
+            sel = np.nonzero(np.all((q >= 0) & (q < side), axis=1))[0]
+        found = np.zeros(len(sel), dtype=bool)
+        for dl in (-1, 0, 1):
+            ll = levels[sel] + dl
+            okl = (ll >= 0) & (ll <= lmax)
+            llc = np.clip(ll, 0, lmax)
+            cs = q[sel] >> (lmax - llc)[:, None]
+            found |= okl & present(llc, cs)
+        if not np.all(found):
+            return False
+    return True
