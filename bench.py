@@ -106,6 +106,69 @@ def pct(sorted_ms, q):
     return sorted_ms[i]
 
 
+def batched_form(probs, steps, log):
+    """The batched workload (synth.batch_problems): every transform in its own
+    precision (FP32 when tol >= 1e-6, else FP64) in one batch (a captured HIP
+    graph, schedule picked by the autotuner), against the same transforms run
+    one after another with plain fgt_execute, in their own precision and all
+    in FP64."""
+    import torch
+
+    from paper_2305_07165_amd import api
+
+    npts = sum(t.npoints for t in probs)
+    sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
+
+    def seq(prec_of):
+        plans = [api.Plan(t.levels, t.coords, t.p, t.delta, t.tol, precision=prec_of(t)) for t in probs]
+        us = [torch.empty_like(s) for s in sig]
+        for pl, s_, u_ in zip(plans, sig, us):
+            pl.execute(s_, u_)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for pl, s_, u_ in zip(plans, sig, us):
+                pl.execute(s_, u_)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        return plans, us, dt
+
+    plans64, _, dt64 = seq(lambda t: "fp64")
+    for pl in plans64:
+        pl.close()
+    del plans64
+    plans, us_seq, dtmix = seq(lambda t: t.precision)
+    log(f"batched: {len(probs)} transforms, {npts} points; sequential fp64 {1e3 * dt64:.2f} ms, "
+        f"sequential mixed {1e3 * dtmix:.2f} ms")
+    b = api.Batch(plans)
+    us = [torch.empty_like(s) for s in sig]
+    b.bind(sig, us)
+    tuned = b.tune(reps=3)
+    b.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.execute()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    same = all(torch.equal(a, c) for a, c in zip(us, us_seq))
+    info = b.info()
+    log(f"batched: {1e3 * dt:.2f} ms per batch ({npts / dt:.3e} pts/s), tuned {tuned:.2f} ms, "
+        f"{info['nclasses']} classes, {info['nlaunches']} launches, streams {info['nstreams']}, "
+        f"class-major {info['class_major']}, bitwise equal to sequential: {same}")
+    b.close()
+    for pl in plans:
+        pl.close()
+    return {"value": npts / dt, "unit": "grid points/s", "ms_per_batch": 1e3 * dt, "transforms": len(probs),
+            "npoints": npts, "sequential_fp64_ms": 1e3 * dt64, "sequential_same_precision_ms": 1e3 * dtmix,
+            "speedup_vs_sequential_fp64": dt64 / dt, "speedup_vs_sequential_same_precision": dtmix / dt,
+            "bitwise_equal_to_sequential": same, "tuned_ms": tuned,
+            "schedule": {"nstreams": info["nstreams"], "class_major": bool(info["class_major"])},
+            "nclasses": info["nclasses"], "nlaunches": info["nlaunches"],
+            "precisions": {"fp32": sum(t.precision == "fp32" for t in probs),
+                           "fp64": sum(t.precision == "fp64" for t in probs)}}
+
+
 def served_form(seed, nreq, log):
     """The serving workload: a pool of request types (d ~ U{2,3}, N log-uniform
     in [1e4, 1e8], delta log-uniform in [1e-6, 1e-2], tol ~ U{1e-3, 1e-6,
@@ -161,6 +224,8 @@ def main():
                     help="target leaves in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the tol=1e-10 and FP32 lines")
     ap.add_argument("--no-serve", action="store_true", help="skip the served form")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
+    ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps of the headline plan only (for rocprofv3)")
@@ -186,6 +251,13 @@ def main():
     t0 = time.perf_counter()
     pr = synth.adaptive_3d(args.seed)
     log(f"tree: {len(pr.levels)} leaves, N={pr.npoints}, generated in {time.perf_counter() - t0:.1f}s")
+    batch_probs = None
+    if not (args.no_forms or args.no_batch or args.profile_only):
+        # generated before the process touches the GPU (tree building forks workers)
+        t0 = time.perf_counter()
+        batch_probs = synth.batch_problems(args.seed + 200, args.batch_size,
+                                           workers=min(16, os.cpu_count() or 1))
+        log(f"batched workload: {len(batch_probs)} transforms, generated in {time.perf_counter() - t0:.1f}s")
     dev = torch.device("cuda:0")
     s = torch.from_numpy(pr.sigma).to(dev)
     u = torch.empty_like(s)
@@ -262,7 +334,10 @@ def main():
             fp.close()
             log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
 
-    if not args.no_serve:
+    if batch_probs is not None:
+        forms["batched"] = batched_form(batch_probs, 3, log)
+        del batch_probs
+    if not (args.no_forms or args.no_serve):
         forms["served"] = served_form(args.seed + 100, args.serve_requests, log)
 
     cpu = None
@@ -285,8 +360,9 @@ def main():
             return float(np.linalg.norm(a[tg] - uo) / np.linalg.norm(uo))
         accuracy["fp64_tol%g" % args.tol] = err(u_head)
         for name, f in forms.items():
-            accuracy[name] = err(f["_u"])
-            f["rel_l2_vs_oracle"] = accuracy[name]
+            if "_u" in f:
+                accuracy[name] = err(f["_u"])
+                f["rel_l2_vs_oracle"] = accuracy[name]
     for f in forms.values():
         f.pop("_u", None)
 

@@ -1,5 +1,5 @@
-"""ctypes declarations of the C ABI in include/fgt.h and include/fgt_serve.h
-(argument marshalling only).
+"""ctypes declarations of the C ABI in include/fgt.h, include/fgt_serve.h and
+include/fgt_batch.h (argument marshalling only).
 
 Every step of the transform runs in libfgt.so's HIP kernels; there is no CPU
 fallback.  If the library is missing this module raises on first use.
@@ -29,7 +29,9 @@ EXPORTED = ["fgt_plan", "fgt_execute", "fgt_sync", "fgt_plan_info", "fgt_stage_t
             "fgt_destroy", "fgt_strerror", "fgt_last_error", "fgt_pw_terms",
             "fgt_periodic_terms", "fgt_plan_array",
             "fgt_server_create", "fgt_server_submit", "fgt_server_poll", "fgt_server_wait",
-            "fgt_server_drain", "fgt_server_stats", "fgt_server_destroy"]
+            "fgt_server_drain", "fgt_server_stats", "fgt_server_destroy",
+            "fgt_batch_create", "fgt_batch_bind", "fgt_batch_execute", "fgt_batch_tune",
+            "fgt_batch_info", "fgt_batch_destroy"]
 
 
 class fgt_tree_t(ctypes.Structure):
@@ -99,6 +101,22 @@ class fgt_server_stats_t(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class fgt_batch_opts_t(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
+                ("nstreams", ctypes.c_int32), ("class_major", ctypes.c_int32)]
+
+
+class fgt_batch_info_t(ctypes.Structure):
+    _fields_ = [("njobs", ctypes.c_int64), ("npoints", ctypes.c_int64),
+                ("nclasses", ctypes.c_int32), ("nsingle", ctypes.c_int32),
+                ("nlaunches", ctypes.c_int32), ("nstreams", ctypes.c_int32),
+                ("class_major", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("tuned_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -151,6 +169,19 @@ def lib():
         L.fgt_server_stats.argtypes = [vp, ctypes.POINTER(fgt_server_stats_t)]
         L.fgt_server_destroy.restype = ctypes.c_int
         L.fgt_server_destroy.argtypes = [vp]
+        L.fgt_batch_create.restype = ctypes.c_int
+        L.fgt_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int64,
+                                       ctypes.POINTER(fgt_batch_opts_t), ctypes.POINTER(vp)]
+        L.fgt_batch_bind.restype = ctypes.c_int
+        L.fgt_batch_bind.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.fgt_batch_execute.restype = ctypes.c_int
+        L.fgt_batch_execute.argtypes = [vp]
+        L.fgt_batch_tune.restype = ctypes.c_int
+        L.fgt_batch_tune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.fgt_batch_info.restype = ctypes.c_int
+        L.fgt_batch_info.argtypes = [vp, ctypes.POINTER(fgt_batch_info_t)]
+        L.fgt_batch_destroy.restype = ctypes.c_int
+        L.fgt_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
 

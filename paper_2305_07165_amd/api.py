@@ -294,3 +294,99 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# many transforms per launch (include/fgt_batch.h)
+
+
+def fgt_batch_create(plans, stream: int = 0, use_graph: bool = True, nstreams: int = 1,
+                     class_major: bool = False) -> int:
+    handles = (ctypes.c_void_p * len(plans))(*[int(p) for p in plans])
+    opts = _lib.fgt_batch_opts_t(ctypes.c_void_p(int(stream) or None), int(bool(use_graph)),
+                                 int(nstreams), int(bool(class_major)))
+    h = ctypes.c_void_p()
+    check(_lib.lib().fgt_batch_create(handles, len(plans), ctypes.byref(opts), ctypes.byref(h)),
+          "fgt_batch_create")
+    return h.value
+
+
+def fgt_batch_bind(batch: int, sigmas, us) -> None:
+    n = len(sigmas)
+    sp = (ctypes.c_void_p * n)(*[_ptr(x) for x in sigmas])
+    up = (ctypes.c_void_p * n)(*[_ptr(x) for x in us])
+    check(_lib.lib().fgt_batch_bind(batch, sp, up), "fgt_batch_bind")
+
+
+def fgt_batch_execute(batch: int) -> None:
+    check(_lib.lib().fgt_batch_execute(batch), "fgt_batch_execute")
+
+
+def fgt_batch_tune(batch: int, reps: int = 5) -> float:
+    ms = ctypes.c_double()
+    check(_lib.lib().fgt_batch_tune(batch, int(reps), ctypes.byref(ms)), "fgt_batch_tune")
+    return ms.value
+
+
+def fgt_batch_info(batch: int) -> dict:
+    info = _lib.fgt_batch_info_t()
+    check(_lib.lib().fgt_batch_info(batch, ctypes.byref(info)), "fgt_batch_info")
+    return info.as_dict()
+
+
+def fgt_batch_destroy(batch: int) -> None:
+    check(_lib.lib().fgt_batch_destroy(batch), "fgt_batch_destroy")
+
+
+class Batch:
+    """Owns one batch over existing ``Plan`` objects (kept alive here).  By
+    default it runs on torch's current stream."""
+
+    def __init__(self, plans, stream=None, use_graph: bool = True, nstreams: int = 1,
+                 class_major: bool = False):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        self.plans = list(plans)
+        self.handle = 0
+        self.handle = fgt_batch_create([p.handle for p in self.plans], int(stream or 0),
+                                       use_graph, nstreams, class_major)
+        self._bound = None
+
+    def bind(self, sigmas, us):
+        if len(sigmas) != len(self.plans) or len(us) != len(self.plans):
+            raise ValueError("one sigma and one u per plan")
+        for pl, s_, u_ in zip(self.plans, sigmas, us):
+            expect = (pl.nleaves, pl.p ** pl.dim)
+            for t in (s_, u_):
+                if tuple(t.shape) != expect or str(t.dtype) != "torch.float64" or not t.is_cuda \
+                        or not t.is_contiguous():
+                    raise ValueError(f"sigma/u must be contiguous float64 device tensors of shape {expect}")
+        fgt_batch_bind(self.handle, sigmas, us)
+        self._bound = (list(sigmas), list(us))
+
+    def execute(self):
+        fgt_batch_execute(self.handle)
+
+    def tune(self, reps: int = 5) -> float:
+        return fgt_batch_tune(self.handle, reps)
+
+    def info(self) -> dict:
+        return fgt_batch_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            fgt_batch_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

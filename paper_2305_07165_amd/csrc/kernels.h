@@ -33,6 +33,57 @@ struct DeviceArgs {
   void* partial = nullptr;  // [nslots][nr^d] partial sums of split boxes
 };
 
+// One transform of a batch: its arguments and its sigma / u.
+struct BatchJob {
+  DeviceArgs a;
+  const double* sigma = nullptr;
+  double* u = nullptr;
+};
+
+// The device stages in launch order.
+enum Stage { kFormLeaf = 0, kFormBox, kReduce, kTranslate, kEvalBox, kEvalLeaf, kNear, kNumStages };
+
+// Transforms of one kernel class share every kernel instantiation: dimension,
+// compute precision, mode tiles per axis NT = ceil(nr/16), node steps KS.
+struct KernelClass {
+  int d = 0;
+  bool fp32 = false;
+  int nt = 0, ks = 0;
+  bool operator<(const KernelClass& o) const {
+    if (d != o.d) return d < o.d;
+    if (fp32 != o.fp32) return fp32 < o.fp32;
+    if (nt != o.nt) return nt < o.nt;
+    return ks < o.ks;
+  }
+};
+KernelClass kernel_class(const DeviceArgs& a);
+
+// Workgroups `stage` takes for one transform of d = 2 or 3 (0: the stage does
+// not run); the grids of launch_fast.
+int64_t stage_blocks(const DeviceArgs& a, int stage);
+int64_t translate_blocks(const DeviceArgs& a);
+
+// Block b of a batched launch belongs to the last job j with start[j] <= b.
+__device__ __forceinline__ int batch_job_of(const int32_t* __restrict__ start, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Launches one stage for njobs transforms of class c.  jobs, start and count
+// are device arrays: job j owns blocks [start[j], start[j] + count[j]) of a
+// grid of `grid` blocks, start[j] a multiple of 8 (blocks past count[j] exit).
+hipError_t launch_stage_batched(const KernelClass& c, int stage, const BatchJob* jobs,
+                                const int32_t* start, const int32_t* count, int njobs,
+                                int64_t grid, hipStream_t st);
+template <typename T>
+void launch_translate_batched(int d, const BatchJob* jobs, const int32_t* start,
+                              const int32_t* count, int njobs, int64_t grid, hipStream_t st);
+
 // Dynamic LDS bytes of the stages that stage data in LDS.
 size_t lds_form_leaf(int d, int p, int nr, size_t tsize);
 size_t lds_eval_leaf(int d, int p, int nr, size_t tsize);

@@ -196,17 +196,17 @@ __global__ __launch_bounds__(256) void k_form_box(const T* __restrict__ Y,
 // kernels_fast.hip) instead of [r3][r2][r1]; threads then run along m_2.
 
 template <typename T, int D, bool R2F>
-__global__ __launch_bounds__(256) void k_translate(const T* __restrict__ phi,
-                                                   const int32_t* __restrict__ plist_start,
-                                                   const int32_t* __restrict__ plist_src,
-                                                   const int32_t* __restrict__ plist_dir,
-                                                   const T* __restrict__ rot, int M, int nr,
-                                                   int nA, T* __restrict__ psi) {
+__device__ __forceinline__ void translate_body(const T* __restrict__ phi,
+                                               const int32_t* __restrict__ plist_start,
+                                               const int32_t* __restrict__ plist_src,
+                                               const int32_t* __restrict__ plist_dir,
+                                               const T* __restrict__ rot, int M, int nr, int nA,
+                                               T* __restrict__ psi, int bid) {
   // Every XCD owns a contiguous (Morton) range of nbx target boxes and walks
   // it chunk of modes by chunk of modes, so a source's slice is fetched into
   // that XCD's L2 once and reused by all its neighbors in the range.
   const int nbx = (nA + kXcds - 1) / kXcds;
-  const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+  const int xcd = bid % kXcds, local = bid / kXcds;
   const int A = xcd * nbx + local % nbx;
   const int b = (local / nbx) * blockDim.x + threadIdx.x;
   int nblk = 1;
@@ -302,6 +302,55 @@ __global__ __launch_bounds__(256) void k_translate(const T* __restrict__ phi,
     if (D > 2 && cnt[2] == 1 && ((v >> 2) & 1)) ok = false;
     if (ok) dst[off[v]] = acc[v];
   }
+}
+
+template <typename T, int D, bool R2F>
+__global__ __launch_bounds__(256) void k_translate(const T* __restrict__ phi,
+                                                   const int32_t* __restrict__ plist_start,
+                                                   const int32_t* __restrict__ plist_src,
+                                                   const int32_t* __restrict__ plist_dir,
+                                                   const T* __restrict__ rot, int M, int nr,
+                                                   int nA, T* __restrict__ psi) {
+  translate_body<T, D, R2F>(phi, plist_start, plist_src, plist_dir, rot, M, nr, nA, psi, blockIdx.x);
+}
+
+// The same stage for many transforms in one launch.  Every transform's block
+// range starts at a multiple of 8, so block b of a transform still runs on XCD
+// b % 8 and the XCD-contiguous box ranges above are kept.
+template <typename T, int D, bool R2F>
+__global__ __launch_bounds__(256) void k_translate_batched(const BatchJob* __restrict__ jobs,
+                                                           const int32_t* __restrict__ start,
+                                                           const int32_t* __restrict__ count,
+                                                           int njobs) {
+  const int j = batch_job_of(start, njobs, blockIdx.x);
+  const int bid = blockIdx.x - start[j];
+  if (bid >= count[j]) return;
+  const DeviceArgs& a = jobs[j].a;
+  translate_body<T, D, R2F>(static_cast<const T*>(a.phi), a.plist_start, a.plist_src, a.plist_dir,
+                            static_cast<const T*>(a.rot), a.M, a.nr, (int)a.nA,
+                            static_cast<T*>(const_cast<void*>(a.psi)), bid);
+}
+
+template <typename T>
+void launch_translate_batched(int d, const BatchJob* jobs, const int32_t* start,
+                              const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+  if (d == 2)
+    hipLaunchKernelGGL((k_translate_batched<T, 2, false>), dim3((unsigned)grid), dim3(256), 0, st, jobs,
+                       start, count, njobs);
+  else
+    hipLaunchKernelGGL((k_translate_batched<T, 3, true>), dim3((unsigned)grid), dim3(256), 0, st, jobs,
+                       start, count, njobs);
+}
+template void launch_translate_batched<double>(int, const BatchJob*, const int32_t*, const int32_t*,
+                                               int, int64_t, hipStream_t);
+template void launch_translate_batched<float>(int, const BatchJob*, const int32_t*, const int32_t*,
+                                              int, int64_t, hipStream_t);
+
+int64_t translate_blocks(const DeviceArgs& a) {
+  int64_t nblk = 1;
+  for (int i = 0; i < a.d; i++) nblk *= a.M;
+  const int64_t nbx = (a.nA + kXcds - 1) / kXcds;
+  return kXcds * nbx * ((nblk + 255) / 256);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,9 +752,7 @@ static hipError_t launch_all(const DeviceArgs& a, const double* sigma, double* u
 
 template <typename T>
 void launch_translate(const DeviceArgs& a, hipStream_t st) {
-  const int nblk = ipow(a.M, a.d);
-  const int64_t nbx = (a.nA + kXcds - 1) / kXcds;  // boxes per XCD (see k_translate)
-  const unsigned grid = (unsigned)(kXcds * nbx * ((nblk + 255) / 256));
+  const unsigned grid = (unsigned)translate_blocks(a);
   const T* phi = static_cast<const T*>(a.phi);
   const T* rot = static_cast<const T*>(a.rot);
   T* psi = static_cast<T*>(a.psi);

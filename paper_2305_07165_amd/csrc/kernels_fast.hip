@@ -18,6 +18,7 @@
 // d = 2 fuses formation and evaluation per box / per leaf (no intermediate).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -41,15 +42,15 @@ struct Steps {
 //   Y[r1][r2]   = sum_j1 F1[r1][j1] X^T[j1][r2]        (B operand chained from X^T)
 
 template <typename T, int NT, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void form3_leaf(const double* __restrict__ sigma,
+__device__ __forceinline__ void form3_leaf_body(const double* __restrict__ sigma,
                                                   const int32_t* __restrict__ leaf_id,
                                                   const int32_t* __restrict__ leaf_tab,
                                                   const T* __restrict__ F, int p, int nr,
-                                                  T* __restrict__ Y) {
+                                                  T* __restrict__ Y, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<T, KS>::value;
-  const int s = blockIdx.x;
+  const int s = bid;
   const int leaf = leaf_id[s];
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
@@ -110,19 +111,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
 // last-axis formation merged over the leaves of a cutoff box (a grouped GEMM)
 
 template <typename T, int D, int NT, int KS>
-__global__ __launch_bounds__(256) void form_box(const T* __restrict__ Y,
+__device__ __forceinline__ void form_box_body(const T* __restrict__ Y,
                                                 const int32_t* __restrict__ fitem,
                                                 const int32_t* __restrict__ leaf_tab,
                                                 const T* __restrict__ F, int p, int nr,
                                                 int ncoltiles, T* __restrict__ phi,
-                                                T* __restrict__ partial) {
+                                                T* __restrict__ partial, int bid) {
   // one work item (<= kFormLeaves leaves of a box) x 128 columns per workgroup;
   // every wave owns two 16-column slabs, sharing the table operand between them
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<T, KS>::value;
-  const int item = blockIdx.x / ncoltiles;
-  const int ct = blockIdx.x % ncoltiles;
+  const int item = bid / ncoltiles;
+  const int ct = bid % ncoltiles;
   const int A = fitem[4 * item], slot = fitem[4 * item + 3];
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
@@ -194,12 +195,12 @@ __global__ __launch_bounds__(256) void form_box(const T* __restrict__ Y,
 
 // phi_A = sum of the partial sums of a split box, in item order (deterministic)
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_partials(const T* __restrict__ partial,
+__device__ __forceinline__ void reduce_partials_body(const T* __restrict__ partial,
                                                        const int32_t* __restrict__ fred,
                                                        int64_t ncoef, int nchunk,
-                                                       T* __restrict__ phi) {
-  const int r = blockIdx.x / nchunk;
-  const int64_t i = (int64_t)(blockIdx.x % nchunk) * blockDim.x + threadIdx.x;
+                                                       T* __restrict__ phi, int bid) {
+  const int r = bid / nchunk;
+  const int64_t i = (int64_t)(bid % nchunk) * blockDim.x + threadIdx.x;
   if (i >= ncoef) return;
   const int A = fred[3 * r], slot0 = fred[3 * r + 1], n = fred[3 * r + 2];
   T s = 0;
@@ -214,18 +215,18 @@ __global__ __launch_bounds__(256) void reduce_partials(const T* __restrict__ par
 // visited in the order box_order (most leaves first).
 
 template <typename T, int D, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval_box(const T* __restrict__ psi,
+__device__ __forceinline__ void eval_box_body(const T* __restrict__ psi,
                                                 const int32_t* __restrict__ box_order,
                                                 const int32_t* __restrict__ pw_start,
                                                 const int32_t* __restrict__ leaf_tab,
                                                 const T* __restrict__ E, int p, int nr,
                                                 int ncoltiles, uint32_t pmagic,
-                                                T* __restrict__ Z) {
+                                                T* __restrict__ Z, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
-  const int A = box_order[blockIdx.x / ncoltiles];
-  const int ct = blockIdx.x % ncoltiles;
+  const int A = box_order[bid / ncoltiles];
+  const int ct = bid % ncoltiles;
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
   const int N2 = D == 3 ? nr * nr : nr;
@@ -286,15 +287,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
 //   u[i2][i1]   = sum_r2 E2[i2][r2] W^T[r2][i1]         (B operand chained from W^T)
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval3_leaf(const T* __restrict__ Z,
+__device__ __forceinline__ void eval3_leaf_body(const T* __restrict__ Z,
                                                   const int32_t* __restrict__ leaf_id,
                                                   const int32_t* __restrict__ leaf_tab,
                                                   const T* __restrict__ E, int p, int nr,
-                                                  double* __restrict__ u) {
+                                                  double* __restrict__ u, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
-  const int s = blockIdx.x;
+  const int s = bid;
   const int leaf = leaf_id[s];
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
@@ -346,21 +347,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
 //   level C  u[i3][i2][i1]   += sum_j3 V3[i3][j3] U[j3][i1][i2]      (j3 spans waves: LDS)
 
 template <typename T, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void near3(const double* __restrict__ sigma,
+__device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
                                              const int32_t* __restrict__ near_tgt,
                                              const int32_t* __restrict__ near_haspw,
                                              const int32_t* __restrict__ near_start,
                                              const int32_t* __restrict__ near_src,
                                              const int32_t* __restrict__ near_tab,
                                              const T* __restrict__ V, int p,
-                                             double* __restrict__ u) {
+                                             double* __restrict__ u, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<T, KS>::value;
   constexpr int RS = 17;            // padded i2 stride of the LDS tile
   constexpr int US = 16 * RS + 4;   // padded j3 stride
   __shared__ T Us[16 * US];         // U[j3][i2][i1]
-  const int t = blockIdx.x;
+  const int t = bid;
   const int Tleaf = near_tgt[t];
   const bool add = near_haspw[t] != 0;
   const int q0 = near_start[t], q1 = near_start[t + 1];
@@ -476,17 +477,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
 // Waves split the r1 tiles; every wave keeps all r2 tiles of its columns.
 
 template <typename T, int NT, int KS>
-__global__ __launch_bounds__(256) void form2_box(const double* __restrict__ sigma,
+__device__ __forceinline__ void form2_box_body(const double* __restrict__ sigma,
                                                  const int32_t* __restrict__ fitem,
                                                  const int32_t* __restrict__ leaf_id,
                                                  const int32_t* __restrict__ leaf_tab,
                                                  const T* __restrict__ F, int p, int nr,
-                                                 T* __restrict__ phi, T* __restrict__ partial) {
+                                                 T* __restrict__ phi, T* __restrict__ partial, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<T, KS>::value;
   constexpr int TW = (NT + 3) / 4;  // r1 tiles per wave
-  const int item = blockIdx.x;
+  const int item = bid;
   const int A = fitem[4 * item], slot = fitem[4 * item + 3];
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
@@ -551,17 +552,17 @@ __global__ __launch_bounds__(256) void form2_box(const double* __restrict__ sigm
 
 // d = 2: evaluation of one leaf per wave from its box's incoming expansion.
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void eval2_leaf(const T* __restrict__ psi,
+__device__ __forceinline__ void eval2_leaf_body(const T* __restrict__ psi,
                                                   const int32_t* __restrict__ leaf_box,
                                                   const int32_t* __restrict__ leaf_id,
                                                   const int32_t* __restrict__ leaf_tab,
                                                   const T* __restrict__ E, int p, int nr,
-                                                  int nleaf, double* __restrict__ u) {
+                                                  int nleaf, double* __restrict__ u, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
   const int lane = lane_of(), w = wave_of();
-  const int s = blockIdx.x * 4 + w;
+  const int s = bid * 4 + w;
   if (s >= nleaf) return;
   const int lr = lane & 15, lk = lane >> 4;
   const T* E1 = E + (int64_t)leaf_tab[s * 2 + 0] * p * nr;
@@ -604,19 +605,19 @@ __global__ __launch_bounds__(256) void eval2_leaf(const T* __restrict__ psi,
 // d = 2 near field: one target per wave; sources sorted by (V2, V1): axis 1
 // per source, axis 2 once per V2 group.
 template <typename T, int KS>
-__global__ __launch_bounds__(256) void near2(const double* __restrict__ sigma,
+__device__ __forceinline__ void near2_body(const double* __restrict__ sigma,
                                              const int32_t* __restrict__ near_tgt,
                                              const int32_t* __restrict__ near_haspw,
                                              const int32_t* __restrict__ near_start,
                                              const int32_t* __restrict__ near_src,
                                              const int32_t* __restrict__ near_tab,
                                              const T* __restrict__ V, int p, int ntgt,
-                                             double* __restrict__ u) {
+                                             double* __restrict__ u, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<T, KS>::value;
   const int lane = lane_of(), w = wave_of();
-  const int t = blockIdx.x * 4 + w;
+  const int t = bid * 4 + w;
   if (t >= ntgt) return;
   const int lr = lane & 15, lk = lane >> 4;
   const int pp = p * p;
@@ -656,6 +657,238 @@ __global__ __launch_bounds__(256) void near2(const double* __restrict__ sigma,
 }
 
 // ---------------------------------------------------------------------------
+// kernels: one transform per launch (blockIdx.x is the stage's block), and
+// many transforms of one kernel class per launch (BatchJob tables; the block
+// is found in the job's range, see batch_job_of).
+
+#define FGT_BATCH_PROLOGUE                               \
+  const int j = batch_job_of(start, njobs, blockIdx.x); \
+  const int bid = blockIdx.x - start[j];                 \
+  if (bid >= count[j]) return;                           \
+  const DeviceArgs& a = jobs[j].a;
+#define FGT_BATCH_PARAMS \
+  const BatchJob* __restrict__ jobs, const int32_t* __restrict__ start, const int32_t* __restrict__ count, int njobs
+
+template <typename T> __device__ __forceinline__ const T* cptr(const void* p) { return static_cast<const T*>(p); }
+template <typename T> __device__ __forceinline__ T* mptr(void* p) { return static_cast<T*>(p); }
+__device__ __forceinline__ int n2_of(int d, int nr) { return d == 3 ? nr * nr : nr; }
+__device__ __forceinline__ uint32_t pmagic_of(int p) { return (uint32_t)((0x100000000ull + p - 1) / p); }
+
+template <typename T, int NT, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void form3_leaf(
+    const double* __restrict__ sigma, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
+    const T* __restrict__ F, int p, int nr, T* __restrict__ Y) {
+  form3_leaf_body<T, NT, KS>(sigma, leaf_id, leaf_tab, F, p, nr, Y, blockIdx.x);
+}
+template <typename T, int NT, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void form3_leaf_b(
+    FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  form3_leaf_body<T, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr, mptr<T>(a.Y), bid);
+}
+
+template <typename T, int D, int NT, int KS>
+__global__ __launch_bounds__(256) void form_box(const T* __restrict__ Y, const int32_t* __restrict__ fitem,
+                                                const int32_t* __restrict__ leaf_tab, const T* __restrict__ F,
+                                                int p, int nr, int ncoltiles, T* __restrict__ phi,
+                                                T* __restrict__ partial) {
+  form_box_body<T, D, NT, KS>(Y, fitem, leaf_tab, F, p, nr, ncoltiles, phi, partial, blockIdx.x);
+}
+template <typename T, int D, int NT, int KS>
+__global__ __launch_bounds__(256) void form_box_b(FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  const int ncol128 = (n2_of(D, a.nr) + 127) / 128;
+  form_box_body<T, D, NT, KS>(cptr<T>(a.Y), a.fitem, a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr, ncol128,
+                              mptr<T>(a.phi), mptr<T>(a.partial), bid);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_partials(const T* __restrict__ partial, const int32_t* __restrict__ fred,
+                                                       int64_t ncoef, int nchunk, T* __restrict__ phi) {
+  reduce_partials_body<T>(partial, fred, ncoef, nchunk, phi, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_partials_b(FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  int64_t ncoef = a.nr;
+  for (int i = 1; i < a.d; i++) ncoef *= a.nr;
+  reduce_partials_body<T>(cptr<T>(a.partial), a.fred, ncoef, (int)((ncoef + 255) / 256), mptr<T>(a.phi), bid);
+}
+
+template <typename T, int D, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval_box(
+    const T* __restrict__ psi, const int32_t* __restrict__ box_order, const int32_t* __restrict__ pw_start,
+    const int32_t* __restrict__ leaf_tab, const T* __restrict__ E, int p, int nr, int ncoltiles,
+    uint32_t pmagic, T* __restrict__ Z) {
+  eval_box_body<T, D, NT>(psi, box_order, pw_start, leaf_tab, E, p, nr, ncoltiles, pmagic, Z, blockIdx.x);
+}
+template <typename T, int D, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval_box_b(
+    FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  const int ncol = (n2_of(D, a.nr) + 63) / 64;
+  eval_box_body<T, D, NT>(cptr<T>(a.psi), a.box_order, a.pw_start, a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr, ncol,
+                          pmagic_of(a.p), mptr<T>(a.Y), bid);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval3_leaf(
+    const T* __restrict__ Z, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
+    const T* __restrict__ E, int p, int nr, double* __restrict__ u) {
+  eval3_leaf_body<T, NT>(Z, leaf_id, leaf_tab, E, p, nr, u, blockIdx.x);
+}
+template <typename T, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval3_leaf_b(
+    FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  eval3_leaf_body<T, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr, jobs[j].u, bid);
+}
+
+template <typename T, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void near3(
+    const double* __restrict__ sigma, const int32_t* __restrict__ near_tgt, const int32_t* __restrict__ near_haspw,
+    const int32_t* __restrict__ near_start, const int32_t* __restrict__ near_src,
+    const int32_t* __restrict__ near_tab, const T* __restrict__ V, int p, double* __restrict__ u) {
+  near3_body<T, KS>(sigma, near_tgt, near_haspw, near_start, near_src, near_tab, V, p, u, blockIdx.x);
+}
+template <typename T, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void near3_b(FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  near3_body<T, KS>(jobs[j].sigma, a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, cptr<T>(a.V),
+                    a.p, jobs[j].u, bid);
+}
+
+template <typename T, int NT, int KS>
+__global__ __launch_bounds__(256) void form2_box(const double* __restrict__ sigma, const int32_t* __restrict__ fitem,
+                                                 const int32_t* __restrict__ leaf_id,
+                                                 const int32_t* __restrict__ leaf_tab, const T* __restrict__ F,
+                                                 int p, int nr, T* __restrict__ phi, T* __restrict__ partial) {
+  form2_box_body<T, NT, KS>(sigma, fitem, leaf_id, leaf_tab, F, p, nr, phi, partial, blockIdx.x);
+}
+template <typename T, int NT, int KS>
+__global__ __launch_bounds__(256) void form2_box_b(FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  form2_box_body<T, NT, KS>(jobs[j].sigma, a.fitem, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
+                            mptr<T>(a.phi), mptr<T>(a.partial), bid);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void eval2_leaf(const T* __restrict__ psi, const int32_t* __restrict__ leaf_box,
+                                                  const int32_t* __restrict__ leaf_id,
+                                                  const int32_t* __restrict__ leaf_tab, const T* __restrict__ E,
+                                                  int p, int nr, int nleaf, double* __restrict__ u) {
+  eval2_leaf_body<T, NT>(psi, leaf_box, leaf_id, leaf_tab, E, p, nr, nleaf, u, blockIdx.x);
+}
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void eval2_leaf_b(FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  eval2_leaf_body<T, NT>(cptr<T>(a.psi), a.pwleaf_box, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr,
+                         (int)a.nL, jobs[j].u, bid);
+}
+
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void near2(const double* __restrict__ sigma, const int32_t* __restrict__ near_tgt,
+                                             const int32_t* __restrict__ near_haspw,
+                                             const int32_t* __restrict__ near_start,
+                                             const int32_t* __restrict__ near_src,
+                                             const int32_t* __restrict__ near_tab, const T* __restrict__ V, int p,
+                                             int ntgt, double* __restrict__ u) {
+  near2_body<T, KS>(sigma, near_tgt, near_haspw, near_start, near_src, near_tab, V, p, ntgt, u, blockIdx.x);
+}
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void near2_b(FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  near2_body<T, KS>(jobs[j].sigma, a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, cptr<T>(a.V),
+                    a.p, (int)a.nT, jobs[j].u, bid);
+}
+
+#undef FGT_BATCH_PROLOGUE
+#undef FGT_BATCH_PARAMS
+
+// ---------------------------------------------------------------------------
+// grids
+
+KernelClass kernel_class(const DeviceArgs& a) {
+  KernelClass c;
+  c.d = a.d;
+  c.fp32 = a.fp32;
+  c.nt = std::min(8, std::max(1, (a.nr + 15) / 16));
+  c.ks = a.p <= 8 ? 2 : 4;
+  return c;
+}
+
+int64_t stage_blocks(const DeviceArgs& a, int stage) {
+  const int64_t nr = a.nr;
+  const int64_t N2 = a.d == 3 ? nr * nr : nr;
+  const bool pw = a.nL > 0;
+  switch (stage) {
+    case kFormLeaf: return pw && a.d == 3 ? a.nL : 0;
+    case kFormBox: return pw ? (a.d == 3 ? a.nFI * ((N2 + 127) / 128) : a.nFI) : 0;
+    case kReduce: return pw && a.nFR > 0 ? a.nFR * ((N2 * nr + 255) / 256) : 0;
+    case kTranslate: return pw ? translate_blocks(a) : 0;
+    case kEvalBox: return pw && a.d == 3 ? a.nA * ((N2 + 63) / 64) : 0;
+    case kEvalLeaf: return pw ? (a.d == 3 ? a.nL : (a.nL + 3) / 4) : 0;
+    case kNear: return a.nT > 0 ? (a.d == 3 ? a.nT : (a.nT + 3) / 4) : 0;
+    default: return 0;
+  }
+}
+
+template <typename T, int NT, int KS>
+static void launch_batched_nt(int d, int stage, const BatchJob* jobs, const int32_t* start,
+                              const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+  const dim3 g((unsigned)grid), b(256);
+  if (d == 3) {
+    switch (stage) {
+      case kFormLeaf: hipLaunchKernelGGL((form3_leaf_b<T, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kFormBox: hipLaunchKernelGGL((form_box_b<T, 3, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kTranslate: launch_translate_batched<T>(3, jobs, start, count, njobs, grid, st); break;
+      case kEvalBox: hipLaunchKernelGGL((eval_box_b<T, 3, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kEvalLeaf: hipLaunchKernelGGL((eval3_leaf_b<T, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kNear: hipLaunchKernelGGL((near3_b<T, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+    }
+  } else {
+    switch (stage) {
+      case kFormBox: hipLaunchKernelGGL((form2_box_b<T, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kTranslate: launch_translate_batched<T>(2, jobs, start, count, njobs, grid, st); break;
+      case kEvalLeaf: hipLaunchKernelGGL((eval2_leaf_b<T, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kNear: hipLaunchKernelGGL((near2_b<T, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      default: break;
+    }
+  }
+}
+
+template <typename T, int KS>
+static void launch_batched_ks(const KernelClass& c, int stage, const BatchJob* jobs, const int32_t* start,
+                              const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+  switch (c.nt) {
+    case 1: launch_batched_nt<T, 1, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 2: launch_batched_nt<T, 2, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 3: launch_batched_nt<T, 3, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 4: launch_batched_nt<T, 4, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 5: launch_batched_nt<T, 5, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 6: launch_batched_nt<T, 6, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 7: launch_batched_nt<T, 7, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    default: launch_batched_nt<T, 8, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+  }
+}
+
+hipError_t launch_stage_batched(const KernelClass& c, int stage, const BatchJob* jobs, const int32_t* start,
+                                const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+  if (grid <= 0 || njobs <= 0) return hipSuccess;
+  if (c.d != 2 && c.d != 3) return hipErrorInvalidValue;
+  if (c.fp32) {
+    if (c.ks == 2) launch_batched_ks<float, 2>(c, stage, jobs, start, count, njobs, grid, st);
+    else launch_batched_ks<float, 4>(c, stage, jobs, start, count, njobs, grid, st);
+  } else {
+    if (c.ks == 2) launch_batched_ks<double, 2>(c, stage, jobs, start, count, njobs, grid, st);
+    else launch_batched_ks<double, 4>(c, stage, jobs, start, count, njobs, grid, st);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // launch
 
 template <typename T>
@@ -664,7 +897,7 @@ static void launch_reduce(const DeviceArgs& a, hipStream_t st) {
   int64_t ncoef = a.nr;
   for (int i = 1; i < a.d; i++) ncoef *= a.nr;
   const int nchunk = (int)((ncoef + 255) / 256);
-  hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)(a.nFR * nchunk)), dim3(256), 0, st,
+  hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)stage_blocks(a, kReduce)), dim3(256), 0, st,
                      static_cast<const T*>(a.partial), a.fred, ncoef, nchunk, static_cast<T*>(a.phi));
 }
 
@@ -683,32 +916,32 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
   if (a.nL > 0) {
     if (D == 3) {
       const int N2 = nr * nr, ncol = (N2 + 63) / 64, ncol128 = (N2 + 127) / 128;
-      hipLaunchKernelGGL((form3_leaf<T, NT, KS>), dim3(a.nL), dim3(256), 0, st, sigma, a.pwleaf_id,
+      hipLaunchKernelGGL((form3_leaf<T, NT, KS>), dim3((unsigned)stage_blocks(a, kFormLeaf)), dim3(256), 0, st, sigma, a.pwleaf_id,
                          a.pwleaf_tab, F, p, nr, Y);
       rec(1);
-      hipLaunchKernelGGL((form_box<T, 3, NT, KS>), dim3((unsigned)(a.nFI * ncol128)), dim3(256), 0, st, Y,
+      hipLaunchKernelGGL((form_box<T, 3, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, Y,
                          a.fitem, a.pwleaf_tab, F, p, nr, ncol128, phi, static_cast<T*>(a.partial));
       launch_reduce<T>(a, st);
       rec(2);
       launch_translate<T>(a, st);
       rec(3);
       const uint32_t pmagic = (uint32_t)((0x100000000ull + p - 1) / p);  // ceil(2^32 / p)
-      hipLaunchKernelGGL((eval_box<T, 3, NT>), dim3((unsigned)(a.nA * ncol)), dim3(256), 0, st, psi,
+      hipLaunchKernelGGL((eval_box<T, 3, NT>), dim3((unsigned)stage_blocks(a, kEvalBox)), dim3(256), 0, st, psi,
                          a.box_order, a.pw_start, a.pwleaf_tab, E, p, nr, ncol, pmagic, Y);
       rec(4);
-      hipLaunchKernelGGL((eval3_leaf<T, NT>), dim3(a.nL), dim3(256), 0, st, Y, a.pwleaf_id,
+      hipLaunchKernelGGL((eval3_leaf<T, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, Y, a.pwleaf_id,
                          a.pwleaf_tab, E, p, nr, u);
       rec(5);
     } else {
       rec(1);
-      hipLaunchKernelGGL((form2_box<T, NT, KS>), dim3(a.nFI), dim3(256), 0, st, sigma, a.fitem,
+      hipLaunchKernelGGL((form2_box<T, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, sigma, a.fitem,
                          a.pwleaf_id, a.pwleaf_tab, F, p, nr, phi, static_cast<T*>(a.partial));
       launch_reduce<T>(a, st);
       rec(2);
       launch_translate<T>(a, st);
       rec(3);
       rec(4);
-      hipLaunchKernelGGL((eval2_leaf<T, NT>), dim3((unsigned)((a.nL + 3) / 4)), dim3(256), 0, st, psi,
+      hipLaunchKernelGGL((eval2_leaf<T, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, psi,
                          a.pwleaf_box, a.pwleaf_id, a.pwleaf_tab, E, p, nr, (int)a.nL, u);
       rec(5);
     }
@@ -717,10 +950,10 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
   }
   if (a.nT > 0) {
     if (D == 3)
-      hipLaunchKernelGGL((near3<T, KS>), dim3(a.nT), dim3(256), 0, st, sigma, a.near_tgt, a.near_haspw,
+      hipLaunchKernelGGL((near3<T, KS>), dim3((unsigned)stage_blocks(a, kNear)), dim3(256), 0, st, sigma, a.near_tgt, a.near_haspw,
                          a.near_start, a.near_src, a.near_tab, V, p, u);
     else
-      hipLaunchKernelGGL((near2<T, KS>), dim3((unsigned)((a.nT + 3) / 4)), dim3(256), 0, st, sigma,
+      hipLaunchKernelGGL((near2<T, KS>), dim3((unsigned)stage_blocks(a, kNear)), dim3(256), 0, st, sigma,
                          a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, V, p,
                          (int)a.nT, u);
   }

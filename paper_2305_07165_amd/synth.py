@@ -177,10 +177,14 @@ def _coefficients(vals: np.ndarray, p: int, d: int) -> np.ndarray:
 
 def resolve_tree(func, d: int, p: int, eps: float, norm: float | None = None,
                  max_level: int = 12, min_level: int = 0,
-                 periodic: bool = False, chunk: int = 2048):
+                 periodic: bool = False, chunk: int = 2048, max_leaves: int | None = None):
     """Adaptive tree that resolves ``func`` (Algorithm 3): a box is split when
     the RMS of its Legendre tail exceeds eps*||sigma||_2, then the tree is
-    2:1 balanced.  Returns (levels, coords)."""
+    2:1 balanced.  Returns (levels, coords), or None if the tree before
+    balancing would exceed ``max_leaves``."""
+    sampler = sample
+    if isinstance(func, GaussianSum) and not func.periodic:
+        sampler = sample_separable
     if norm is None:
         norm = func.l2norm()
     thr = eps * norm
@@ -193,7 +197,7 @@ def resolve_tree(func, d: int, p: int, eps: float, norm: float | None = None,
         if level < max_level:
             for s in range(0, len(boxes), chunk):
                 b = boxes[s:s + chunk]
-                vals = sample(np.full(len(b), level), b, p, func)
+                vals = sampler(np.full(len(b), level), b, p, func)
                 coef = _coefficients(vals, p, d)
                 e = np.sqrt(np.mean(coef[:, mask] ** 2, axis=1))
                 split[s:s + chunk] = e > thr
@@ -205,9 +209,11 @@ def resolve_tree(func, d: int, p: int, eps: float, norm: float | None = None,
                 for o in itertools.product((0, 1), repeat=d)]
         boxes = np.concatenate(kids, 0) if len(parents) else np.zeros((0, d), np.int32)
         level += 1
+        if max_leaves is not None and sum(len(c) for c in leaves_c) + len(boxes) > max_leaves:
+            return None
     levels = np.concatenate(leaves_l)
     coords = np.concatenate(leaves_c, 0).astype(np.int32)
-    return balance(levels, coords, periodic=periodic)
+    return balance_fast(levels, coords, periodic=periodic)
 
 
 def balance(levels, coords, periodic: bool = False):
@@ -480,21 +486,20 @@ def serve_request_types(seed: int, ntypes: int, log10_n=(4.0, 8.0), log10_delta=
         nb = int(rng.integers(2, 17))
         dens = GaussianSum(*_blobs(rng, nb, d, -0.3, 0.3, 1e-2, 5e-2, False))
         lv, cs = sized_tree(d, dens.centers, round(n / p ** d))
-        if not is_balanced_fast(lv, cs):
-            lv, cs = balance(lv, cs)
+        lv, cs = balance_fast(lv, cs)
         out.append(RequestType(k, d, p, delta, tol, "fp32" if tol >= fp32_min_tol else "fp64",
                                lv, cs, sample_separable(lv, cs, p, dens)))
     return out
 
 
-def is_balanced_fast(levels, coords, periodic: bool = False) -> bool:
-    """Vectorized 2:1 check with corner adjacency, for trees that tile the box.
-    If leaves A (coarser) and B share a boundary point, B's whole face, edge
-    or corner on that contact lies in A's boundary, so the finest-grid cell
-    just outside B in that direction (at B's lower corner along the other
-    axes) lies in A.  The check therefore asks, for every leaf and each of the
-    3^d - 1 directions, that this cell lies in a leaf at most one level
-    coarser; finer neighbors are covered from their own side."""
+def _coarse_neighbors(levels, coords, periodic: bool = False) -> np.ndarray:
+    """Indices of leaves that violate 2:1 balance (corner adjacency) by being
+    at least two levels coarser than a leaf they touch; vectorized, for trees
+    that tile the box.  If leaves A (coarser) and B touch, B's whole face,
+    edge or corner on that contact lies in A's boundary, so the finest-grid
+    cell just outside B in that direction (at B's lower corner along the other
+    axes) lies in A: for every leaf and each of the 3^d - 1 directions, the
+    leaf covering that cell is found and reported if it is too coarse."""
     levels = np.asarray(levels, dtype=np.int64)
     coords = np.asarray(coords, dtype=np.int64)
     n, d = coords.shape
@@ -503,20 +508,23 @@ def is_balanced_fast(levels, coords, periodic: bool = False) -> bool:
 
     def keys(lv, cs):
         k = lv.copy()
-        for a in range(d):
-            k = k * side + cs[:, a]
+        for ax in range(d):
+            k = k * side + cs[:, ax]
         return k
 
-    table = np.sort(keys(levels, coords))
+    key = keys(levels, coords)
+    order = np.argsort(key)
+    table = key[order]
 
-    def present(lv, cs):
+    def lookup(lv, cs):
         k = keys(lv, cs)
-        i = np.minimum(np.searchsorted(table, k), len(table) - 1)
-        return table[i] == k
+        i = np.minimum(np.searchsorted(table, k), n - 1)
+        return np.where(table[i] == k, order[i], -1)
 
     sh = lmax - levels
     base = coords << sh[:, None]
     step = (np.int64(1) << sh)[:, None]
+    bad = []
     for o in itertools.product((-1, 0, 1), repeat=d):
         if not any(o):
             continue
@@ -532,8 +540,83 @@ def is_balanced_fast(levels, coords, periodic: bool = False) -> bool:
             ll = levels[sel] + dl
             okl = (ll >= 0) & (ll <= lmax)
             llc = np.clip(ll, 0, lmax)
-            cs = q[sel] >> (lmax - llc)[:, None]
-            found |= okl & present(llc, cs)
-        if not np.all(found):
-            return False
-    return True
+            found |= okl & (lookup(llc, q[sel] >> (lmax - llc)[:, None]) >= 0)
+        miss = sel[~found]
+        qm = q[miss]
+        for ll in range(lmax - 2, -1, -1):  # the covering leaf is coarser still
+            lv = np.full(len(miss), ll, dtype=np.int64)
+            hit = lookup(lv, qm >> (lmax - ll))
+            ok = (hit >= 0) & (ll <= levels[miss] - 2)
+            bad.append(hit[ok])
+    return np.unique(np.concatenate(bad)) if bad else np.zeros(0, dtype=np.int64)
+
+
+def is_balanced_fast(levels, coords, periodic: bool = False) -> bool:
+    """Vectorized equivalent of `is_balanced` for trees that tile the box."""
+    return len(_coarse_neighbors(levels, coords, periodic)) == 0
+
+
+def balance_fast(levels, coords, periodic: bool = False):
+    """Vectorized equivalent of `balance`: split every leaf that is two or
+    more levels coarser than a leaf it touches, until none is."""
+    levels = np.asarray(levels, dtype=np.int32)
+    coords = np.asarray(coords, dtype=np.int32)
+    d = coords.shape[1]
+    kids_off = np.array(list(itertools.product((0, 1), repeat=d)), dtype=np.int32)
+    while True:
+        bad = _coarse_neighbors(levels, coords, periodic)
+        if len(bad) == 0:
+            break
+        keep = np.ones(len(levels), dtype=bool)
+        keep[bad] = False
+        kl = np.repeat(levels[bad] + 1, len(kids_off))
+        kc = (2 * coords[bad][:, None, :] + kids_off[None, :, :]).reshape(-1, d)
+        levels = np.concatenate([levels[keep], kl]).astype(np.int32)
+        coords = np.concatenate([coords[keep], kc], 0).astype(np.int32)
+    idx = np.lexsort(tuple(coords[:, a] for a in range(d - 1, -1, -1)) + (levels,))
+    return levels[idx], coords[idx]
+
+def _batch_tree(args):
+    """Parameters and tree of transform k of the batched workload."""
+    seed, k, max_points, eps, tols, fp32_min_tol, one_thread = args
+    if one_thread:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):
+            return _batch_tree((seed, k, max_points, eps, tols, fp32_min_tol, False))
+    rng = np.random.default_rng((seed, k))
+    d = int(rng.integers(2, 4))
+    delta = float(10.0 ** rng.uniform(-6.0, -2.0))
+    depth = int(rng.integers(3, 10))
+    p = int((8, 16)[int(rng.integers(0, 2))])
+    nb = int(rng.integers(2, 17))
+    tol = float(tols[int(rng.integers(0, len(tols)))])
+    dens = GaussianSum(*_blobs(rng, nb, d, -0.3, 0.3, 1e-2, 5e-2, False))
+    cap = max(1, max_points // p ** d)
+    while True:
+        t = resolve_tree(dens, d, p, eps, max_level=depth, max_leaves=cap)
+        if t is not None and len(t[0]) <= cap:
+            break
+        depth -= 1
+    return k, d, p, delta, tol, "fp32" if tol >= fp32_min_tol else "fp64", t[0], t[1], dens
+
+
+def batch_problems(seed: int, n: int = 512, max_points: int = 1 << 21, eps: float = 1e-9,
+                   tols=(1e-3, 1e-6, 1e-10), fp32_min_tol: float = 1e-6, workers: int = 1):
+    """The batched workload: n independent transforms, each with d ~ U{2,3},
+    log10 delta ~ U[-6,-2], a depth cap ~ U{3..9} on the Algorithm 3 tree that
+    resolves sigma to eps*||sigma||_2, p ~ U{8,16}, sigma a sum of 2-16
+    Gaussians as in the small 2D workload (centers U[-0.3,0.3]^d, widths
+    U[0.01,0.05], amplitudes U(-1,1)), tol ~ U{tols}; FP32 when
+    tol >= fp32_min_tol, else FP64.  A transform over max_points grid points
+    has its depth cap lowered until it fits.  Transform k draws from its own
+    generator (seed, k), so the result does not depend on `workers`: processes
+    forked to build the trees (fork them before the process uses a GPU)."""
+    jobs = [(seed, k, max_points, eps, tuple(tols), fp32_min_tol, True) for k in range(n)]
+    if workers <= 1:
+        trees = [_batch_tree(j) for j in jobs]
+    else:
+        import multiprocessing
+        with multiprocessing.get_context("fork").Pool(workers) as pool:
+            trees = pool.map(_batch_tree, jobs, chunksize=2)
+    return [RequestType(k, d, p, delta, tol, prec, lv, cs, sample_separable(lv, cs, p, dens))
+            for k, d, p, delta, tol, prec, lv, cs, dens in trees]

@@ -1,0 +1,134 @@
+"""GPU tests of batched execution (include/fgt_batch.h).
+
+A batch runs the same kernel bodies as fgt_execute, so every transform's
+result must equal its result alone bitwise, in graph replay and direct mode,
+under every schedule the autotuner tries, and after rebinding.  Two
+transforms are also checked against the FP64 oracle within their tol.
+"""
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+from paper_2305_07165_amd import api, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-batch] {msg}", flush=True)
+
+
+_CACHE = {}
+
+
+def _problems():
+    if "p" not in _CACHE:
+        probs = synth.batch_problems(3, 20, max_points=1 << 17)
+        # a periodic 2D transform and a 1D transform (run with their own launches)
+        dens = synth.GaussianSum(np.array([[0.46, -0.17], [-0.2, 0.49]]), np.array([0.01, 0.03]),
+                                 np.array([0.7, -0.4]), periodic=True)
+        lv, cs = synth.resolve_tree(dens, 2, 8, 1e-10, max_level=6, periodic=True)
+        probs.append(synth.RequestType(100, 2, 8, 1e-3, 1e-6, "fp64", lv, cs,
+                                       synth.sample(lv, cs, 8, dens)))
+        d1 = synth.GaussianSum(np.array([[0.13]]), np.array([0.01]), np.array([1.0]))
+        lv, cs = synth.resolve_tree(d1, 1, 9, 1e-12, max_level=9)
+        probs.append(synth.RequestType(101, 1, 9, 1e-4, 1e-10, "fp64", lv, cs, synth.sample(lv, cs, 9, d1)))
+        _CACHE["p"] = probs
+    return _CACHE["p"]
+
+
+def _periodic(t):
+    return t.key == 100
+
+
+def _plans(probs):
+    return [api.Plan(t.levels, t.coords, t.p, t.delta, t.tol, periodic=_periodic(t), precision=t.precision)
+            for t in probs]
+
+
+def _alone(plans, sig):
+    out = []
+    for pl, s in zip(plans, sig):
+        out.append(pl.execute(s).clone())
+    torch.cuda.synchronize()
+    return out
+
+
+def test_batch_equals_alone_graph_and_direct():
+    probs = _problems()
+    for t in probs:
+        _say(f"job {t.key}: d={t.d} p={t.p} leaves={len(t.levels)} N={t.npoints} delta={t.delta:.1e} "
+             f"tol={t.tol} {t.precision}")
+    plans = _plans(probs)
+    sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
+    ref = _alone(plans, sig)
+    for use_graph in (True, False):
+        b = api.Batch(plans, use_graph=use_graph)
+        us = [torch.full_like(s, float("nan")) for s in sig]
+        b.bind(sig, us)
+        info = b.info()
+        _say(f"graph={use_graph} info {info}")
+        assert info["njobs"] == len(probs) and info["nsingle"] == 1
+        for rep in range(3):
+            b.execute()
+            torch.cuda.synchronize()
+            for i, (u, r) in enumerate(zip(us, ref)):
+                assert torch.equal(u, r), f"rep {rep} job {i} differs from its result alone"
+            # eager work between replays; results must not depend on it
+            for u in us:
+                u.fill_(float("nan"))
+            torch.cuda.synchronize()
+        b.close()
+
+
+def test_batch_rebind_and_tune():
+    probs = _problems()
+    plans = _plans(probs)
+    sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
+    ref = _alone(plans, sig)
+    b = api.Batch(plans)
+    us = [torch.empty_like(s) for s in sig]
+    b.bind(sig, us)
+    b.execute()
+    best = b.tune(reps=2)
+    info = b.info()
+    _say(f"tuned {best:.3f} ms/exec: {info}")
+    assert best > 0 and info["tuned_ms"] == best
+    # new outputs and doubled inputs after tuning: linear, and still exact per job
+    sig2 = [2.0 * s for s in sig]
+    us2 = [torch.full_like(s, float("nan")) for s in sig]
+    b.bind(sig2, us2)
+    b.execute()
+    torch.cuda.synchronize()
+    ref2 = _alone(plans, sig2)
+    for u, r in zip(us2, ref2):
+        assert torch.equal(u, r)
+    b.close()
+
+
+def test_batch_matches_oracle():
+    probs = [t for t in _problems() if t.d == 2 and t.npoints <= 40_000][:2]
+    assert probs
+    plans = _plans(probs)
+    sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
+    us = [torch.empty_like(s) for s in sig]
+    b = api.Batch(plans)
+    b.bind(sig, us)
+    b.execute()
+    torch.cuda.synchronize()
+    for t, u in zip(probs, us):
+        uo = oracle.oracle_u(t.levels, t.coords, t.p, t.delta, t.sigma, periodic=_periodic(t))
+        err = cf.rel_l2(u.cpu().numpy(), uo)
+        _say(f"job {t.key} vs oracle: rel_l2={err:.2e} tol={t.tol}")
+        assert err < t.tol
+    b.close()
+
+
+def test_batch_rejects_host_only_plans():
+    t = _problems()[0]
+    hp = api.Plan(t.levels, t.coords, t.p, t.delta, t.tol, host_only=True)
+    with pytest.raises(api.FgtError):
+        api.Batch([hp])

@@ -155,7 +155,7 @@ def test_errors_are_reported():
     t = _types()[0]
     s = torch.from_numpy(t.sigma).cuda()
     u = torch.empty_like(s)
-    with api.Server(nslots=1, hbm_budget=1 << 16) as srv:
+    with api.Server(nslots=1, hbm_budget=1024) as srv:
         # a type that cannot fit the budget completes with FGT_ERR_OOM
         srv.submit(1, s, u, t.p, t.delta, t.tol, precision=t.precision,
                    levels=t.levels, coords=t.coords)
