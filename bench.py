@@ -44,16 +44,24 @@ def stage_work(info: dict) -> dict:
     nL, nA, nP, nN = info["n_pwleaf"], info["n_pwbox"], info["n_plist"], info["n_near_pair"]
     ts = 4 if info["precision"] == 1 else 8
     n2 = nr ** (d - 1)
-    lead = sum(2.0 * nr ** a * p ** (d - a + 1) for a in range(1, d))  # axes 1..d-1
-    last = 2.0 * nr ** d * p                                           # axis d
     npts = info["npoints"]
     npw = nL * p ** d
+    if d == 3:
+        # axis 2 per leaf, axis 1 per row, axis 3 per plane (leaf groups that
+        # share a 1D table); the intermediate holds one p x nr^2 block per plane
+        nU = info["n_plane"]
+        lead = 2.0 * nr * p ** 3 * nL + 2.0 * nr ** 2 * p ** 2 * info["n_row"]
+        last = 2.0 * nr ** 3 * p * nU
+    else:
+        nU = nL
+        lead = nL * sum(2.0 * nr ** a * p ** (d - a + 1) for a in range(1, d))
+        last = nL * 2.0 * nr ** d * p
     return {
-        "form_leaf": {"flops": nL * lead, "bytes": 8.0 * npw + ts * nL * p * n2},
-        "form_box": {"flops": nL * last, "bytes": ts * nL * p * n2 + ts * nA * nr ** d},
+        "form_leaf": {"flops": lead, "bytes": 8.0 * npw + ts * nU * p * n2},
+        "form_box": {"flops": last, "bytes": ts * nU * p * n2 + ts * nA * nr ** d},
         "translate": {"flops": (3.0 * d + 1) * nr ** d * nP, "bytes": 2.0 * ts * nA * nr ** d},
-        "eval_box": {"flops": nL * last, "bytes": ts * nA * nr ** d + ts * nL * p * n2},
-        "eval_leaf": {"flops": nL * lead, "bytes": ts * nL * p * n2 + 8.0 * npw},
+        "eval_box": {"flops": last, "bytes": ts * nA * nr ** d + ts * nU * p * n2},
+        "eval_leaf": {"flops": lead, "bytes": ts * nU * p * n2 + 8.0 * npw},
         "near": {"flops": 2.0 * d * p ** (d + 1) * nN,
                  "bytes": 8.0 * (npts - npw + info["n_near_target"] * p ** d)},
     }
@@ -61,7 +69,7 @@ def stage_work(info: dict) -> dict:
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h"):
+    for f in ("kernels.hip", "kernels_fast.hip", "kernels.h", "mfma.h"):
         with open(os.path.join(ROOT, "paper_2305_07165_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

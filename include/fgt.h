@@ -84,6 +84,9 @@ typedef struct fgt_info {
   double bytes_min;      /* algorithmic minimum HBM bytes per execute */
   int64_t device_bytes;  /* device memory held by the plan; for a host-only plan, the
                             bytes it would hold once on the device (an upper bound) */
+  int64_t n_plane, n_row; /* d = 3: plane-wave leaves grouped by (box, level, axis-3
+                            position) and, within those, by axis-1 position; formation and
+                            evaluation apply each 1D table once per group; 0 for d < 3 */
 } fgt_info_t;
 
 typedef struct fgt_plan fgt_plan_t;

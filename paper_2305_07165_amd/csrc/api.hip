@@ -91,7 +91,8 @@ int64_t fgt::plan_device_bytes(const HostPlan& hp) {
   for (const std::vector<int32_t>* v : {&hp.pw_start, &hp.pwleaf_id, &hp.pwleaf_tab, &hp.pwleaf_box,
                                         &hp.box_order, &hp.plist_start, &hp.plist_src, &hp.plist_dir,
                                         &hp.echunk, &hp.near_tgt, &hp.fitem, &hp.fred, &hp.near_haspw,
-                                        &hp.near_start, &hp.near_src, &hp.near_tab})
+                                        &hp.near_start, &hp.near_src, &hp.near_tab, &hp.plane_start,
+                                        &hp.plane_tab, &hp.plane_row, &hp.row_start, &hp.row_tab})
     b += 4 * (int64_t)v->size();
   return b + plan_workspace_bytes(hp);
 }
@@ -103,7 +104,8 @@ int64_t fgt::plan_workspace_bytes(const HostPlan& hp) {
   const int64_t ncoef = n2 * hp.nr;
   const int64_t round = 256 / ts;  // each array starts on a 256-byte boundary
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
-  return ts * (up(hp.n_pwleaf() * hp.p * n2) + 2 * up(hp.n_pwbox() * ncoef) + up((int64_t)hp.nslots * ncoef));
+  const int64_t nU = hp.d == 3 ? hp.n_plane() : hp.n_pwleaf();
+  return ts * (up(nU * hp.p * n2) + 2 * up(hp.n_pwbox() * ncoef) + up((int64_t)hp.nslots * ncoef));
 }
 
 namespace {
@@ -147,11 +149,16 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
       (rc = upload_i32(pl, hp.fitem, &a.fitem)) || (rc = upload_i32(pl, hp.fred, &a.fred)) ||
       (rc = upload_i32(pl, hp.near_haspw, &a.near_haspw)) ||
       (rc = upload_i32(pl, hp.near_start, &a.near_start)) || (rc = upload_i32(pl, hp.near_src, &a.near_src)) ||
-      (rc = upload_i32(pl, hp.near_tab, &a.near_tab)))
+      (rc = upload_i32(pl, hp.near_tab, &a.near_tab)) ||
+      (rc = upload_i32(pl, hp.plane_start, &a.plane_start)) ||
+      (rc = upload_i32(pl, hp.plane_tab, &a.plane_tab)) || (rc = upload_i32(pl, hp.plane_row, &a.plane_row)) ||
+      (rc = upload_i32(pl, hp.row_start, &a.row_start)) || (rc = upload_i32(pl, hp.row_tab, &a.row_tab)))
     return rc;
+  a.nPl = hp.n_plane();
   const size_t n2 = (size_t)ipowd(hp.nr, hp.d - 1);
   const size_t ncoef = n2 * hp.nr;
-  if ((rc = alloc(pl, (size_t)a.nL * hp.p * n2 * ts, &a.Y)) ||
+  const int64_t nU = hp.d == 3 ? hp.n_plane() : a.nL;
+  if ((rc = alloc(pl, (size_t)nU * hp.p * n2 * ts, &a.Y)) ||
       (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.phi)) || (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.psi)) ||
       (rc = alloc(pl, (size_t)hp.nslots * ncoef * ts, &a.partial)))
     return rc;
@@ -243,7 +250,7 @@ int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem
   char* c = static_cast<char*>(m);
   *args = pl->args;
   args->Y = c;
-  c += ts * up(hp.n_pwleaf() * hp.p * n2);
+  c += ts * up((hp.d == 3 ? hp.n_plane() : hp.n_pwleaf()) * hp.p * n2);
   args->phi = c;
   c += ts * up(hp.n_pwbox() * ncoef);
   args->psi = c;
@@ -361,10 +368,18 @@ int fgt_plan_info(const fgt_plan_t* pl, fgt_info_t* info) {
   info->n_plist = hp.n_plist();
   info->n_near_target = hp.n_near_tgt();
   info->n_near_pair = hp.n_near_pair();
-  double per_leaf = 0;
-  for (int a = 1; a <= hp.d; a++) per_leaf += 2.0 * ipowd(hp.nr, a) * ipowd(hp.p, hp.d - a + 1);
-  info->flops_form = per_leaf * hp.n_pwleaf();
-  info->flops_eval = per_leaf * hp.n_pwleaf();
+  double fe = 0;  // formation (= evaluation) flops: each 1D table applied once per leaf group
+  if (hp.d == 3) {
+    fe = 2.0 * hp.nr * ipowd(hp.p, 4) * hp.n_pwleaf() + 2.0 * ipowd(hp.nr, 2) * ipowd(hp.p, 3) * hp.n_row() +
+         2.0 * ipowd(hp.nr, 3) * ipowd(hp.p, 2) * hp.n_plane();
+    fe /= hp.p;
+  } else {
+    for (int a = 1; a <= hp.d; a++) fe += 2.0 * ipowd(hp.nr, a) * ipowd(hp.p, hp.d - a + 1) * hp.n_pwleaf();
+  }
+  info->flops_form = fe;
+  info->flops_eval = fe;
+  info->n_plane = hp.n_plane();
+  info->n_row = hp.n_row();
   info->flops_translate = (3.0 * hp.d + 1.0) * ipowd(hp.nr, hp.d) * hp.n_plist();
   info->flops_near = 2.0 * hp.d * ipowd(hp.p, hp.d + 1) * hp.n_near_pair();
   const double ts = hp.precision == FGT_FP32 ? 4.0 : 8.0;
@@ -430,6 +445,11 @@ int64_t fgt_plan_array(const fgt_plan_t* pl, const char* name, void* dst, int64_
   else if (n == "near_tab") iv = &hp.near_tab;
   else if (n == "ftab_meta") iv = &hp.ftab_meta;
   else if (n == "vtab_meta") iv = &hp.vtab_meta;
+  else if (n == "plane_start") iv = &hp.plane_start;
+  else if (n == "plane_tab") iv = &hp.plane_tab;
+  else if (n == "plane_row") iv = &hp.plane_row;
+  else if (n == "row_start") iv = &hp.row_start;
+  else if (n == "row_tab") iv = &hp.row_tab;
   else return fail(FGT_ERR_INVALID_ARG, "unknown array name");
   if (dv) {
     if (dst && cap > 0) std::memcpy(dst, dv->data(), sizeof(double) * std::min<int64_t>(cap, dv->size()));

@@ -46,10 +46,19 @@ struct HostPlan {
   std::vector<int32_t> plist_start;   // [nA+1]
   std::vector<int32_t> plist_src;     // [nP] plane-wave box index
   std::vector<int32_t> plist_dir;     // [nP] sum_a (dir_a+1) 3^a, dir = src - dst
+  // d = 3 only: a plane is a run of pw leaves of one box with the same level and
+  // axis-3 position (one axis-3 table); a row is a run of a plane's leaves that
+  // also share the axis-1 position (one axis-1 table)
+  std::vector<int32_t> plane_start;   // [nA+1] ranges of planes per box
+  std::vector<int32_t> plane_tab;     // [nPl*3] entry 2: the plane's axis-3 table (0, 0, t3)
+  std::vector<int32_t> plane_row;     // [nPl+1] ranges of rows per plane
+  std::vector<int32_t> row_start;     // [nR+1] ranges of pw leaves per row
+  std::vector<int32_t> row_tab;       // [nR] the row's axis-1 table
   // evaluation work items: (box, first pw leaf, count) with count*p <= 64 rows
   std::vector<int32_t> echunk;        // [nE*3]
-  // formation work items: (box, first pw leaf, end pw leaf, partial slot or -1);
-  // boxes with more than kFormLeaves leaves are split, their partial sums
+  // formation work items: (box, first unit, end unit, partial slot or -1), a unit
+  // being a plane for d = 3 and a pw leaf otherwise;
+  // boxes with more than kFormLeaves units are split, their partial sums
   // reduced in item order by (box, first slot, slot count) records
   std::vector<int32_t> fitem;         // [nFI*4]
   std::vector<int32_t> fred;          // [nFR*3]
@@ -79,6 +88,8 @@ struct HostPlan {
   int64_t n_plist() const { return (int64_t)plist_src.size(); }
   int64_t n_near_tgt() const { return (int64_t)near_tgt.size(); }
   int64_t n_near_pair() const { return (int64_t)near_src.size(); }
+  int64_t n_plane() const { return row_start.empty() ? 0 : (int64_t)plane_row.size() - 1; }
+  int64_t n_row() const { return row_start.empty() ? 0 : (int64_t)row_start.size() - 1; }
 };
 
 // Validates the tree and fills every field above.  Returns an FGT_* code.

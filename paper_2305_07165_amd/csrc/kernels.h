@@ -26,9 +26,14 @@ struct DeviceArgs {
   // the reductions of split boxes (box, first slot, slot count)
   const int32_t *fitem = nullptr, *fred = nullptr;
   int64_t nFI = 0, nFR = 0;
+  // d = 3 planes and rows of pw leaves (fgt_host.h)
+  int64_t nPl = 0;
+  const int32_t *plane_start = nullptr, *plane_tab = nullptr, *plane_row = nullptr;
+  const int32_t *row_start = nullptr, *row_tab = nullptr;
   const int32_t *near_tgt = nullptr, *near_haspw = nullptr, *near_start = nullptr;
   const int32_t *near_src = nullptr, *near_tab = nullptr;
-  // workspace (compute precision): Y/Z [nL][p*nr^(d-1)], phi/psi [nA][nr^d]
+  // workspace (compute precision): Y/Z [nU][p*nr^(d-1)] (nU = planes for d = 3,
+  // pw leaves otherwise), phi/psi [nA][nr^d]
   void *Y = nullptr, *phi = nullptr, *psi = nullptr;
   void* partial = nullptr;  // [nslots][nr^d] partial sums of split boxes
 };

@@ -7,11 +7,14 @@
 // used only where a contraction runs across the tiles held by different waves.
 //
 // d = 3:
-//   form3_leaf  Y_s[j3][r1][r2] = sum_j1 F1[r1][j1] (sum_j2 sigma_s[j3][j2][j1] F2[r2][j2])
-//   form_box    phi_A[r3][c]    = sum_{s in A} sum_j3 F3_s[r3][j3] Y_s[j3][c]
+//   form3_plane Y_P[j3][r1][r2] = sum_{rows} F1_row[r1][j1] (sum_{s in row} sum_j2 sigma_s[j3][j2][j1] F2_s[r2][j2])
+//   form_box    phi_A[r3][c]    = sum_{P in A} sum_j3 F3_P[r3][j3] Y_P[j3][c]
 //   translate   psi_A = sum_{B in P(A)} Rot(c_B - c_A) phi_B        (kernels.hip)
-//   eval_box    Z_s[i3][c]      = sum_r3 E3_s[i3][r3] psi_A[r3][c]
-//   eval3_leaf  u_s[i3][i2][i1] = sum_r2 E2[i2][r2] (sum_r1 Z_s[i3][r1][r2] E1[i1][r1])
+//   eval_box    Z_P[i3][c]      = sum_r3 E3_P[i3][r3] psi_A[r3][c]
+//   eval3_plane u_s[i3][i2][i1] = sum_r2 E2_s[i2][r2] (sum_r1 Z_P[i3][r1][r2] E1_row[i1][r1])
+// (P: a plane of leaves sharing level and axis-3 table; row: leaves of a plane
+// sharing the axis-1 table.  Grouping the sums this way is exact: each table
+// factor is applied once to the sum of everything it multiplies.)
 //   near3       u_T (+)= sum_S (V3 (x) V2 (x) V1) sigma_S, grouped by tables
 // The mode tensors phi, psi, Y, Z of d = 3 are stored with the r2 index fastest
 // ([r3][r1][r2]), so that every global operand load runs along a contiguous axis.
@@ -36,74 +39,93 @@ struct Steps {
 };
 
 // ---------------------------------------------------------------------------
-// d = 3 formation, axes 2 and 1, one leaf per workgroup, one j3 slice per wave.
-// Mode tensors are stored [r3][r1][r2] (r2 fastest).  Per slice:
-//   X^T[j1][r2] = sum_j2 sigma[j3][j2][j1] F2[r2][j2]   (lanes run along j1: coalesced)
-//   Y[r1][r2]   = sum_j1 F1[r1][j1] X^T[j1][r2]        (B operand chained from X^T)
+// d = 3 formation, axes 2 and 1, one plane per workgroup.  A plane is a run of
+// leaves of one cutoff box with the same level and axis-3 position; its rows
+// also share the axis-1 position (fgt_host.h).  By separability
+//   Y_P[j3][r1][r2] = sum_rows F1_row[r1][j1] (sum_{s in row} sum_j2 sigma_s[j3][j2][j1] F2_s[r2][j2])
+// and the last axis then runs once per plane instead of once per leaf.  Work
+// items (j3 slice, r2 tile ti) are spread over the 4 waves; per item:
+//   X^T[j1][r2] += sigma_s[j3] x F2_s      over the leaves of a row (lanes along j1)
+//   Y[r1][r2]   += F1_row x X^T            once per row (X^T chained as the B operand)
 
 template <typename T, int NT, int KS>
-__device__ __forceinline__ void form3_leaf_body(const double* __restrict__ sigma,
-                                                  const int32_t* __restrict__ leaf_id,
-                                                  const int32_t* __restrict__ leaf_tab,
-                                                  const T* __restrict__ F, int p, int nr,
-                                                  T* __restrict__ Y, int bid) {
+__device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigma,
+                                                 const int32_t* __restrict__ leaf_id,
+                                                 const int32_t* __restrict__ leaf_tab,
+                                                 const int32_t* __restrict__ plane_row,
+                                                 const int32_t* __restrict__ row_start,
+                                                 const int32_t* __restrict__ row_tab,
+                                                 const T* __restrict__ F, int p, int nr,
+                                                 T* __restrict__ Y, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<T, KS>::value;
-  const int s = bid;
-  const int leaf = leaf_id[s];
+  const int P = bid;
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
-  const T* F1 = F + (int64_t)leaf_tab[s * 3 + 0] * nr * p;
-  const T* F2 = F + (int64_t)leaf_tab[s * 3 + 1] * nr * p;
-  T a1[NT][S], b2[NT][S];
-#pragma unroll
-  for (int t = 0; t < NT; t++)
-#pragma unroll
-    for (int kk = 0; kk < S; kk++) {
-      const int k = M::kidx(kk, lk), r = 16 * t + lr;
-      const bool ok = r < nr && k < p;
-      a1[t][kk] = ld0<T>(F1, r * p + k, ok);  // A[r1][j1]
-      b2[t][kk] = ld0<T>(F2, r * p + k, ok);  // B[j2][r2] = F2[r2][j2]
-    }
-  const double* sg = sigma + (int64_t)leaf * p * p * p;
-  T* Ys = Y + (int64_t)s * p * nr * nr;
-  T avs[KS][S];
-#pragma unroll
-  for (int it = 0; it < KS; it++)
+  const int rw0 = plane_row[P], rw1 = plane_row[P + 1];
+  const int s_begin = row_start[rw0], s_end = row_start[rw1];
+  const int64_t ppp = (int64_t)p * p * p;
+  T* Yp = Y + (int64_t)P * p * nr * nr;
+  // operands of leaf s for slice j3 and r2 tile ti; masked loads (no branches)
+  auto load = [&](int s, int j3, int ti, T (&av)[S], T (&b2)[S]) {
+    const bool ls = s < s_end;
+    const int sc = ls ? s : s_begin;
+    const double* sg = sigma + (int64_t)leaf_id[sc] * ppp;
+    const T* F2 = F + (int64_t)leaf_tab[sc * 3 + 1] * nr * p;
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
-      const int j3 = w + 4 * it, k = M::kidx(kk, lk);
-      avs[it][kk] = ld0<T>(sg, (j3 * p + k) * p + lr, j3 < p && lr < p && k < p);  // A[j1][j2]
+      const int k = M::kidx(kk, lk), r = 16 * ti + lr;
+      av[kk] = ld0<T>(sg, (j3 * p + k) * p + lr, ls && lr < p && k < p);  // A[j1][j2]
+      b2[kk] = ld0<T>(F2, r * p + k, ls && r < nr && k < p);            // B[j2][r2] = F2[r2][j2]
     }
+  };
+  const int nitem = p * NT;
+  for (int item = w; item < nitem; item += 4) {
+    const int j3 = item / NT, ti = item - j3 * NT;
+    acc_t y[NT];
 #pragma unroll
-  for (int it = 0; it < KS; it++) {
-    const int j3 = w + 4 * it;
-    if (j3 >= p) break;
-    const T (&av)[S] = avs[it];
-    acc_t x[NT];  // X^T, rows j1, columns r2 (tile ti)
+    for (int tj = 0; tj < NT; tj++) zero4(y[tj]);
+    T av[S], b2[S];
+    load(s_begin, j3, ti, av, b2);
+    int rw = rw0;
+    int row_end = row_start[rw0 + 1];
+    acc_t x;
+    zero4(x);
+    for (int s = s_begin; s < s_end; s++) {
+      T avn[S], b2n[S];
+      load(s + 1, j3, ti, avn, b2n);
 #pragma unroll
-    for (int ti = 0; ti < NT; ti++) {
-      zero4(x[ti]);
+      for (int kk = 0; kk < S; kk++) x = M::step(av[kk], b2[kk], x);
+      if (s + 1 == row_end) {
+        const T* F1 = F + (int64_t)row_tab[rw] * nr * p;
 #pragma unroll
-      for (int kk = 0; kk < S; kk++) x[ti] = M::step(av[kk], b2[ti][kk], x[ti]);
-    }
+        for (int tj = 0; tj < NT; tj++) {
 #pragma unroll
-    for (int tj = 0; tj < NT; tj++) {
-#pragma unroll
-      for (int ti = 0; ti < NT; ti++) {
-        acc_t y;  // rows r1 (tile tj), columns r2 (tile ti)
-        zero4(y);
-#pragma unroll
-        for (int kk = 0; kk < S; kk++) y = M::step(a1[tj][kk], x[ti][kk], y);
-        const int r2 = 16 * ti + lr;
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-          const int r1 = 16 * tj + M::row(lk, t);
-          if (r1 < nr && r2 < nr) Ys[((int64_t)j3 * nr + r1) * nr + r2] = y[t];
+          for (int kk = 0; kk < S; kk++) {
+            const int k = M::kidx(kk, lk), r = 16 * tj + lr;
+            const T a1 = ld0<T>(F1, r * p + k, r < nr && k < p);  // A[r1][j1]
+            y[tj] = M::step(a1, x[kk], y[tj]);
+          }
         }
+        zero4(x);
+        rw++;
+        if (rw < rw1) row_end = row_start[rw + 1];
+      }
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) {
+        av[kk] = avn[kk];
+        b2[kk] = b2n[kk];
       }
     }
+    const int r2 = 16 * ti + lr;
+#pragma unroll
+    for (int tj = 0; tj < NT; tj++)
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int r1 = 16 * tj + M::row(lk, t);
+        if (r1 < nr && r2 < nr) Yp[((int64_t)j3 * nr + r1) * nr + r2] = y[tj][t];
+      }
   }
 }
 
@@ -281,59 +303,75 @@ __device__ __forceinline__ void eval_box_body(const T* __restrict__ psi,
 }
 
 // ---------------------------------------------------------------------------
-// d = 3 evaluation, axes 1 and 2, one leaf per workgroup, one i3 slice per wave.
-// Z_s is stored [i3][r1][r2] (r2 fastest).  Per slice:
-//   W^T[r2][i1] = sum_r1 Z[r1][r2] E1[i1][r1]           (lanes run along r2: coalesced)
-//   u[i2][i1]   = sum_r2 E2[i2][r2] W^T[r2][i1]         (B operand chained from W^T)
+// d = 3 evaluation, axes 1 and 2, one plane per workgroup, one i3 slice per
+// wave.  Z_P is stored [i3][r1][r2] (r2 fastest).  Per slice and row:
+//   W^T[r2][i1] = sum_r1 Z_P[r1][r2] E1_row[i1][r1]       (lanes along r2: coalesced)
+// and per leaf s of the row:
+//   u_s[i2][i1] = sum_r2 E2_s[i2][r2] W^T[r2][i1]         (B operand chained from W^T)
 
 template <typename T, int NT>
-__device__ __forceinline__ void eval3_leaf_body(const T* __restrict__ Z,
-                                                  const int32_t* __restrict__ leaf_id,
-                                                  const int32_t* __restrict__ leaf_tab,
-                                                  const T* __restrict__ E, int p, int nr,
-                                                  double* __restrict__ u, int bid) {
+__device__ __forceinline__ void eval3_plane_body(const T* __restrict__ Z,
+                                                 const int32_t* __restrict__ leaf_id,
+                                                 const int32_t* __restrict__ leaf_tab,
+                                                 const int32_t* __restrict__ plane_row,
+                                                 const int32_t* __restrict__ row_start,
+                                                 const int32_t* __restrict__ row_tab,
+                                                 const T* __restrict__ E, int p, int nr,
+                                                 double* __restrict__ u, int bid) {
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
-  const int s = bid;
-  const int leaf = leaf_id[s];
+  const int P = bid;
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
-  const T* E1 = E + (int64_t)leaf_tab[s * 3 + 0] * p * nr;
-  const T* E2 = E + (int64_t)leaf_tab[s * 3 + 1] * p * nr;
-  T b1[Q], a2[Q];
+  const int rw0 = plane_row[P], rw1 = plane_row[P + 1];
+  const int64_t ppp = (int64_t)p * p * p;
+  // rows outer, slices inner: a slice's Z_P block is read once per row instead
+  // of being held in registers across rows
+  for (int rw = rw0; rw < rw1; rw++) {
+    const T* E1 = E + (int64_t)row_tab[rw] * p * nr;
+    T b1[Q];
 #pragma unroll
-  for (int q = 0; q < Q; q++) {
-    const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
-    const bool ok = lr < p && k < nr;
-    b1[q] = ld0<T>(E1, lr * nr + k, ok);  // B[r1][i1] = E1[i1][r1]
-    a2[q] = ld0<T>(E2, lr * nr + k, ok);  // A[i2][r2]
-  }
-  double* ul = u + (int64_t)leaf * p * p * p;
-  for (int i3 = w; i3 < p; i3 += 4) {
-    const T* Zs = Z + ((int64_t)s * p + i3) * nr * nr;
-    acc_t wt[NT];  // W^T, rows r2 (tile ti), columns i1
-#pragma unroll
-    for (int ti = 0; ti < NT; ti++) {
-      zero4(wt[ti]);
-      const int r2 = 16 * ti + lr;
-#pragma unroll
-      for (int q = 0; q < Q; q++) {
-        const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);  // r1
-        const T a = ld0<T>(Zs, k * nr + r2, r2 < nr && k < nr);
-        wt[ti] = M::step(a, b1[q], wt[ti]);
-      }
+    for (int q = 0; q < Q; q++) {
+      const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+      b1[q] = ld0<T>(E1, lr * nr + k, lr < p && k < nr);  // B[r1][i1] = E1[i1][r1]
     }
-    acc_t uu;
-    zero4(uu);
+    const int s0 = row_start[rw], s1 = row_start[rw + 1];
+    for (int i3 = w; i3 < p; i3 += 4) {
+      const T* Zs = Z + ((int64_t)P * p + i3) * nr * nr;
+      acc_t wt[NT];  // W^T, rows r2 (tile ti), columns i1
 #pragma unroll
-    for (int ti = 0; ti < NT; ti++)
+      for (int ti = 0; ti < NT; ti++) {
+        zero4(wt[ti]);
+        const int r2 = 16 * ti + lr;
 #pragma unroll
-      for (int kk = 0; kk < 4; kk++) uu = M::step(a2[4 * ti + kk], wt[ti][kk], uu);
+        for (int q = 0; q < Q; q++) {
+          const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);  // r1
+          const T a = ld0<T>(Zs, k * nr + r2, r2 < nr && k < nr);
+          wt[ti] = M::step(a, b1[q], wt[ti]);
+        }
+      }
+      for (int s = s0; s < s1; s++) {
+        const T* E2 = E + (int64_t)leaf_tab[s * 3 + 1] * p * nr;
+        T a2[Q];
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-      const int i2 = M::row(lk, t);
-      if (i2 < p && lr < p) ul[((int64_t)i3 * p + i2) * p + lr] = (double)uu[t];
+        for (int q = 0; q < Q; q++) {
+          const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+          a2[q] = ld0<T>(E2, lr * nr + k, lr < p && k < nr);  // A[i2][r2]
+        }
+        acc_t uu;
+        zero4(uu);
+#pragma unroll
+        for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+          for (int kk = 0; kk < 4; kk++) uu = M::step(a2[4 * ti + kk], wt[ti][kk], uu);
+        double* ul = u + (int64_t)leaf_id[s] * ppp;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int i2 = M::row(lk, t);
+          if (i2 < p && lr < p) ul[((int64_t)i3 * p + i2) * p + lr] = (double)uu[t];
+        }
+      }
     }
   }
 }
@@ -675,16 +713,17 @@ __device__ __forceinline__ int n2_of(int d, int nr) { return d == 3 ? nr * nr : 
 __device__ __forceinline__ uint32_t pmagic_of(int p) { return (uint32_t)((0x100000000ull + p - 1) / p); }
 
 template <typename T, int NT, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void form3_leaf(
+__global__ __launch_bounds__(256) void form3_plane(
     const double* __restrict__ sigma, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
-    const T* __restrict__ F, int p, int nr, T* __restrict__ Y) {
-  form3_leaf_body<T, NT, KS>(sigma, leaf_id, leaf_tab, F, p, nr, Y, blockIdx.x);
+    const int32_t* __restrict__ plane_row, const int32_t* __restrict__ row_start,
+    const int32_t* __restrict__ row_tab, const T* __restrict__ F, int p, int nr, T* __restrict__ Y) {
+  form3_plane_body<T, NT, KS>(sigma, leaf_id, leaf_tab, plane_row, row_start, row_tab, F, p, nr, Y, blockIdx.x);
 }
 template <typename T, int NT, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void form3_leaf_b(
-    FGT_BATCH_PARAMS) {
+__global__ __launch_bounds__(256) void form3_plane_b(FGT_BATCH_PARAMS) {
   FGT_BATCH_PROLOGUE
-  form3_leaf_body<T, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr, mptr<T>(a.Y), bid);
+  form3_plane_body<T, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
+                              cptr<T>(a.F), a.p, a.nr, mptr<T>(a.Y), bid);
 }
 
 template <typename T, int D, int NT, int KS>
@@ -698,7 +737,8 @@ template <typename T, int D, int NT, int KS>
 __global__ __launch_bounds__(256) void form_box_b(FGT_BATCH_PARAMS) {
   FGT_BATCH_PROLOGUE
   const int ncol128 = (n2_of(D, a.nr) + 127) / 128;
-  form_box_body<T, D, NT, KS>(cptr<T>(a.Y), a.fitem, a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr, ncol128,
+  form_box_body<T, D, NT, KS>(cptr<T>(a.Y), a.fitem, D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
+                              ncol128,
                               mptr<T>(a.phi), mptr<T>(a.partial), bid);
 }
 
@@ -727,21 +767,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
     FGT_BATCH_PARAMS) {
   FGT_BATCH_PROLOGUE
   const int ncol = (n2_of(D, a.nr) + 63) / 64;
-  eval_box_body<T, D, NT>(cptr<T>(a.psi), a.box_order, a.pw_start, a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr, ncol,
+  eval_box_body<T, D, NT>(cptr<T>(a.psi), a.box_order, D == 3 ? a.plane_start : a.pw_start,
+                          D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr, ncol,
                           pmagic_of(a.p), mptr<T>(a.Y), bid);
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval3_leaf(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1))) void eval3_plane(
     const T* __restrict__ Z, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
-    const T* __restrict__ E, int p, int nr, double* __restrict__ u) {
-  eval3_leaf_body<T, NT>(Z, leaf_id, leaf_tab, E, p, nr, u, blockIdx.x);
+    const int32_t* __restrict__ plane_row, const int32_t* __restrict__ row_start,
+    const int32_t* __restrict__ row_tab, const T* __restrict__ E, int p, int nr, double* __restrict__ u) {
+  eval3_plane_body<T, NT>(Z, leaf_id, leaf_tab, plane_row, row_start, row_tab, E, p, nr, u, blockIdx.x);
 }
 template <typename T, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval3_leaf_b(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1))) void eval3_plane_b(
     FGT_BATCH_PARAMS) {
   FGT_BATCH_PROLOGUE
-  eval3_leaf_body<T, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr, jobs[j].u, bid);
+  eval3_plane_body<T, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
+                          cptr<T>(a.E), a.p, a.nr, jobs[j].u, bid);
 }
 
 template <typename T, int KS>
@@ -822,12 +865,12 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
   const int64_t N2 = a.d == 3 ? nr * nr : nr;
   const bool pw = a.nL > 0;
   switch (stage) {
-    case kFormLeaf: return pw && a.d == 3 ? a.nL : 0;
+    case kFormLeaf: return pw && a.d == 3 ? a.nPl : 0;
     case kFormBox: return pw ? (a.d == 3 ? a.nFI * ((N2 + 127) / 128) : a.nFI) : 0;
     case kReduce: return pw && a.nFR > 0 ? a.nFR * ((N2 * nr + 255) / 256) : 0;
     case kTranslate: return pw ? translate_blocks(a) : 0;
     case kEvalBox: return pw && a.d == 3 ? a.nA * ((N2 + 63) / 64) : 0;
-    case kEvalLeaf: return pw ? (a.d == 3 ? a.nL : (a.nL + 3) / 4) : 0;
+    case kEvalLeaf: return pw ? (a.d == 3 ? a.nPl : (a.nL + 3) / 4) : 0;
     case kNear: return a.nT > 0 ? (a.d == 3 ? a.nT : (a.nT + 3) / 4) : 0;
     default: return 0;
   }
@@ -839,12 +882,12 @@ static void launch_batched_nt(int d, int stage, const BatchJob* jobs, const int3
   const dim3 g((unsigned)grid), b(256);
   if (d == 3) {
     switch (stage) {
-      case kFormLeaf: hipLaunchKernelGGL((form3_leaf_b<T, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kFormLeaf: hipLaunchKernelGGL((form3_plane_b<T, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kFormBox: hipLaunchKernelGGL((form_box_b<T, 3, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
       case kTranslate: launch_translate_batched<T>(3, jobs, start, count, njobs, grid, st); break;
       case kEvalBox: hipLaunchKernelGGL((eval_box_b<T, 3, NT>), g, b, 0, st, jobs, start, count, njobs); break;
-      case kEvalLeaf: hipLaunchKernelGGL((eval3_leaf_b<T, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kEvalLeaf: hipLaunchKernelGGL((eval3_plane_b<T, NT>), g, b, 0, st, jobs, start, count, njobs); break;
       case kNear: hipLaunchKernelGGL((near3_b<T, KS>), g, b, 0, st, jobs, start, count, njobs); break;
     }
   } else {
@@ -916,21 +959,21 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
   if (a.nL > 0) {
     if (D == 3) {
       const int N2 = nr * nr, ncol = (N2 + 63) / 64, ncol128 = (N2 + 127) / 128;
-      hipLaunchKernelGGL((form3_leaf<T, NT, KS>), dim3((unsigned)stage_blocks(a, kFormLeaf)), dim3(256), 0, st, sigma, a.pwleaf_id,
-                         a.pwleaf_tab, F, p, nr, Y);
+      hipLaunchKernelGGL((form3_plane<T, NT, KS>), dim3((unsigned)stage_blocks(a, kFormLeaf)), dim3(256), 0, st, sigma,
+                         a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, F, p, nr, Y);
       rec(1);
       hipLaunchKernelGGL((form_box<T, 3, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, Y,
-                         a.fitem, a.pwleaf_tab, F, p, nr, ncol128, phi, static_cast<T*>(a.partial));
+                         a.fitem, a.plane_tab, F, p, nr, ncol128, phi, static_cast<T*>(a.partial));
       launch_reduce<T>(a, st);
       rec(2);
       launch_translate<T>(a, st);
       rec(3);
       const uint32_t pmagic = (uint32_t)((0x100000000ull + p - 1) / p);  // ceil(2^32 / p)
       hipLaunchKernelGGL((eval_box<T, 3, NT>), dim3((unsigned)stage_blocks(a, kEvalBox)), dim3(256), 0, st, psi,
-                         a.box_order, a.pw_start, a.pwleaf_tab, E, p, nr, ncol, pmagic, Y);
+                         a.box_order, a.plane_start, a.plane_tab, E, p, nr, ncol, pmagic, Y);
       rec(4);
-      hipLaunchKernelGGL((eval3_leaf<T, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, Y, a.pwleaf_id,
-                         a.pwleaf_tab, E, p, nr, u);
+      hipLaunchKernelGGL((eval3_plane<T, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, Y,
+                         a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, E, p, nr, u);
       rec(5);
     } else {
       rec(1);

@@ -225,7 +225,11 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
   for (int32_t a = 0; a < nA; a++) hp.pwbox_isleaf[a] = lcbox[pwb[a]].isleaf;
 
   // ---- plane-wave leaves grouped by their cutoff box; form/eval table ids
-  struct PwLeaf { int32_t box; uint64_t m; int32_t id; };
+  // d = 3: within a box, leaves are ordered by (level, position on axis 3,
+  // position on axis 1, position on axis 2), so that a plane (leaves of one
+  // level sharing the axis-3 position, hence the axis-3 table) and a row of a
+  // plane (also sharing the axis-1 position and table) are contiguous ranges.
+  struct PwLeaf { int32_t box; uint64_t m; int32_t id; int32_t lv; };
   std::vector<PwLeaf> pl;
   for (int64_t i = 0; i < n; i++) {
     int l = level[i];
@@ -234,10 +238,20 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     for (int a = 0; a < d; a++) c[a] = coord[i * d + a] >> (l - lc);
     const LcBox& b = lcbox[lcmap[key(lc, c)]];
     if (!b.f) continue;
-    pl.push_back({b.idx, morton(&coord[i * d], d, lmax - l), (int32_t)i});
+    uint64_t m = morton(&coord[i * d], d, lmax - l);
+    int32_t lv = 0;
+    if (d == 3) {
+      const int sh = l - lc;  // < 21: positions take 21 bits each
+      auto rel = [&](int a) { return (uint64_t)(coord[i * d + a] - ((coord[i * d + a] >> sh) << sh)); };
+      m = (rel(2) << 42) | (rel(0) << 21) | rel(1);
+      lv = l;
+    }
+    pl.push_back({b.idx, m, (int32_t)i, lv});
   }
   std::sort(pl.begin(), pl.end(), [](const PwLeaf& x, const PwLeaf& y) {
-    return x.box != y.box ? x.box < y.box : x.m < y.m;
+    if (x.box != y.box) return x.box < y.box;
+    if (x.lv != y.lv) return x.lv < y.lv;
+    return x.m < y.m;
   });
   std::unordered_map<uint64_t, int32_t> ftab;  // (level, pos) -> id
   std::vector<int32_t> ftab_lv, ftab_pos;
@@ -272,16 +286,41 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
   hp.ftab_meta = ftab_lv;
   hp.ftab_meta.insert(hp.ftab_meta.end(), ftab_pos.begin(), ftab_pos.end());
 
-  // dispatch order of per-box work: most leaves first (longest work first)
+  // d = 3 planes and rows (see the leaf order above)
+  if (d == 3) {
+    hp.plane_start.assign(nA + 1, 0);
+    for (int32_t a = 0; a < nA; a++) {
+      for (int32_t s = hp.pw_start[a]; s < hp.pw_start[a + 1]; s++) {
+        const int32_t t3 = hp.pwleaf_tab[s * 3 + 2], t1 = hp.pwleaf_tab[s * 3 + 0];
+        const bool new_plane = s == hp.pw_start[a] || hp.pwleaf_tab[(s - 1) * 3 + 2] != t3;
+        const bool new_row = new_plane || hp.pwleaf_tab[(s - 1) * 3 + 0] != t1;
+        if (new_plane) {
+          hp.plane_row.push_back((int32_t)hp.row_tab.size());
+          hp.plane_tab.insert(hp.plane_tab.end(), {0, 0, t3});
+        }
+        if (new_row) {
+          hp.row_start.push_back(s);
+          hp.row_tab.push_back(t1);
+        }
+      }
+      hp.plane_start[a + 1] = (int32_t)hp.plane_row.size();
+    }
+    hp.plane_row.push_back((int32_t)hp.row_tab.size());
+    hp.row_start.push_back((int32_t)pl.size());
+  }
+  // the units the box-level stages run over: planes for d = 3, leaves otherwise
+  const std::vector<int32_t>& unit_start = d == 3 ? hp.plane_start : hp.pw_start;
+
+  // dispatch order of per-box work: most units first (longest work first)
   hp.box_order.resize(nA);
   for (int32_t a = 0; a < nA; a++) hp.box_order[a] = a;
   std::stable_sort(hp.box_order.begin(), hp.box_order.end(), [&](int32_t x, int32_t y) {
-    return hp.pw_start[x + 1] - hp.pw_start[x] > hp.pw_start[y + 1] - hp.pw_start[y];
+    return unit_start[x + 1] - unit_start[x] > unit_start[y + 1] - unit_start[y];
   });
 
-  // formation work items: at most kFormLeaves leaves each
+  // formation work items: at most kFormLeaves units each
   for (int32_t a = 0; a < nA; a++) {
-    const int32_t s0 = hp.pw_start[a], s1 = hp.pw_start[a + 1];
+    const int32_t s0 = unit_start[a], s1 = unit_start[a + 1];
     if (s1 - s0 <= kFormLeaves) {
       hp.fitem.insert(hp.fitem.end(), {a, s0, s1, -1});
       continue;

@@ -25,6 +25,13 @@ def _contract(mats, t):
     return t
 
 
+def _along(m, t, a, d):
+    """Apply matrix m (rows out, cols in) along axis a (0-based, axis 1 = a 0)
+    of a tensor stored [i_d, ..., i_1]."""
+    ax = d - 1 - a
+    return np.moveaxis(np.tensordot(m, t, axes=([1], [ax])), 0, ax)
+
+
 def _rot_matrix(nr, rot, dir_):
     R = np.zeros((nr, nr))
     R[0, 0] = 1.0
@@ -39,7 +46,12 @@ def _rot_matrix(nr, rot, dir_):
     return R
 
 
-def run(plan: api.Plan, sigma: np.ndarray) -> np.ndarray:
+def run(plan: api.Plan, sigma: np.ndarray, grouped: bool = False) -> np.ndarray:
+    """u of the plan's stages.  grouped (d = 3 only): formation and evaluation
+    walk the plan's planes and rows the way the device kernels do -- each
+    leaf's axis-2 table, then once per row the axis-1 table, then once per
+    plane the axis-3 table (and the reverse for evaluation) -- instead of
+    applying all tables per leaf."""
     info = plan.info()
     d, p, nr = info["dim"], info["p"], info["nr"]
     M = (nr + 1) // 2
@@ -62,10 +74,27 @@ def run(plan: api.Plan, sigma: np.ndarray) -> np.ndarray:
     u = np.zeros_like(sigma)
     shp = (p,) * d
     phi = np.zeros((nA,) + (nr,) * d)
-    for A in range(nA):
-        for s in range(pw_start[A], pw_start[A + 1]):
-            mats = [F[pwleaf_tab[s, a]] for a in range(d)]
-            phi[A] += _contract(mats, sigma[pwleaf_id[s]].reshape(shp))
+    if grouped:
+        assert d == 3
+        plane_start = plan.array("plane_start")
+        plane_tab = plan.array("plane_tab").reshape(-1, 3)
+        plane_row = plan.array("plane_row")
+        row_start = plan.array("row_start")
+        row_tab = plan.array("row_tab")
+        for A in range(nA):
+            for P in range(plane_start[A], plane_start[A + 1]):
+                Y = np.zeros((p, nr, nr))
+                for rw in range(plane_row[P], plane_row[P + 1]):
+                    X = np.zeros((p, nr, p))
+                    for s in range(row_start[rw], row_start[rw + 1]):
+                        X += _along(F[pwleaf_tab[s, 1]], sigma[pwleaf_id[s]].reshape(shp), 1, 3)
+                    Y += _along(F[row_tab[rw]], X, 0, 3)
+                phi[A] += _along(F[plane_tab[P, 2]], Y, 2, 3)
+    else:
+        for A in range(nA):
+            for s in range(pw_start[A], pw_start[A + 1]):
+                mats = [F[pwleaf_tab[s, a]] for a in range(d)]
+                phi[A] += _contract(mats, sigma[pwleaf_id[s]].reshape(shp))
     psi = np.zeros_like(phi)
     for A in range(nA):
         for q in range(plist_start[A], plist_start[A + 1]):
@@ -76,11 +105,21 @@ def run(plan: api.Plan, sigma: np.ndarray) -> np.ndarray:
                 code //= 3
             psi[A] += _contract(mats, phi[plist_src[q]])
     haspw = np.zeros(len(sigma), dtype=bool)
-    for A in range(nA):
-        for s in range(pw_start[A], pw_start[A + 1]):
-            mats = [E[pwleaf_tab[s, a]] for a in range(d)]
-            u[pwleaf_id[s]] = _contract(mats, psi[A]).reshape(-1)
-            haspw[pwleaf_id[s]] = True
+    if grouped:
+        for A in range(nA):
+            for P in range(plane_start[A], plane_start[A + 1]):
+                Z = _along(E[plane_tab[P, 2]], psi[A], 2, 3)
+                for rw in range(plane_row[P], plane_row[P + 1]):
+                    W = _along(E[row_tab[rw]], Z, 0, 3)
+                    for s in range(row_start[rw], row_start[rw + 1]):
+                        u[pwleaf_id[s]] = _along(E[pwleaf_tab[s, 1]], W, 1, 3).reshape(-1)
+                        haspw[pwleaf_id[s]] = True
+    else:
+        for A in range(nA):
+            for s in range(pw_start[A], pw_start[A + 1]):
+                mats = [E[pwleaf_tab[s, a]] for a in range(d)]
+                u[pwleaf_id[s]] = _contract(mats, psi[A]).reshape(-1)
+                haspw[pwleaf_id[s]] = True
     for t in range(len(near_tgt)):
         T = near_tgt[t]
         assert bool(near_haspw[t]) == bool(haspw[T])

@@ -329,3 +329,55 @@ def test_host_plan_matches_oracle(case):
     uo = oracle.oracle_u(lv, cs, p, delta, sig, periodic=per)
     uh = host_exec.run(_plan(lv, cs, p, delta, tol, periodic=per, force_lc=flc), sig)
     assert cf.rel_l2(uh, uo) < tol
+
+
+# ---------------------------------------------------------------------------
+# d = 3 planes and rows: the grouping the device formation/evaluation uses
+
+
+def _tree_3d_deep():
+    """A 3D tree whose leaves sit up to three levels below the cutoff level
+    (wide Gaussian, fine tree), so that planes and rows hold many leaves."""
+    dens = synth.GaussianSum(np.array([[0.1, -0.12, 0.05], [-0.2, 0.15, -0.1]]),
+                             np.array([0.03, 0.05]), np.array([1.0, -0.5]))
+    lv, cs = synth.resolve_tree(dens, 3, 4, 1e-6, max_level=5)
+    return lv, cs, synth.sample(lv, cs, 4, dens)
+
+
+def test_planes_and_rows_partition_the_pw_leaves():
+    lv, cs, _ = _tree_3d_deep()
+    pl = _plan(lv, cs, 4, 5e-2, 1e-6)
+    info = pl.info()
+    pw_start, tab = pl.array("pw_start"), pl.array("pwleaf_tab").reshape(-1, 3)
+    ps, pt = pl.array("plane_start"), pl.array("plane_tab").reshape(-1, 3)
+    pr, rs, rt = pl.array("plane_row"), pl.array("row_start"), pl.array("row_tab")
+    meta = pl.array("ftab_meta").reshape(2, -1)  # level, position of each table
+    pid = pl.array("pwleaf_id")
+    assert len(ps) == len(pw_start) and ps[0] == 0 and pr[0] == 0 and rs[0] == 0
+    assert rs[-1] == len(pid) and pr[-1] == len(rt) and ps[-1] == len(pr) - 1
+    assert len(pr) - 1 < len(rt) < len(pid)  # the tree does group leaves
+    for A in range(len(pw_start) - 1):
+        # the planes of box A cover exactly its pw leaves, in order
+        assert rs[pr[ps[A]]] == pw_start[A] and rs[pr[ps[A + 1]]] == pw_start[A + 1]
+        keys = set()
+        for P in range(ps[A], ps[A + 1]):
+            keys.add(int(pt[P, 2]))
+            for r in range(pr[P], pr[P + 1]):
+                leaves = range(rs[r], rs[r + 1])
+                assert len(leaves) > 0
+                assert all(tab[s, 2] == pt[P, 2] for s in leaves)   # one axis-3 table
+                assert all(tab[s, 0] == rt[r] for s in leaves)      # one axis-1 table
+                assert all(lv[pid[s]] == meta[0, pt[P, 2]] for s in leaves)  # one level
+        assert len(keys) == ps[A + 1] - ps[A]  # planes of a box are distinct
+    assert info["lc"] < lv.max() - 1
+
+
+def test_grouped_walk_equals_per_leaf_walk():
+    lv, cs, sig = _tree_3d_deep()
+    for delta, tol in ((5e-2, 1e-6), (1e-2, 1e-10)):
+        pl = _plan(lv, cs, 4, delta, tol)
+        a = host_exec.run(pl, sig)
+        b = host_exec.run(pl, sig, grouped=True)
+        assert cf.rel_l2(b, a) < 1e-13
+    uo = oracle.oracle_u(lv, cs, 4, 5e-2, sig)
+    assert cf.rel_l2(host_exec.run(_plan(lv, cs, 4, 5e-2, 1e-6), sig, grouped=True), uo) < 1e-6
