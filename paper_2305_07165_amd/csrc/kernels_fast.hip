@@ -33,18 +33,22 @@ namespace fgt {
 __device__ __forceinline__ int lane_of() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_of() { return threadIdx.x >> 6; }
 
+// r2 tiles per form3_plane work item: all of them while the y accumulators
+// (NT x TG tiles) stay small, fewer for large NT.
+__host__ __device__ constexpr int form3_tile_group(int nt) { return nt <= 4 ? nt : (nt == 5 ? 3 : 2); }
+
 template <typename T, int KS>
 struct Steps {
   static constexpr int value = std::is_same<T, float>::value ? 4 : KS;
 };
 
 // ---------------------------------------------------------------------------
-// d = 3 formation, axes 2 and 1, one plane per workgroup.  A plane is a run of
-// leaves of one cutoff box with the same level and axis-3 position; its rows
-// also share the axis-1 position (fgt_host.h).  By separability
+// d = 3 formation, axes 2 and 1, per plane.  A plane is a run of leaves of one
+// cutoff box with the same level and axis-3 position; its rows also share the
+// axis-1 position (fgt_host.h).  By separability
 //   Y_P[j3][r1][r2] = sum_rows F1_row[r1][j1] (sum_{s in row} sum_j2 sigma_s[j3][j2][j1] F2_s[r2][j2])
-// and the last axis then runs once per plane instead of once per leaf.  Work
-// items (j3 slice, r2 tile ti) are spread over the 4 waves; per item:
+// and the last axis then runs once per plane instead of once per leaf.  A wave
+// owns one item (j3 slice, group of TG r2 tiles); 4 items per workgroup:
 //   X^T[j1][r2] += sigma_s[j3] x F2_s      over the leaves of a row (lanes along j1)
 //   Y[r1][r2]   += F1_row x X^T            once per row (X^T chained as the B operand)
 
@@ -60,71 +64,86 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<T, KS>::value;
-  const int P = bid;
+  constexpr int TG = form3_tile_group(NT), NG = (NT + TG - 1) / TG;
+  const int nitem = p * NG, nsplit = (nitem + 3) / 4;
+  const int P = bid / nsplit;
   const int lane = lane_of(), w = wave_of();
+  const int item = (bid - P * nsplit) * 4 + w;
+  if (item >= nitem) return;
+  const int j3 = item / NG, t0 = (item - j3 * NG) * TG;
   const int lr = lane & 15, lk = lane >> 4;
   const int rw0 = plane_row[P], rw1 = plane_row[P + 1];
   const int s_begin = row_start[rw0], s_end = row_start[rw1];
   const int64_t ppp = (int64_t)p * p * p;
-  T* Yp = Y + (int64_t)P * p * nr * nr;
-  // operands of leaf s for slice j3 and r2 tile ti; masked loads (no branches)
-  auto load = [&](int s, int j3, int ti, T (&av)[S], T (&b2)[S]) {
+  // operands of leaf s; masked loads (no branches)
+  auto load = [&](int s, T (&av)[S], T (&b2)[TG][S]) {
     const bool ls = s < s_end;
     const int sc = ls ? s : s_begin;
     const double* sg = sigma + (int64_t)leaf_id[sc] * ppp;
     const T* F2 = F + (int64_t)leaf_tab[sc * 3 + 1] * nr * p;
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
-      const int k = M::kidx(kk, lk), r = 16 * ti + lr;
+      const int k = M::kidx(kk, lk);
       av[kk] = ld0<T>(sg, (j3 * p + k) * p + lr, ls && lr < p && k < p);  // A[j1][j2]
-      b2[kk] = ld0<T>(F2, r * p + k, ls && r < nr && k < p);            // B[j2][r2] = F2[r2][j2]
+#pragma unroll
+      for (int g = 0; g < TG; g++) {
+        const int r = 16 * (t0 + g) + lr;
+        b2[g][kk] = ld0<T>(F2, r * p + k, ls && r < nr && k < p);       // B[j2][r2] = F2[r2][j2]
+      }
     }
   };
-  const int nitem = p * NT;
-  for (int item = w; item < nitem; item += 4) {
-    const int j3 = item / NT, ti = item - j3 * NT;
-    acc_t y[NT];
+  acc_t y[NT][TG];
 #pragma unroll
-    for (int tj = 0; tj < NT; tj++) zero4(y[tj]);
-    T av[S], b2[S];
-    load(s_begin, j3, ti, av, b2);
-    int rw = rw0;
-    int row_end = row_start[rw0 + 1];
-    acc_t x;
-    zero4(x);
-    for (int s = s_begin; s < s_end; s++) {
-      T avn[S], b2n[S];
-      load(s + 1, j3, ti, avn, b2n);
+  for (int tj = 0; tj < NT; tj++)
 #pragma unroll
-      for (int kk = 0; kk < S; kk++) x = M::step(av[kk], b2[kk], x);
-      if (s + 1 == row_end) {
-        const T* F1 = F + (int64_t)row_tab[rw] * nr * p;
+    for (int g = 0; g < TG; g++) zero4(y[tj][g]);
+  acc_t x[TG];
 #pragma unroll
-        for (int tj = 0; tj < NT; tj++) {
+  for (int g = 0; g < TG; g++) zero4(x[g]);
+  T av[S], b2[TG][S];
+  load(s_begin, av, b2);
+  int rw = rw0;
+  int row_end = row_start[rw0 + 1];
+  for (int s = s_begin; s < s_end; s++) {
+    T avn[S], b2n[TG][S];
+    load(s + 1, avn, b2n);
 #pragma unroll
-          for (int kk = 0; kk < S; kk++) {
-            const int k = M::kidx(kk, lk), r = 16 * tj + lr;
-            const T a1 = ld0<T>(F1, r * p + k, r < nr && k < p);  // A[r1][j1]
-            y[tj] = M::step(a1, x[kk], y[tj]);
-          }
+    for (int g = 0; g < TG; g++)
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) x[g] = M::step(av[kk], b2[g][kk], x[g]);
+    if (s + 1 == row_end) {
+      const T* F1 = F + (int64_t)row_tab[rw] * nr * p;
+#pragma unroll
+      for (int tj = 0; tj < NT; tj++)
+#pragma unroll
+        for (int kk = 0; kk < S; kk++) {
+          const int k = M::kidx(kk, lk), r = 16 * tj + lr;
+          const T a1 = ld0<T>(F1, r * p + k, r < nr && k < p);  // A[r1][j1]
+#pragma unroll
+          for (int g = 0; g < TG; g++) y[tj][g] = M::step(a1, x[g][kk], y[tj][g]);
         }
-        zero4(x);
-        rw++;
-        if (rw < rw1) row_end = row_start[rw + 1];
-      }
 #pragma unroll
-      for (int kk = 0; kk < S; kk++) {
-        av[kk] = avn[kk];
-        b2[kk] = b2n[kk];
-      }
+      for (int g = 0; g < TG; g++) zero4(x[g]);
+      rw++;
+      if (rw < rw1) row_end = row_start[rw + 1];
     }
-    const int r2 = 16 * ti + lr;
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      av[kk] = avn[kk];
+#pragma unroll
+      for (int g = 0; g < TG; g++) b2[g][kk] = b2n[g][kk];
+    }
+  }
+  T* Yp = Y + (int64_t)P * p * nr * nr;
+#pragma unroll
+  for (int g = 0; g < TG; g++) {
+    const int r2 = 16 * (t0 + g) + lr;
 #pragma unroll
     for (int tj = 0; tj < NT; tj++)
 #pragma unroll
       for (int t = 0; t < 4; t++) {
         const int r1 = 16 * tj + M::row(lk, t);
-        if (r1 < nr && r2 < nr) Yp[((int64_t)j3 * nr + r1) * nr + r2] = y[tj][t];
+        if (r1 < nr && r2 < nr) Yp[((int64_t)j3 * nr + r1) * nr + r2] = y[tj][g][t];
       }
   }
 }
@@ -303,8 +322,9 @@ __device__ __forceinline__ void eval_box_body(const T* __restrict__ psi,
 }
 
 // ---------------------------------------------------------------------------
-// d = 3 evaluation, axes 1 and 2, one plane per workgroup, one i3 slice per
-// wave.  Z_P is stored [i3][r1][r2] (r2 fastest).  Per slice and row:
+// d = 3 evaluation, axes 1 and 2, one i3 slice of one plane per wave (a plane
+// spans ceil(p/4) workgroups).  Z_P is stored [i3][r1][r2] (r2 fastest).  Per
+// slice and row:
 //   W^T[r2][i1] = sum_r1 Z_P[r1][r2] E1_row[i1][r1]       (lanes along r2: coalesced)
 // and per leaf s of the row:
 //   u_s[i2][i1] = sum_r2 E2_s[i2][r2] W^T[r2][i1]         (B operand chained from W^T)
@@ -321,13 +341,15 @@ __device__ __forceinline__ void eval3_plane_body(const T* __restrict__ Z,
   typedef Mfma<T> M;
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
-  const int P = bid;
+  const int nsplit = (p + 3) / 4;
+  const int P = bid / nsplit;
   const int lane = lane_of(), w = wave_of();
+  const int i3 = (bid - P * nsplit) * 4 + w;
+  if (i3 >= p) return;
   const int lr = lane & 15, lk = lane >> 4;
   const int rw0 = plane_row[P], rw1 = plane_row[P + 1];
   const int64_t ppp = (int64_t)p * p * p;
-  // rows outer, slices inner: a slice's Z_P block is read once per row instead
-  // of being held in registers across rows
+  const T* Zs = Z + ((int64_t)P * p + i3) * nr * nr;
   for (int rw = rw0; rw < rw1; rw++) {
     const T* E1 = E + (int64_t)row_tab[rw] * p * nr;
     T b1[Q];
@@ -337,8 +359,7 @@ __device__ __forceinline__ void eval3_plane_body(const T* __restrict__ Z,
       b1[q] = ld0<T>(E1, lr * nr + k, lr < p && k < nr);  // B[r1][i1] = E1[i1][r1]
     }
     const int s0 = row_start[rw], s1 = row_start[rw + 1];
-    for (int i3 = w; i3 < p; i3 += 4) {
-      const T* Zs = Z + ((int64_t)P * p + i3) * nr * nr;
+    {
       acc_t wt[NT];  // W^T, rows r2 (tile ti), columns i1
 #pragma unroll
       for (int ti = 0; ti < NT; ti++) {
@@ -359,12 +380,17 @@ __device__ __forceinline__ void eval3_plane_body(const T* __restrict__ Z,
           const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
           a2[q] = ld0<T>(E2, lr * nr + k, lr < p && k < nr);  // A[i2][r2]
         }
-        acc_t uu;
-        zero4(uu);
+        acc_t u0, u1;  // two accumulation chains, summed at the end
+        zero4(u0);
+        zero4(u1);
 #pragma unroll
         for (int ti = 0; ti < NT; ti++)
 #pragma unroll
-          for (int kk = 0; kk < 4; kk++) uu = M::step(a2[4 * ti + kk], wt[ti][kk], uu);
+          for (int kk = 0; kk < 4; kk++) {
+            if (kk & 1) u1 = M::step(a2[4 * ti + kk], wt[ti][kk], u1);
+            else u0 = M::step(a2[4 * ti + kk], wt[ti][kk], u0);
+          }
+        const acc_t uu = u0 + u1;
         double* ul = u + (int64_t)leaf_id[s] * ppp;
 #pragma unroll
         for (int t = 0; t < 4; t++) {
@@ -865,12 +891,16 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
   const int64_t N2 = a.d == 3 ? nr * nr : nr;
   const bool pw = a.nL > 0;
   switch (stage) {
-    case kFormLeaf: return pw && a.d == 3 ? a.nPl : 0;
+    case kFormLeaf: {
+      if (!pw || a.d != 3) return 0;
+      const int nt = kernel_class(a).nt, tg = form3_tile_group(nt);
+      return a.nPl * ((a.p * ((nt + tg - 1) / tg) + 3) / 4);
+    }
     case kFormBox: return pw ? (a.d == 3 ? a.nFI * ((N2 + 127) / 128) : a.nFI) : 0;
     case kReduce: return pw && a.nFR > 0 ? a.nFR * ((N2 * nr + 255) / 256) : 0;
     case kTranslate: return pw ? translate_blocks(a) : 0;
     case kEvalBox: return pw && a.d == 3 ? a.nA * ((N2 + 63) / 64) : 0;
-    case kEvalLeaf: return pw ? (a.d == 3 ? a.nPl : (a.nL + 3) / 4) : 0;
+    case kEvalLeaf: return pw ? (a.d == 3 ? a.nPl * ((a.p + 3) / 4) : (a.nL + 3) / 4) : 0;
     case kNear: return a.nT > 0 ? (a.d == 3 ? a.nT : (a.nT + 3) / 4) : 0;
     default: return 0;
   }
