@@ -36,10 +36,36 @@ PEAK_HBM = 8.0e12     # bytes/s
 STAGES = ("form_leaf", "form_box", "translate", "eval_box", "eval_leaf", "near")
 
 
-def stage_work(info: dict) -> dict:
+def near_runs(plan) -> tuple:
+    """(sources, (axis-3, axis-1) table runs, axis-3 table runs) summed over
+    the near-field targets: the contraction counts of the near stage, which
+    applies the axis-2 table per source, the axis-1 table once per run of
+    sources sharing the axis-3 and axis-1 tables, and the axis-3 table once per
+    run sharing the axis-3 table (d = 2: axis 1 per source, axis 2 per run)."""
+    import numpy as np
+    info = plan.info()
+    d = info["dim"]
+    st = plan.array("near_start")
+    tab = plan.array("near_tab").reshape(-1, d)
+    r_a = r_b = 0
+    for t in range(len(st) - 1):
+        q = tab[st[t]:st[t + 1]]
+        if len(q) == 0:
+            continue
+        if d == 3:
+            r_a += 1 + int(np.count_nonzero((q[1:, 2] != q[:-1, 2]) | (q[1:, 0] != q[:-1, 0])))
+            r_b += 1 + int(np.count_nonzero(q[1:, 2] != q[:-1, 2]))
+        else:
+            r_a += 1 + int(np.count_nonzero(q[1:, 1] != q[:-1, 1]))
+    return len(tab), r_a, r_b
+
+
+def stage_work(info: dict, runs=None) -> dict:
     """Algorithmic flops and bytes per launch of every stage (real plane-wave
-    basis, separable contractions).  bytes are the HBM bytes the stage must
-    move at minimum in this design."""
+    basis, separable contractions, each 1D table applied once per group of
+    leaves that shares it).  bytes are the HBM bytes the stage must move at
+    minimum in this design.  runs: near_runs() of the plan (None: every near
+    pair applies all d tables)."""
     d, p, nr = info["dim"], info["p"], info["nr"]
     nL, nA, nP, nN = info["n_pwleaf"], info["n_pwbox"], info["n_plist"], info["n_near_pair"]
     ts = 4 if info["precision"] == 1 else 8
@@ -62,8 +88,12 @@ def stage_work(info: dict) -> dict:
         "translate": {"flops": (3.0 * d + 1) * nr ** d * nP, "bytes": 2.0 * ts * nA * nr ** d},
         "eval_box": {"flops": last, "bytes": ts * nA * nr ** d + ts * nU * p * n2},
         "eval_leaf": {"flops": lead, "bytes": ts * nU * p * n2 + 8.0 * npw},
-        "near": {"flops": 2.0 * d * p ** (d + 1) * nN,
-                 "bytes": 8.0 * (npts - npw + info["n_near_target"] * p ** d)},
+        # sigma of every distinct source once; u of every target written (and
+        # read first where the plane-wave evaluation already wrote it)
+        "near": {"flops": (2.0 * d * p ** (d + 1) * nN if runs is None else
+                           2.0 * p ** (d + 1) * sum(runs)),
+                 "bytes": 8.0 * p ** d * (info["n_near_source"] + info["n_near_target"]
+                                          + info["n_near_haspw"])},
     }
 
 
@@ -228,8 +258,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--cpu-leaves", type=int, default=1024,
-                    help="target leaves in the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--cpu-leaves", type=int, default=-1,
+                    help="target leaves in the CPU-oracle sample (-1 = every leaf, 0 = skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the tol=1e-10 and FP32 lines")
     ap.add_argument("--no-serve", action="store_true", help="skip the served form")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
@@ -307,7 +337,7 @@ def main():
             acc[k] += v
     stage_ms = {k: v / args.steps for k, v in acc.items()}
     pplan.close()
-    work = stage_work(info)
+    work = stage_work(info, near_runs(plan))
     dom = max(stage_ms, key=stage_ms.get)
     wd = work[dom]
     t_dom = stage_ms[dom] * 1e-3
@@ -350,10 +380,10 @@ def main():
 
     cpu = None
     accuracy = {}
-    if args.cpu_leaves > 0:
+    if args.cpu_leaves != 0:
         import oracle
         rng = np.random.default_rng(12345)
-        nt = min(args.cpu_leaves, len(pr.levels))
+        nt = len(pr.levels) if args.cpu_leaves < 0 else min(args.cpu_leaves, len(pr.levels))
         tg = np.sort(rng.choice(len(pr.levels), nt, replace=False))
         log(f"cpu oracle on {nt} target leaves")
         tc = time.perf_counter()

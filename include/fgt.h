@@ -87,6 +87,8 @@ typedef struct fgt_info {
   int64_t n_plane, n_row; /* d = 3: plane-wave leaves grouped by (box, level, axis-3
                             position) and, within those, by axis-1 position; formation and
                             evaluation apply each 1D table once per group; 0 for d < 3 */
+  int64_t n_near_source; /* distinct leaves that are near-field sources */
+  int64_t n_near_haspw;  /* near-field targets that also receive a plane-wave evaluation */
 } fgt_info_t;
 
 typedef struct fgt_plan fgt_plan_t;

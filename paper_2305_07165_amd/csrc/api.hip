@@ -380,6 +380,15 @@ int fgt_plan_info(const fgt_plan_t* pl, fgt_info_t* info) {
   info->flops_eval = fe;
   info->n_plane = hp.n_plane();
   info->n_row = hp.n_row();
+  {
+    std::vector<char> seen(hp.nleaves, 0);
+    int64_t ns = 0;
+    for (int32_t sidx : hp.near_src) ns += !seen[sidx], seen[sidx] = 1;
+    info->n_near_source = ns;
+    int64_t nh = 0;
+    for (int32_t h : hp.near_haspw) nh += h != 0;
+    info->n_near_haspw = nh;
+  }
   info->flops_translate = (3.0 * hp.d + 1.0) * ipowd(hp.nr, hp.d) * hp.n_plist();
   info->flops_near = 2.0 * hp.d * ipowd(hp.p, hp.d + 1) * hp.n_near_pair();
   const double ts = hp.precision == FGT_FP32 ? 4.0 : 8.0;
