@@ -49,6 +49,10 @@ extern "C" {
 #define FGT_FP64 0 /* every contraction in FP64 */
 #define FGT_FP32 1 /* contractions and expansions in FP32 with FP32 accumulation;
                       tables are built in FP64 and rounded once; sigma/u stay FP64 */
+#define FGT_BF16X3 2 /* as FGT_FP32, but every matrix product runs as three bf16
+                        matrix-core products of hi/lo splits of its FP32 operands
+                        (the lo x lo term dropped), accumulated in FP32; translations
+                        stay FP32.  About 1e-5 relative error per product */
 
 typedef struct fgt_tree {
   int32_t dim;           /* 1, 2 or 3 */
@@ -58,7 +62,7 @@ typedef struct fgt_tree {
 } fgt_tree_t;
 
 typedef struct fgt_opts {
-  int32_t precision;     /* FGT_FP64 (default) or FGT_FP32 */
+  int32_t precision;     /* FGT_FP64 (default), FGT_FP32 or FGT_BF16X3 */
   double eps_internal;   /* plane-wave tolerance eps of Theorem 1; 0 = derived from tol */
   int32_t force_lc;      /* -1 = automatic cutoff level; else a level <= the automatic one */
   void* stream;          /* hipStream_t for fgt_execute; NULL = the HIP default stream */

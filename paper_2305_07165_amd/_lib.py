@@ -24,6 +24,7 @@ FGT_FREE = 0
 FGT_PERIODIC = 1
 FGT_FP64 = 0
 FGT_FP32 = 1
+FGT_BF16X3 = 2
 
 EXPORTED = ["fgt_plan", "fgt_execute", "fgt_sync", "fgt_plan_info", "fgt_stage_times",
             "fgt_destroy", "fgt_strerror", "fgt_last_error", "fgt_pw_terms",

@@ -83,7 +83,7 @@ double ipowd(double b, int e) {
 }  // namespace
 
 int64_t fgt::plan_device_bytes(const HostPlan& hp) {
-  const int64_t ts = hp.precision == FGT_FP32 ? 4 : 8;
+  const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
   int64_t n2 = 1;
   for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
   const int64_t ncoef = n2 * hp.nr;
@@ -98,7 +98,7 @@ int64_t fgt::plan_device_bytes(const HostPlan& hp) {
 }
 
 int64_t fgt::plan_workspace_bytes(const HostPlan& hp) {
-  const int64_t ts = hp.precision == FGT_FP32 ? 4 : 8;
+  const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
   int64_t n2 = 1;
   for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
   const int64_t ncoef = n2 * hp.nr;
@@ -114,7 +114,7 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   fgt::HostPlan& hp = pl->hp;
   hipError_t e = hipGetDevice(&pl->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  const bool fp32 = hp.precision == FGT_FP32;
+  const bool fp32 = hp.precision != FGT_FP64;
   const size_t ts = fp32 ? sizeof(float) : sizeof(double);
   int lds_max = 0;
   e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
@@ -130,6 +130,7 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   a.nr = hp.nr;
   a.M = hp.pw.M;
   a.fp32 = fp32;
+  a.bf3 = hp.precision == FGT_BF16X3;
   a.nA = hp.n_pwbox();
   a.nL = hp.n_pwleaf();
   a.nE = (int64_t)hp.echunk.size() / 3;
@@ -238,7 +239,7 @@ int fgt::plan_unload(fgt_plan_t* pl) {
 int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem) {
   if (!pl || pl->host_only || !args || !mem) return fail(FGT_ERR_INVALID_ARG, "plan is not resident");
   const fgt::HostPlan& hp = pl->hp;
-  const int64_t ts = hp.precision == FGT_FP32 ? 4 : 8;
+  const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
   const int64_t bytes = plan_workspace_bytes(hp);
   void* m = nullptr;
   hipError_t e = hipMalloc(&m, (size_t)std::max<int64_t>(bytes, 256));
@@ -391,7 +392,7 @@ int fgt_plan_info(const fgt_plan_t* pl, fgt_info_t* info) {
   }
   info->flops_translate = (3.0 * hp.d + 1.0) * ipowd(hp.nr, hp.d) * hp.n_plist();
   info->flops_near = 2.0 * hp.d * ipowd(hp.p, hp.d + 1) * hp.n_near_pair();
-  const double ts = hp.precision == FGT_FP32 ? 4.0 : 8.0;
+  const double ts = hp.precision != FGT_FP64 ? 4.0 : 8.0;
   info->bytes_min = 16.0 * hp.nleaves * pd + 4.0 * ts * ipowd(hp.nr, hp.d) * hp.n_pwbox();
   info->device_bytes = pl->host_only ? fgt::plan_device_bytes(hp) : pl->device_bytes;
   return FGT_OK;

@@ -12,7 +12,8 @@ namespace fgt {
 
 struct DeviceArgs {
   int d = 0, p = 0, nr = 0, M = 0;
-  bool fp32 = false;
+  bool fp32 = false;  // FP32 storage (FP32 or BF16x3 products)
+  bool bf3 = false;   // products as split bf16 matrix-core steps (Bf16x3 in mfma.h)
   int64_t nA = 0, nL = 0, nE = 0, nT = 0;
   // tables (compute precision)
   const void *F = nullptr, *E = nullptr, *V = nullptr, *rot = nullptr;
@@ -49,14 +50,16 @@ struct BatchJob {
 enum Stage { kFormLeaf = 0, kFormBox, kReduce, kTranslate, kEvalBox, kEvalLeaf, kNear, kNumStages };
 
 // Transforms of one kernel class share every kernel instantiation: dimension,
-// compute precision, mode tiles per axis NT = ceil(nr/16), node steps KS.
+// compute precision (FP64, FP32, BF16x3), mode tiles per axis NT = ceil(nr/16),
+// node steps KS.
 struct KernelClass {
   int d = 0;
-  bool fp32 = false;
+  bool fp32 = false, bf3 = false;
   int nt = 0, ks = 0;
   bool operator<(const KernelClass& o) const {
     if (d != o.d) return d < o.d;
     if (fp32 != o.fp32) return fp32 < o.fp32;
+    if (bf3 != o.bf3) return bf3 < o.bf3;
     if (nt != o.nt) return nt < o.nt;
     return ks < o.ks;
   }

@@ -37,9 +37,9 @@ __device__ __forceinline__ int wave_of() { return threadIdx.x >> 6; }
 // (NT x TG tiles) stay small, fewer for large NT.
 __host__ __device__ constexpr int form3_tile_group(int nt) { return nt <= 4 ? nt : (nt == 5 ? 3 : 2); }
 
-template <typename T, int KS>
+template <typename C, int KS>
 struct Steps {
-  static constexpr int value = std::is_same<T, float>::value ? 4 : KS;
+  static constexpr int value = std::is_same<C, double>::value ? KS : 4;
 };
 
 // ---------------------------------------------------------------------------
@@ -52,18 +52,19 @@ struct Steps {
 //   X^T[j1][r2] += sigma_s[j3] x F2_s      over the leaves of a row (lanes along j1)
 //   Y[r1][r2]   += F1_row x X^T            once per row (X^T chained as the B operand)
 
-template <typename T, int NT, int KS>
+template <typename C, int NT, int KS>
 __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigma,
                                                  const int32_t* __restrict__ leaf_id,
                                                  const int32_t* __restrict__ leaf_tab,
                                                  const int32_t* __restrict__ plane_row,
                                                  const int32_t* __restrict__ row_start,
                                                  const int32_t* __restrict__ row_tab,
-                                                 const T* __restrict__ F, int p, int nr,
-                                                 T* __restrict__ Y, int bid) {
-  typedef Mfma<T> M;
+                                                 const elem_t<C>* __restrict__ F, int p, int nr,
+                                                 elem_t<C>* __restrict__ Y, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<T, KS>::value;
+  constexpr int S = Steps<C, KS>::value;
   constexpr int TG = form3_tile_group(NT), NG = (NT + TG - 1) / TG;
   const int nitem = p * NG, nsplit = (nitem + 3) / 4;
   const int P = bid / nsplit;
@@ -109,19 +110,25 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
     load(s + 1, avn, b2n);
 #pragma unroll
     for (int g = 0; g < TG; g++)
-#pragma unroll
-      for (int kk = 0; kk < S; kk++) x[g] = M::step(av[kk], b2[g][kk], x[g]);
+      x[g] = M::template steps<S>(av, b2[g], x[g]);
     if (s + 1 == row_end) {
       const T* F1 = F + (int64_t)row_tab[rw] * nr * p;
 #pragma unroll
-      for (int tj = 0; tj < NT; tj++)
+      for (int tj = 0; tj < NT; tj++) {
+        T a1[S];
 #pragma unroll
         for (int kk = 0; kk < S; kk++) {
           const int k = M::kidx(kk, lk), r = 16 * tj + lr;
-          const T a1 = ld0<T>(F1, r * p + k, r < nr && k < p);  // A[r1][j1]
-#pragma unroll
-          for (int g = 0; g < TG; g++) y[tj][g] = M::step(a1, x[g][kk], y[tj][g]);
+          a1[kk] = ld0<T>(F1, r * p + k, r < nr && k < p);  // A[r1][j1]
         }
+#pragma unroll
+        for (int g = 0; g < TG; g++) {
+          T xb[S];
+#pragma unroll
+          for (int kk = 0; kk < S; kk++) xb[kk] = x[g][kk];
+          y[tj][g] = M::template steps<S>(a1, xb, y[tj][g]);
+        }
+      }
 #pragma unroll
       for (int g = 0; g < TG; g++) zero4(x[g]);
       rw++;
@@ -151,18 +158,19 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
 // ---------------------------------------------------------------------------
 // last-axis formation merged over the leaves of a cutoff box (a grouped GEMM)
 
-template <typename T, int D, int NT, int KS>
-__device__ __forceinline__ void form_box_body(const T* __restrict__ Y,
+template <typename C, int D, int NT, int KS>
+__device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
                                                 const int32_t* __restrict__ fitem,
                                                 const int32_t* __restrict__ leaf_tab,
-                                                const T* __restrict__ F, int p, int nr,
-                                                int ncoltiles, T* __restrict__ phi,
-                                                T* __restrict__ partial, int bid) {
+                                                const elem_t<C>* __restrict__ F, int p, int nr,
+                                                int ncoltiles, elem_t<C>* __restrict__ phi,
+                                                elem_t<C>* __restrict__ partial, int bid) {
+  typedef elem_t<C> T;
   // one work item (<= kFormLeaves leaves of a box) x 128 columns per workgroup;
   // every wave owns two 16-column slabs, sharing the table operand between them
-  typedef Mfma<T> M;
+  typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<T, KS>::value;
+  constexpr int S = Steps<C, KS>::value;
   const int item = bid / ncoltiles;
   const int ct = bid % ncoltiles;
   const int A = fitem[4 * item], slot = fitem[4 * item + 3];
@@ -208,11 +216,13 @@ __device__ __forceinline__ void form_box_body(const T* __restrict__ Y,
     T an[NT][S], bn[S][2];
     load(s + 1, an, bn);
 #pragma unroll
-    for (int kk = 0; kk < S; kk++)
+    for (int h = 0; h < 2; h++) {
+      T bh[S];
 #pragma unroll
-      for (int ti = 0; ti < NT; ti++)
+      for (int kk = 0; kk < S; kk++) bh[kk] = b[kk][h];
 #pragma unroll
-        for (int h = 0; h < 2; h++) acc[ti][h] = M::step(a[ti][kk], b[kk][h], acc[ti][h]);
+      for (int ti = 0; ti < NT; ti++) acc[ti][h] = M::template steps<S>(a[ti], bh, acc[ti][h]);
+    }
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
       b[kk][0] = bn[kk][0];
@@ -255,15 +265,16 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 // walks the stacked leaf rows (s*p + i) two 16-row tiles at a time.  Boxes are
 // visited in the order box_order (most leaves first).
 
-template <typename T, int D, int NT>
-__device__ __forceinline__ void eval_box_body(const T* __restrict__ psi,
+template <typename C, int D, int NT>
+__device__ __forceinline__ void eval_box_body(const elem_t<C>* __restrict__ psi,
                                                 const int32_t* __restrict__ box_order,
                                                 const int32_t* __restrict__ pw_start,
                                                 const int32_t* __restrict__ leaf_tab,
-                                                const T* __restrict__ E, int p, int nr,
+                                                const elem_t<C>* __restrict__ E, int p, int nr,
                                                 int ncoltiles, uint32_t pmagic,
-                                                T* __restrict__ Z, int bid) {
-  typedef Mfma<T> M;
+                                                elem_t<C>* __restrict__ Z, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
   const int A = box_order[bid / ncoltiles];
@@ -303,12 +314,19 @@ __device__ __forceinline__ void eval_box_body(const T* __restrict__ psi,
     tnext[0] = tab_of(rt + 32 + lr);
     tnext[1] = tab_of(rt + 48 + lr);
 #pragma unroll
-    for (int q = 0; q < Q; q++) {
-      const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+    for (int g = 0; g < NT; g++) {
+      T bq[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) bq[kk] = b[4 * g + kk];
 #pragma unroll
       for (int h = 0; h < 2; h++) {
-        const T a = ld0<T>(E, eoff[h] + k, ok[h] && k < nr);
-        acc[h] = M::step(a, b[q], acc[h]);
+        T aq[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
+          const int k = 16 * g + M::kidx(kk, lk);
+          aq[kk] = ld0<T>(E, eoff[h] + k, ok[h] && k < nr);
+        }
+        acc[h] = M::template steps<4>(aq, bq, acc[h]);
       }
     }
 #pragma unroll
@@ -329,16 +347,17 @@ __device__ __forceinline__ void eval_box_body(const T* __restrict__ psi,
 // and per leaf s of the row:
 //   u_s[i2][i1] = sum_r2 E2_s[i2][r2] W^T[r2][i1]         (B operand chained from W^T)
 
-template <typename T, int NT>
-__device__ __forceinline__ void eval3_plane_body(const T* __restrict__ Z,
+template <typename C, int NT>
+__device__ __forceinline__ void eval3_plane_body(const elem_t<C>* __restrict__ Z,
                                                  const int32_t* __restrict__ leaf_id,
                                                  const int32_t* __restrict__ leaf_tab,
                                                  const int32_t* __restrict__ plane_row,
                                                  const int32_t* __restrict__ row_start,
                                                  const int32_t* __restrict__ row_tab,
-                                                 const T* __restrict__ E, int p, int nr,
+                                                 const elem_t<C>* __restrict__ E, int p, int nr,
                                                  double* __restrict__ u, int bid) {
-  typedef Mfma<T> M;
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
   const int nsplit = (p + 3) / 4;
@@ -366,10 +385,15 @@ __device__ __forceinline__ void eval3_plane_body(const T* __restrict__ Z,
         zero4(wt[ti]);
         const int r2 = 16 * ti + lr;
 #pragma unroll
-        for (int q = 0; q < Q; q++) {
-          const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);  // r1
-          const T a = ld0<T>(Zs, k * nr + r2, r2 < nr && k < nr);
-          wt[ti] = M::step(a, b1[q], wt[ti]);
+        for (int g = 0; g < NT; g++) {
+          T aq[4], bq[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; kk++) {
+            const int k = 16 * g + M::kidx(kk, lk);  // r1
+            aq[kk] = ld0<T>(Zs, k * nr + r2, r2 < nr && k < nr);
+            bq[kk] = b1[4 * g + kk];
+          }
+          wt[ti] = M::template steps<4>(aq, bq, wt[ti]);
         }
       }
       for (int s = s0; s < s1; s++) {
@@ -384,12 +408,16 @@ __device__ __forceinline__ void eval3_plane_body(const T* __restrict__ Z,
         zero4(u0);
         zero4(u1);
 #pragma unroll
-        for (int ti = 0; ti < NT; ti++)
+        for (int ti = 0; ti < NT; ti++) {
+          T aq[4], bq[4];
 #pragma unroll
           for (int kk = 0; kk < 4; kk++) {
-            if (kk & 1) u1 = M::step(a2[4 * ti + kk], wt[ti][kk], u1);
-            else u0 = M::step(a2[4 * ti + kk], wt[ti][kk], u0);
+            aq[kk] = a2[4 * ti + kk];
+            bq[kk] = wt[ti][kk];
           }
+          if (ti & 1) u1 = M::template steps<4>(aq, bq, u1);
+          else u0 = M::template steps<4>(aq, bq, u0);
+        }
         const acc_t uu = u0 + u1;
         double* ul = u + (int64_t)leaf_id[s] * ppp;
 #pragma unroll
@@ -410,18 +438,19 @@ __device__ __forceinline__ void eval3_plane_body(const T* __restrict__ Z,
 //   level B  U[j3][i1][i2]   += sum_j1 V1[i1][j1] T^T[j3][j1][i2]    (chained)
 //   level C  u[i3][i2][i1]   += sum_j3 V3[i3][j3] U[j3][i1][i2]      (j3 spans waves: LDS)
 
-template <typename T, int KS>
+template <typename C, int KS>
 __device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
                                              const int32_t* __restrict__ near_tgt,
                                              const int32_t* __restrict__ near_haspw,
                                              const int32_t* __restrict__ near_start,
                                              const int32_t* __restrict__ near_src,
                                              const int32_t* __restrict__ near_tab,
-                                             const T* __restrict__ V, int p,
+                                             const elem_t<C>* __restrict__ V, int p,
                                              double* __restrict__ u, int bid) {
-  typedef Mfma<T> M;
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<T, KS>::value;
+  constexpr int S = Steps<C, KS>::value;
   constexpr int RS = 17;            // padded i2 stride of the LDS tile
   constexpr int US = 16 * RS + 4;   // padded j3 stride
   __shared__ T Us[16 * US];         // U[j3][i2][i1]
@@ -461,8 +490,7 @@ __device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
     }
 #pragma unroll
     for (int c = 0; c < KS; c++)
-#pragma unroll
-      for (int kk = 0; kk < S; kk++) tacc[c] = M::step(av[c][kk], b2[kk], tacc[c]);
+      tacc[c] = M::template steps<S>(av[c], b2, tacc[c]);
     const bool last = q + 1 == q1;
     const bool end1 = last || near_tab[q * 3 + 5] != t3 || near_tab[q * 3 + 3] != t1;
     const bool end3 = last || near_tab[q * 3 + 5] != t3;
@@ -476,8 +504,12 @@ __device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
       }
 #pragma unroll
       for (int c = 0; c < KS; c++) {
+        {
+          T tb[S];
 #pragma unroll
-        for (int kk = 0; kk < S; kk++) uacc[c] = M::step(a1[kk], tacc[c][kk], uacc[c]);
+          for (int kk = 0; kk < S; kk++) tb[kk] = tacc[c][kk];
+          uacc[c] = M::template steps<S>(a1, tb, uacc[c]);
+        }
         zero4(tacc[c]);
       }
     }
@@ -503,13 +535,14 @@ __device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
 #pragma unroll
       for (int c = 0; c < KS; c++) {
         const int i2 = w + 4 * c;  // column tile (i2, i1 = lr); rows i2 >= p are never stored
+        T bq[S];
 #pragma unroll
         for (int kk = 0; kk < S; kk++) {
           const int j3 = M::kidx(kk, lk);
           const T uv = Us[j3 < p && i2 < p ? j3 * US + i2 * RS + lr : 0];  // LDS: select, no branch
-          const T b = j3 < p ? uv : (T)0;
-          oacc[c] = M::step(a3[kk], b, oacc[c]);
+          bq[kk] = j3 < p ? uv : (T)0;
         }
+        oacc[c] = M::template steps<S>(a3, bq, oacc[c]);
       }
     }
   }
@@ -540,16 +573,17 @@ __device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
 // d = 2: formation of a whole cutoff box, both axes, leaves in sequence.
 // Waves split the r1 tiles; every wave keeps all r2 tiles of its columns.
 
-template <typename T, int NT, int KS>
+template <typename C, int NT, int KS>
 __device__ __forceinline__ void form2_box_body(const double* __restrict__ sigma,
                                                  const int32_t* __restrict__ fitem,
                                                  const int32_t* __restrict__ leaf_id,
                                                  const int32_t* __restrict__ leaf_tab,
-                                                 const T* __restrict__ F, int p, int nr,
-                                                 T* __restrict__ phi, T* __restrict__ partial, int bid) {
-  typedef Mfma<T> M;
+                                                 const elem_t<C>* __restrict__ F, int p, int nr,
+                                                 elem_t<C>* __restrict__ phi, elem_t<C>* __restrict__ partial, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<T, KS>::value;
+  constexpr int S = Steps<C, KS>::value;
   constexpr int TW = (NT + 3) / 4;  // r1 tiles per wave
   const int item = bid;
   const int A = fitem[4 * item], slot = fitem[4 * item + 3];
@@ -583,17 +617,19 @@ __device__ __forceinline__ void form2_box_body(const double* __restrict__ sigma,
         // X[j2][r1] = sum_j1 sigma[j2][j1] F1[r1][j1]
         acc_t x;
         zero4(x);
+        T bq[S];
 #pragma unroll
         for (int kk = 0; kk < S; kk++) {
           const int k = M::kidx(kk, lk), r = 16 * tj + lr;
-          const T b = ld0<T>(F1, r * p + k, r < nr && k < p);
-          x = M::step(av[kk], b, x);
+          bq[kk] = ld0<T>(F1, r * p + k, r < nr && k < p);
         }
+        x = M::template steps<S>(av, bq, x);
         // phi[r2][r1] += sum_j2 F2[r2][j2] X[j2][r1]
+        T xb[S];
 #pragma unroll
-        for (int ti = 0; ti < NT; ti++)
+        for (int kk = 0; kk < S; kk++) xb[kk] = x[kk];
 #pragma unroll
-          for (int kk = 0; kk < S; kk++) acc[ti][c] = M::step(a2[ti][kk], x[kk], acc[ti][c]);
+        for (int ti = 0; ti < NT; ti++) acc[ti][c] = M::template steps<S>(a2[ti], xb, acc[ti][c]);
       }
     }
   }
@@ -615,14 +651,15 @@ __device__ __forceinline__ void form2_box_body(const double* __restrict__ sigma,
 }
 
 // d = 2: evaluation of one leaf per wave from its box's incoming expansion.
-template <typename T, int NT>
-__device__ __forceinline__ void eval2_leaf_body(const T* __restrict__ psi,
+template <typename C, int NT>
+__device__ __forceinline__ void eval2_leaf_body(const elem_t<C>* __restrict__ psi,
                                                   const int32_t* __restrict__ leaf_box,
                                                   const int32_t* __restrict__ leaf_id,
                                                   const int32_t* __restrict__ leaf_tab,
-                                                  const T* __restrict__ E, int p, int nr,
+                                                  const elem_t<C>* __restrict__ E, int p, int nr,
                                                   int nleaf, double* __restrict__ u, int bid) {
-  typedef Mfma<T> M;
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
   const int lane = lane_of(), w = wave_of();
@@ -637,27 +674,39 @@ __device__ __forceinline__ void eval2_leaf_body(const T* __restrict__ psi,
 #pragma unroll
   for (int ti = 0; ti < NT; ti++) zero4(wt[ti]);
 #pragma unroll
-  for (int q = 0; q < Q; q++) {
-    const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
-    const T b = ld0<T>(E1, lr * nr + k, lr < p && k < nr);
+  for (int g = 0; g < NT; g++) {
+    T bq[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; kk++) {
+      const int k = 16 * g + M::kidx(kk, lk);
+      bq[kk] = ld0<T>(E1, lr * nr + k, lr < p && k < nr);
+    }
 #pragma unroll
     for (int ti = 0; ti < NT; ti++) {
       const int r2 = 16 * ti + lr;
-      const T a = ld0<T>(P, r2 * nr + k, r2 < nr && k < nr);
-      wt[ti] = M::step(a, b, wt[ti]);
+      T aq[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) {
+        const int k = 16 * g + M::kidx(kk, lk);
+        aq[kk] = ld0<T>(P, r2 * nr + k, r2 < nr && k < nr);
+      }
+      wt[ti] = M::template steps<4>(aq, bq, wt[ti]);
     }
   }
   // u[i2][i1] = sum_r2 E2[i2][r2] W[r2][i1]
   acc_t uu;
   zero4(uu);
 #pragma unroll
-  for (int ti = 0; ti < NT; ti++)
+  for (int ti = 0; ti < NT; ti++) {
+    T aq[4], bq[4];
 #pragma unroll
     for (int kk = 0; kk < 4; kk++) {
       const int k = 16 * ti + M::kidx(kk, lk);
-      const T a = ld0<T>(E2, lr * nr + k, lr < p && k < nr);
-      uu = M::step(a, wt[ti][kk], uu);
+      aq[kk] = ld0<T>(E2, lr * nr + k, lr < p && k < nr);
+      bq[kk] = wt[ti][kk];
     }
+    uu = M::template steps<4>(aq, bq, uu);
+  }
   double* ul = u + (int64_t)leaf_id[s] * p * p;
 #pragma unroll
   for (int t = 0; t < 4; t++) {
@@ -668,18 +717,19 @@ __device__ __forceinline__ void eval2_leaf_body(const T* __restrict__ psi,
 
 // d = 2 near field: one target per wave; sources sorted by (V2, V1): axis 1
 // per source, axis 2 once per V2 group.
-template <typename T, int KS>
+template <typename C, int KS>
 __device__ __forceinline__ void near2_body(const double* __restrict__ sigma,
                                              const int32_t* __restrict__ near_tgt,
                                              const int32_t* __restrict__ near_haspw,
                                              const int32_t* __restrict__ near_start,
                                              const int32_t* __restrict__ near_src,
                                              const int32_t* __restrict__ near_tab,
-                                             const T* __restrict__ V, int p, int ntgt,
+                                             const elem_t<C>* __restrict__ V, int p, int ntgt,
                                              double* __restrict__ u, int bid) {
-  typedef Mfma<T> M;
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<T, KS>::value;
+  constexpr int S = Steps<C, KS>::value;
   const int lane = lane_of(), w = wave_of();
   const int t = bid * 4 + w;
   if (t >= ntgt) return;
@@ -693,21 +743,26 @@ __device__ __forceinline__ void near2_body(const double* __restrict__ sigma,
     const int t1 = near_tab[q * 2 + 0], t2 = near_tab[q * 2 + 1];
     const double* sg = sigma + (int64_t)near_src[q] * pp;
     const T* V1 = V + (int64_t)t1 * pp;
-#pragma unroll
-    for (int kk = 0; kk < S; kk++) {
-      const int k = M::kidx(kk, lk);
-      const T a = ld0<T>(sg, lr * p + k, lr < p && k < p);
-      const T b = ld0<T>(V1, lr * p + k, lr < p && k < p);
-      tacc = M::step(a, b, tacc);  // T[j2][i1]
-    }
-    if (q + 1 == q1 || near_tab[q * 2 + 3] != t2) {
-      const T* V2 = V + (int64_t)t2 * pp;
+    {
+      T aq[S], bq[S];
 #pragma unroll
       for (int kk = 0; kk < S; kk++) {
         const int k = M::kidx(kk, lk);
-        const T a = ld0<T>(V2, lr * p + k, lr < p && k < p);
-        oacc = M::step(a, tacc[kk], oacc);  // u[i2][i1] += V2[i2][j2] T[j2][i1]
+        aq[kk] = ld0<T>(sg, lr * p + k, lr < p && k < p);
+        bq[kk] = ld0<T>(V1, lr * p + k, lr < p && k < p);
       }
+      tacc = M::template steps<S>(aq, bq, tacc);  // T[j2][i1]
+    }
+    if (q + 1 == q1 || near_tab[q * 2 + 3] != t2) {
+      const T* V2 = V + (int64_t)t2 * pp;
+      T aq[S], bq[S];
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) {
+        const int k = M::kidx(kk, lk);
+        aq[kk] = ld0<T>(V2, lr * p + k, lr < p && k < p);
+        bq[kk] = tacc[kk];
+      }
+      oacc = M::template steps<S>(aq, bq, oacc);  // u[i2][i1] += V2[i2][j2] T[j2][i1]
       zero4(tacc);
     }
   }
@@ -738,32 +793,36 @@ template <typename T> __device__ __forceinline__ T* mptr(void* p) { return stati
 __device__ __forceinline__ int n2_of(int d, int nr) { return d == 3 ? nr * nr : nr; }
 __device__ __forceinline__ uint32_t pmagic_of(int p) { return (uint32_t)((0x100000000ull + p - 1) / p); }
 
-template <typename T, int NT, int KS>
+template <typename C, int NT, int KS>
 __global__ __launch_bounds__(256) void form3_plane(
     const double* __restrict__ sigma, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
     const int32_t* __restrict__ plane_row, const int32_t* __restrict__ row_start,
-    const int32_t* __restrict__ row_tab, const T* __restrict__ F, int p, int nr, T* __restrict__ Y) {
-  form3_plane_body<T, NT, KS>(sigma, leaf_id, leaf_tab, plane_row, row_start, row_tab, F, p, nr, Y, blockIdx.x);
+    const int32_t* __restrict__ row_tab, const elem_t<C>* __restrict__ F, int p, int nr, elem_t<C>* __restrict__ Y) {
+  typedef elem_t<C> T;
+  form3_plane_body<C, NT, KS>(sigma, leaf_id, leaf_tab, plane_row, row_start, row_tab, F, p, nr, Y, blockIdx.x);
 }
-template <typename T, int NT, int KS>
+template <typename C, int NT, int KS>
 __global__ __launch_bounds__(256) void form3_plane_b(FGT_BATCH_PARAMS) {
+  typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  form3_plane_body<T, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
+  form3_plane_body<C, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
                               cptr<T>(a.F), a.p, a.nr, mptr<T>(a.Y), bid);
 }
 
-template <typename T, int D, int NT, int KS>
-__global__ __launch_bounds__(256) void form_box(const T* __restrict__ Y, const int32_t* __restrict__ fitem,
-                                                const int32_t* __restrict__ leaf_tab, const T* __restrict__ F,
-                                                int p, int nr, int ncoltiles, T* __restrict__ phi,
-                                                T* __restrict__ partial) {
-  form_box_body<T, D, NT, KS>(Y, fitem, leaf_tab, F, p, nr, ncoltiles, phi, partial, blockIdx.x);
+template <typename C, int D, int NT, int KS>
+__global__ __launch_bounds__(256) void form_box(const elem_t<C>* __restrict__ Y, const int32_t* __restrict__ fitem,
+                                                const int32_t* __restrict__ leaf_tab, const elem_t<C>* __restrict__ F,
+                                                int p, int nr, int ncoltiles, elem_t<C>* __restrict__ phi,
+                                                elem_t<C>* __restrict__ partial) {
+  typedef elem_t<C> T;
+  form_box_body<C, D, NT, KS>(Y, fitem, leaf_tab, F, p, nr, ncoltiles, phi, partial, blockIdx.x);
 }
-template <typename T, int D, int NT, int KS>
+template <typename C, int D, int NT, int KS>
 __global__ __launch_bounds__(256) void form_box_b(FGT_BATCH_PARAMS) {
+  typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
   const int ncol128 = (n2_of(D, a.nr) + 127) / 128;
-  form_box_body<T, D, NT, KS>(cptr<T>(a.Y), a.fitem, D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
+  form_box_body<C, D, NT, KS>(cptr<T>(a.Y), a.fitem, D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
                               ncol128,
                               mptr<T>(a.phi), mptr<T>(a.partial), bid);
 }
@@ -781,93 +840,105 @@ __global__ __launch_bounds__(256) void reduce_partials_b(FGT_BATCH_PARAMS) {
   reduce_partials_body<T>(cptr<T>(a.partial), a.fred, ncoef, (int)((ncoef + 255) / 256), mptr<T>(a.phi), bid);
 }
 
-template <typename T, int D, int NT>
+template <typename C, int D, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval_box(
-    const T* __restrict__ psi, const int32_t* __restrict__ box_order, const int32_t* __restrict__ pw_start,
-    const int32_t* __restrict__ leaf_tab, const T* __restrict__ E, int p, int nr, int ncoltiles,
-    uint32_t pmagic, T* __restrict__ Z) {
-  eval_box_body<T, D, NT>(psi, box_order, pw_start, leaf_tab, E, p, nr, ncoltiles, pmagic, Z, blockIdx.x);
+    const elem_t<C>* __restrict__ psi, const int32_t* __restrict__ box_order, const int32_t* __restrict__ pw_start,
+    const int32_t* __restrict__ leaf_tab, const elem_t<C>* __restrict__ E, int p, int nr, int ncoltiles,
+    uint32_t pmagic, elem_t<C>* __restrict__ Z) {
+  typedef elem_t<C> T;
+  eval_box_body<C, D, NT>(psi, box_order, pw_start, leaf_tab, E, p, nr, ncoltiles, pmagic, Z, blockIdx.x);
 }
-template <typename T, int D, int NT>
+template <typename C, int D, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2 : 1))) void eval_box_b(
     FGT_BATCH_PARAMS) {
+  typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
   const int ncol = (n2_of(D, a.nr) + 63) / 64;
-  eval_box_body<T, D, NT>(cptr<T>(a.psi), a.box_order, D == 3 ? a.plane_start : a.pw_start,
+  eval_box_body<C, D, NT>(cptr<T>(a.psi), a.box_order, D == 3 ? a.plane_start : a.pw_start,
                           D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr, ncol,
                           pmagic_of(a.p), mptr<T>(a.Y), bid);
 }
 
-template <typename T, int NT>
+template <typename C, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1))) void eval3_plane(
-    const T* __restrict__ Z, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
+    const elem_t<C>* __restrict__ Z, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
     const int32_t* __restrict__ plane_row, const int32_t* __restrict__ row_start,
-    const int32_t* __restrict__ row_tab, const T* __restrict__ E, int p, int nr, double* __restrict__ u) {
-  eval3_plane_body<T, NT>(Z, leaf_id, leaf_tab, plane_row, row_start, row_tab, E, p, nr, u, blockIdx.x);
+    const int32_t* __restrict__ row_tab, const elem_t<C>* __restrict__ E, int p, int nr, double* __restrict__ u) {
+  typedef elem_t<C> T;
+  eval3_plane_body<C, NT>(Z, leaf_id, leaf_tab, plane_row, row_start, row_tab, E, p, nr, u, blockIdx.x);
 }
-template <typename T, int NT>
+template <typename C, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1))) void eval3_plane_b(
     FGT_BATCH_PARAMS) {
+  typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  eval3_plane_body<T, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
+  eval3_plane_body<C, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
                           cptr<T>(a.E), a.p, a.nr, jobs[j].u, bid);
 }
 
-template <typename T, int KS>
+template <typename C, int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void near3(
     const double* __restrict__ sigma, const int32_t* __restrict__ near_tgt, const int32_t* __restrict__ near_haspw,
     const int32_t* __restrict__ near_start, const int32_t* __restrict__ near_src,
-    const int32_t* __restrict__ near_tab, const T* __restrict__ V, int p, double* __restrict__ u) {
-  near3_body<T, KS>(sigma, near_tgt, near_haspw, near_start, near_src, near_tab, V, p, u, blockIdx.x);
+    const int32_t* __restrict__ near_tab, const elem_t<C>* __restrict__ V, int p, double* __restrict__ u) {
+  typedef elem_t<C> T;
+  near3_body<C, KS>(sigma, near_tgt, near_haspw, near_start, near_src, near_tab, V, p, u, blockIdx.x);
 }
-template <typename T, int KS>
+template <typename C, int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void near3_b(FGT_BATCH_PARAMS) {
+  typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  near3_body<T, KS>(jobs[j].sigma, a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, cptr<T>(a.V),
+  near3_body<C, KS>(jobs[j].sigma, a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, cptr<T>(a.V),
                     a.p, jobs[j].u, bid);
 }
 
-template <typename T, int NT, int KS>
+template <typename C, int NT, int KS>
 __global__ __launch_bounds__(256) void form2_box(const double* __restrict__ sigma, const int32_t* __restrict__ fitem,
                                                  const int32_t* __restrict__ leaf_id,
-                                                 const int32_t* __restrict__ leaf_tab, const T* __restrict__ F,
-                                                 int p, int nr, T* __restrict__ phi, T* __restrict__ partial) {
-  form2_box_body<T, NT, KS>(sigma, fitem, leaf_id, leaf_tab, F, p, nr, phi, partial, blockIdx.x);
+                                                 const int32_t* __restrict__ leaf_tab, const elem_t<C>* __restrict__ F,
+                                                 int p, int nr, elem_t<C>* __restrict__ phi, elem_t<C>* __restrict__ partial) {
+  typedef elem_t<C> T;
+  form2_box_body<C, NT, KS>(sigma, fitem, leaf_id, leaf_tab, F, p, nr, phi, partial, blockIdx.x);
 }
-template <typename T, int NT, int KS>
+template <typename C, int NT, int KS>
 __global__ __launch_bounds__(256) void form2_box_b(FGT_BATCH_PARAMS) {
+  typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  form2_box_body<T, NT, KS>(jobs[j].sigma, a.fitem, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
+  form2_box_body<C, NT, KS>(jobs[j].sigma, a.fitem, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
                             mptr<T>(a.phi), mptr<T>(a.partial), bid);
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(256) void eval2_leaf(const T* __restrict__ psi, const int32_t* __restrict__ leaf_box,
+template <typename C, int NT>
+__global__ __launch_bounds__(256) void eval2_leaf(const elem_t<C>* __restrict__ psi, const int32_t* __restrict__ leaf_box,
                                                   const int32_t* __restrict__ leaf_id,
-                                                  const int32_t* __restrict__ leaf_tab, const T* __restrict__ E,
+                                                  const int32_t* __restrict__ leaf_tab, const elem_t<C>* __restrict__ E,
                                                   int p, int nr, int nleaf, double* __restrict__ u) {
-  eval2_leaf_body<T, NT>(psi, leaf_box, leaf_id, leaf_tab, E, p, nr, nleaf, u, blockIdx.x);
+  typedef elem_t<C> T;
+  eval2_leaf_body<C, NT>(psi, leaf_box, leaf_id, leaf_tab, E, p, nr, nleaf, u, blockIdx.x);
 }
-template <typename T, int NT>
+template <typename C, int NT>
 __global__ __launch_bounds__(256) void eval2_leaf_b(FGT_BATCH_PARAMS) {
+  typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  eval2_leaf_body<T, NT>(cptr<T>(a.psi), a.pwleaf_box, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr,
+  eval2_leaf_body<C, NT>(cptr<T>(a.psi), a.pwleaf_box, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr,
                          (int)a.nL, jobs[j].u, bid);
 }
 
-template <typename T, int KS>
+template <typename C, int KS>
 __global__ __launch_bounds__(256) void near2(const double* __restrict__ sigma, const int32_t* __restrict__ near_tgt,
                                              const int32_t* __restrict__ near_haspw,
                                              const int32_t* __restrict__ near_start,
                                              const int32_t* __restrict__ near_src,
-                                             const int32_t* __restrict__ near_tab, const T* __restrict__ V, int p,
+                                             const int32_t* __restrict__ near_tab, const elem_t<C>* __restrict__ V, int p,
                                              int ntgt, double* __restrict__ u) {
-  near2_body<T, KS>(sigma, near_tgt, near_haspw, near_start, near_src, near_tab, V, p, ntgt, u, blockIdx.x);
+  typedef elem_t<C> T;
+  near2_body<C, KS>(sigma, near_tgt, near_haspw, near_start, near_src, near_tab, V, p, ntgt, u, blockIdx.x);
 }
-template <typename T, int KS>
+template <typename C, int KS>
 __global__ __launch_bounds__(256) void near2_b(FGT_BATCH_PARAMS) {
+  typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  near2_body<T, KS>(jobs[j].sigma, a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, cptr<T>(a.V),
+  near2_body<C, KS>(jobs[j].sigma, a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, cptr<T>(a.V),
                     a.p, (int)a.nT, jobs[j].u, bid);
 }
 
@@ -881,6 +952,7 @@ KernelClass kernel_class(const DeviceArgs& a) {
   KernelClass c;
   c.d = a.d;
   c.fp32 = a.fp32;
+  c.bf3 = a.bf3;
   c.nt = std::min(8, std::max(1, (a.nr + 15) / 16));
   c.ks = a.p <= 8 ? 2 : 4;
   return c;
@@ -906,44 +978,46 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
   }
 }
 
-template <typename T, int NT, int KS>
+template <typename C, int NT, int KS>
 static void launch_batched_nt(int d, int stage, const BatchJob* jobs, const int32_t* start,
                               const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+  typedef elem_t<C> T;
   const dim3 g((unsigned)grid), b(256);
   if (d == 3) {
     switch (stage) {
-      case kFormLeaf: hipLaunchKernelGGL((form3_plane_b<T, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
-      case kFormBox: hipLaunchKernelGGL((form_box_b<T, 3, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kFormLeaf: hipLaunchKernelGGL((form3_plane_b<C, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kFormBox: hipLaunchKernelGGL((form_box_b<C, 3, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
       case kTranslate: launch_translate_batched<T>(3, jobs, start, count, njobs, grid, st); break;
-      case kEvalBox: hipLaunchKernelGGL((eval_box_b<T, 3, NT>), g, b, 0, st, jobs, start, count, njobs); break;
-      case kEvalLeaf: hipLaunchKernelGGL((eval3_plane_b<T, NT>), g, b, 0, st, jobs, start, count, njobs); break;
-      case kNear: hipLaunchKernelGGL((near3_b<T, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kEvalBox: hipLaunchKernelGGL((eval_box_b<C, 3, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kEvalLeaf: hipLaunchKernelGGL((eval3_plane_b<C, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kNear: hipLaunchKernelGGL((near3_b<C, KS>), g, b, 0, st, jobs, start, count, njobs); break;
     }
   } else {
     switch (stage) {
-      case kFormBox: hipLaunchKernelGGL((form2_box_b<T, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kFormBox: hipLaunchKernelGGL((form2_box_b<C, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
       case kTranslate: launch_translate_batched<T>(2, jobs, start, count, njobs, grid, st); break;
-      case kEvalLeaf: hipLaunchKernelGGL((eval2_leaf_b<T, NT>), g, b, 0, st, jobs, start, count, njobs); break;
-      case kNear: hipLaunchKernelGGL((near2_b<T, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kEvalLeaf: hipLaunchKernelGGL((eval2_leaf_b<C, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kNear: hipLaunchKernelGGL((near2_b<C, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       default: break;
     }
   }
 }
 
-template <typename T, int KS>
+template <typename C, int KS>
 static void launch_batched_ks(const KernelClass& c, int stage, const BatchJob* jobs, const int32_t* start,
                               const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+  typedef elem_t<C> T;
   switch (c.nt) {
-    case 1: launch_batched_nt<T, 1, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 2: launch_batched_nt<T, 2, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 3: launch_batched_nt<T, 3, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 4: launch_batched_nt<T, 4, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 5: launch_batched_nt<T, 5, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 6: launch_batched_nt<T, 6, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 7: launch_batched_nt<T, 7, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    default: launch_batched_nt<T, 8, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 1: launch_batched_nt<C, 1, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 2: launch_batched_nt<C, 2, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 3: launch_batched_nt<C, 3, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 4: launch_batched_nt<C, 4, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 5: launch_batched_nt<C, 5, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 6: launch_batched_nt<C, 6, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 7: launch_batched_nt<C, 7, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    default: launch_batched_nt<C, 8, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
   }
 }
 
@@ -951,7 +1025,10 @@ hipError_t launch_stage_batched(const KernelClass& c, int stage, const BatchJob*
                                 const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
   if (grid <= 0 || njobs <= 0) return hipSuccess;
   if (c.d != 2 && c.d != 3) return hipErrorInvalidValue;
-  if (c.fp32) {
+  if (c.bf3) {
+    if (c.ks == 2) launch_batched_ks<Bf16x3, 2>(c, stage, jobs, start, count, njobs, grid, st);
+    else launch_batched_ks<Bf16x3, 4>(c, stage, jobs, start, count, njobs, grid, st);
+  } else if (c.fp32) {
     if (c.ks == 2) launch_batched_ks<float, 2>(c, stage, jobs, start, count, njobs, grid, st);
     else launch_batched_ks<float, 4>(c, stage, jobs, start, count, njobs, grid, st);
   } else {
@@ -974,9 +1051,10 @@ static void launch_reduce(const DeviceArgs& a, hipStream_t st) {
                      static_cast<const T*>(a.partial), a.fred, ncoef, nchunk, static_cast<T*>(a.phi));
 }
 
-template <typename T, int NT, int KS>
+template <typename C, int NT, int KS>
 static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipStream_t st,
                       hipEvent_t* ev, int D) {
+  typedef elem_t<C> T;
   const int p = a.p, nr = a.nr;
   const T* F = static_cast<const T*>(a.F);
   const T* E = static_cast<const T*>(a.E);
@@ -989,32 +1067,32 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
   if (a.nL > 0) {
     if (D == 3) {
       const int N2 = nr * nr, ncol = (N2 + 63) / 64, ncol128 = (N2 + 127) / 128;
-      hipLaunchKernelGGL((form3_plane<T, NT, KS>), dim3((unsigned)stage_blocks(a, kFormLeaf)), dim3(256), 0, st, sigma,
+      hipLaunchKernelGGL((form3_plane<C, NT, KS>), dim3((unsigned)stage_blocks(a, kFormLeaf)), dim3(256), 0, st, sigma,
                          a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, F, p, nr, Y);
       rec(1);
-      hipLaunchKernelGGL((form_box<T, 3, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, Y,
+      hipLaunchKernelGGL((form_box<C, 3, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, Y,
                          a.fitem, a.plane_tab, F, p, nr, ncol128, phi, static_cast<T*>(a.partial));
       launch_reduce<T>(a, st);
       rec(2);
       launch_translate<T>(a, st);
       rec(3);
       const uint32_t pmagic = (uint32_t)((0x100000000ull + p - 1) / p);  // ceil(2^32 / p)
-      hipLaunchKernelGGL((eval_box<T, 3, NT>), dim3((unsigned)stage_blocks(a, kEvalBox)), dim3(256), 0, st, psi,
+      hipLaunchKernelGGL((eval_box<C, 3, NT>), dim3((unsigned)stage_blocks(a, kEvalBox)), dim3(256), 0, st, psi,
                          a.box_order, a.plane_start, a.plane_tab, E, p, nr, ncol, pmagic, Y);
       rec(4);
-      hipLaunchKernelGGL((eval3_plane<T, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, Y,
+      hipLaunchKernelGGL((eval3_plane<C, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, Y,
                          a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, E, p, nr, u);
       rec(5);
     } else {
       rec(1);
-      hipLaunchKernelGGL((form2_box<T, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, sigma, a.fitem,
+      hipLaunchKernelGGL((form2_box<C, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, sigma, a.fitem,
                          a.pwleaf_id, a.pwleaf_tab, F, p, nr, phi, static_cast<T*>(a.partial));
       launch_reduce<T>(a, st);
       rec(2);
       launch_translate<T>(a, st);
       rec(3);
       rec(4);
-      hipLaunchKernelGGL((eval2_leaf<T, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, psi,
+      hipLaunchKernelGGL((eval2_leaf<C, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, psi,
                          a.pwleaf_box, a.pwleaf_id, a.pwleaf_tab, E, p, nr, (int)a.nL, u);
       rec(5);
     }
@@ -1023,36 +1101,40 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
   }
   if (a.nT > 0) {
     if (D == 3)
-      hipLaunchKernelGGL((near3<T, KS>), dim3((unsigned)stage_blocks(a, kNear)), dim3(256), 0, st, sigma, a.near_tgt, a.near_haspw,
+      hipLaunchKernelGGL((near3<C, KS>), dim3((unsigned)stage_blocks(a, kNear)), dim3(256), 0, st, sigma, a.near_tgt, a.near_haspw,
                          a.near_start, a.near_src, a.near_tab, V, p, u);
     else
-      hipLaunchKernelGGL((near2<T, KS>), dim3((unsigned)stage_blocks(a, kNear)), dim3(256), 0, st, sigma,
+      hipLaunchKernelGGL((near2<C, KS>), dim3((unsigned)stage_blocks(a, kNear)), dim3(256), 0, st, sigma,
                          a.near_tgt, a.near_haspw, a.near_start, a.near_src, a.near_tab, V, p,
                          (int)a.nT, u);
   }
   rec(6);
 }
 
-template <typename T, int KS>
+template <typename C, int KS>
 static void launch_ks(const DeviceArgs& a, const double* sigma, double* u, hipStream_t st,
                       hipEvent_t* ev) {
+  typedef elem_t<C> T;
   const int nt = (a.nr + 15) / 16;
   switch (nt) {
-    case 1: launch_nt<T, 1, KS>(a, sigma, u, st, ev, a.d); break;
-    case 2: launch_nt<T, 2, KS>(a, sigma, u, st, ev, a.d); break;
-    case 3: launch_nt<T, 3, KS>(a, sigma, u, st, ev, a.d); break;
-    case 4: launch_nt<T, 4, KS>(a, sigma, u, st, ev, a.d); break;
-    case 5: launch_nt<T, 5, KS>(a, sigma, u, st, ev, a.d); break;
-    case 6: launch_nt<T, 6, KS>(a, sigma, u, st, ev, a.d); break;
-    case 7: launch_nt<T, 7, KS>(a, sigma, u, st, ev, a.d); break;
-    default: launch_nt<T, 8, KS>(a, sigma, u, st, ev, a.d); break;
+    case 1: launch_nt<C, 1, KS>(a, sigma, u, st, ev, a.d); break;
+    case 2: launch_nt<C, 2, KS>(a, sigma, u, st, ev, a.d); break;
+    case 3: launch_nt<C, 3, KS>(a, sigma, u, st, ev, a.d); break;
+    case 4: launch_nt<C, 4, KS>(a, sigma, u, st, ev, a.d); break;
+    case 5: launch_nt<C, 5, KS>(a, sigma, u, st, ev, a.d); break;
+    case 6: launch_nt<C, 6, KS>(a, sigma, u, st, ev, a.d); break;
+    case 7: launch_nt<C, 7, KS>(a, sigma, u, st, ev, a.d); break;
+    default: launch_nt<C, 8, KS>(a, sigma, u, st, ev, a.d); break;
   }
 }
 
 hipError_t launch_fast(const DeviceArgs& a, const double* sigma, double* u, hipStream_t st,
                        hipEvent_t* ev) {
   const bool ks2 = a.p <= 8;
-  if (a.fp32) {
+  if (a.bf3) {
+    if (ks2) launch_ks<Bf16x3, 2>(a, sigma, u, st, ev);
+    else launch_ks<Bf16x3, 4>(a, sigma, u, st, ev);
+  } else if (a.fp32) {
     if (ks2) launch_ks<float, 2>(a, sigma, u, st, ev);
     else launch_ks<float, 4>(a, sigma, u, st, ev);
   } else {

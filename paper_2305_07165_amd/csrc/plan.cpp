@@ -68,7 +68,11 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
   if (!(delta > 0) || !std::isfinite(delta)) { err = "delta must be > 0"; return FGT_ERR_INVALID_ARG; }
   if (!(tol > 0 && tol < 0.1)) { err = "tol must be in (0, 0.1) (Theorem 1 needs eps < 0.1)"; return FGT_ERR_INVALID_ARG; }
   if (bc != FGT_FREE && bc != FGT_PERIODIC) { err = "bc must be FGT_FREE or FGT_PERIODIC"; return FGT_ERR_INVALID_ARG; }
-  if (precision != FGT_FP64 && precision != FGT_FP32) { err = "precision must be FGT_FP64 or FGT_FP32"; return FGT_ERR_INVALID_ARG; }
+  if (precision != FGT_FP64 && precision != FGT_FP32 && precision != FGT_BF16X3) {
+    err = "precision must be FGT_FP64, FGT_FP32 or FGT_BF16X3";
+    return FGT_ERR_INVALID_ARG;
+  }
+  if (precision == FGT_BF16X3 && d == 1) { err = "FGT_BF16X3 needs d = 2 or 3"; return FGT_ERR_UNSUPPORTED; }
   if (eps_internal < 0 || eps_internal >= 0.1) { err = "eps_internal must be 0 or in (0, 0.1)"; return FGT_ERR_INVALID_ARG; }
   const bool periodic = bc == FGT_PERIODIC;
 

@@ -101,6 +101,34 @@ def test_parity_fp32(shape, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("shape", ["2d", "3d"])
+def test_parity_bf16x3(shape):
+    """BF16x3 products carry about 1e-5 relative error each: the transform
+    must meet tol = 1e-3, and its error against the oracle is reported."""
+    if shape == "2d":
+        lv, cs, sig = _adaptive_2d(False)
+        p, delta = 8, 1e-3
+    else:
+        lv, cs, sig = _adaptive_3d(False)
+        p, delta = 6, 1e-3
+    uo = oracle.oracle_u(lv, cs, p, delta, sig)
+    errs = {}
+    for tol in (1e-3, 1e-6):
+        ug, _ = _run(lv, cs, p, delta, tol, sig, precision="bf16x3")
+        assert np.all(np.isfinite(ug))
+        errs[tol] = cf.rel_l2(ug, uo)
+    _say(f"bf16x3 {shape}: rel_l2 at tol 1e-3 {errs[1e-3]:.3e}, at tol 1e-6 {errs[1e-6]:.3e}")
+    assert errs[1e-3] < 1e-3
+    assert errs[1e-6] < 1e-4
+
+
+def test_bf16x3_rejected_in_1d():
+    lv = np.array([1, 1], dtype=np.int32)
+    cs = np.array([[0], [1]], dtype=np.int32)
+    with pytest.raises(api.FgtError):
+        api.Plan(lv, cs, 8, 1e-3, 1e-3, precision="bf16x3")
+
+
 def test_deterministic_and_reusable():
     lv, cs, sig = _adaptive_2d(False)
     pl = api.Plan(lv, cs, 8, 1e-3, 1e-6)
