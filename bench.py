@@ -144,6 +144,52 @@ def pct(sorted_ms, q):
     return sorted_ms[i]
 
 
+def precision_form(pr, steps, warmup, log, ntarget=96):
+    """The 3D tree of the headline workload at delta in {1e-3, 1e-5}: FP32 and
+    BF16x3 products at tol 1e-3 and 1e-6, each timed and compared with the FP64
+    oracle on a sample of target leaves; speedups are over the FP64 path at
+    tol 1e-6 on the same delta."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2305_07165_amd import api
+
+    s = torch.from_numpy(pr.sigma).cuda()
+    u = torch.empty_like(s)
+    rng = np.random.default_rng(777)
+    tg = np.sort(rng.choice(len(pr.levels), min(ntarget, len(pr.levels)), replace=False))
+    out = []
+    for delta in (1e-3, 1e-5):
+        t0 = time.perf_counter()
+        uo = oracle.oracle_u(pr.levels, pr.coords, pr.p, delta, pr.sigma, targets=tg)
+        t_or = time.perf_counter() - t0
+
+        def run(tol, prec):
+            pl = api.Plan(pr.levels, pr.coords, pr.p, delta, tol, precision=prec)
+            wall, per = timed_steps(pl, s, u, steps, warmup, torch)
+            ug = u.cpu().numpy()
+            info = pl.info()
+            pl.close()
+            err = float(np.linalg.norm(ug[tg] - uo) / np.linalg.norm(uo))
+            return 1e3 * wall / steps, err, info
+
+        ms64, err64, i64 = run(1e-6, "fp64")
+        rec = {"delta": delta, "fp64_tol1e-6": {"ms": ms64, "rel_l2": err64, "lc": i64["lc"], "nr": i64["nr"]},
+               "oracle_targets": int(len(tg)), "oracle_s": t_or}
+        for tol in (1e-3, 1e-6):
+            for prec in ("fp32", "bf16x3"):
+                ms, err, info = run(tol, prec)
+                rec[f"{prec}_tol{tol:g}"] = {"ms": ms, "points_per_s": pr.npoints / (ms * 1e-3),
+                                             "rel_l2": err, "meets_tol": err < tol,
+                                             "speedup_vs_fp64_tol1e-6": ms64 / ms, "nr": info["nr"]}
+        log(f"precision delta={delta:g}: fp64 1e-6 {ms64:.3f} ms err {err64:.1e}; " + "; ".join(
+            f"{k} {v['ms']:.3f} ms err {v['rel_l2']:.1e}" for k, v in rec.items()
+            if isinstance(v, dict) and "speedup_vs_fp64_tol1e-6" in v))
+        out.append(rec)
+    return out
+
+
 def batched_form(probs, steps, log):
     """The batched workload (synth.batch_problems): every transform in its own
     precision (FP32 when tol >= 1e-6, else FP64) in one batch (a captured HIP
@@ -372,6 +418,8 @@ def main():
             fp.close()
             log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
 
+    if not args.no_forms:
+        forms["precision"] = precision_form(pr, min(args.steps, 20), args.warmup, log)
     if batch_probs is not None:
         forms["batched"] = batched_form(batch_probs, 3, log)
         del batch_probs

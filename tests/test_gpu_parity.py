@@ -197,3 +197,21 @@ def test_full_size_3d_sampled(periodic, tol, precision):
     _say(f"full-size: lc={pl.info()['lc']} nr={pl.info()['nr']} rel_l2={err:.3e}")
     assert np.all(np.isfinite(ug))
     assert err < tol
+
+
+# the precision workload: the same tree at delta = 1e-3 and 1e-5, FP32 and
+# BF16x3 products; BF16x3 is held to tol 1e-3 only (its products carry about
+# 1e-5 relative error, so tol 1e-6 is out of its reach)
+@pytest.mark.parametrize("delta,tol,precision", [(1e-3, 1e-3, "fp32"), (1e-3, 1e-6, "fp32"),
+                                                 (1e-5, 1e-3, "fp32"), (1e-5, 1e-6, "fp32"),
+                                                 (1e-3, 1e-3, "bf16x3"), (1e-5, 1e-3, "bf16x3")])
+def test_full_size_3d_precision(delta, tol, precision):
+    pr = _full(False)
+    tg = _sample(pr.levels, n=24, seed=5)
+    _say(f"precision delta={delta} tol={tol} {precision}: {len(tg)} sampled leaves")
+    uo = oracle.oracle_u(pr.levels, pr.coords, pr.p, delta, pr.sigma, targets=tg)
+    ug, pl = _run(pr.levels, pr.coords, pr.p, delta, tol, pr.sigma, precision=precision)
+    err = cf.rel_l2(ug[tg], uo)
+    _say(f"precision: lc={pl.info()['lc']} nr={pl.info()['nr']} rel_l2={err:.3e}")
+    assert np.all(np.isfinite(ug))
+    assert err < tol
