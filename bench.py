@@ -157,8 +157,12 @@ def precision_form(pr, steps, warmup, log, ntarget=96):
 
     s = torch.from_numpy(pr.sigma).cuda()
     u = torch.empty_like(s)
+    # random leaves plus the 16 with the largest |sigma| (where u is largest),
+    # so the sample's l2 norm stands for the whole output's
     rng = np.random.default_rng(777)
-    tg = np.sort(rng.choice(len(pr.levels), min(ntarget, len(pr.levels)), replace=False))
+    tg = set(rng.choice(len(pr.levels), min(ntarget, len(pr.levels)), replace=False).tolist())
+    tg |= set(np.argsort(-np.abs(pr.sigma).max(axis=1))[:16].tolist())
+    tg = np.array(sorted(tg), dtype=np.int64)
     out = []
     for delta in (1e-3, 1e-5):
         t0 = time.perf_counter()

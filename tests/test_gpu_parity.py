@@ -175,11 +175,18 @@ def _full(periodic):
     return _FULL[periodic]
 
 
-def _sample(lv, n=48, seed=3):
+def _sample(lv, n=48, seed=3, sig=None, top=16):
+    """Random leaves, the shallowest and deepest leaf, and (given sigma) the
+    `top` leaves with the largest |sigma|: u is a smoothed sigma, so these hold
+    the largest values and the sample's l2 norm stands for the whole output's
+    (a sample of leaves far from the blobs would measure relative error
+    against values near zero)."""
     rng = np.random.default_rng(seed)
     pick = set(rng.choice(len(lv), n, replace=False).tolist())
     pick.add(int(np.argmin(lv)))
     pick.add(int(np.argmax(lv)))
+    if sig is not None:
+        pick |= set(np.argsort(-np.abs(sig).max(axis=1))[:top].tolist())
     return np.array(sorted(pick), dtype=np.int64)
 
 
@@ -188,7 +195,7 @@ def _sample(lv, n=48, seed=3):
                                                      (True, 1e-10, "fp64")])
 def test_full_size_3d_sampled(periodic, tol, precision):
     pr = _full(periodic)
-    tg = _sample(pr.levels)
+    tg = _sample(pr.levels, sig=pr.sigma)
     _say(f"full-size periodic={periodic} tol={tol} {precision}: N={pr.npoints} sample={len(tg)} leaves")
     uo = oracle.oracle_u(pr.levels, pr.coords, pr.p, pr.delta, pr.sigma, periodic=periodic, targets=tg)
     ug, pl = _run(pr.levels, pr.coords, pr.p, pr.delta, tol, pr.sigma, periodic=periodic,
@@ -207,7 +214,7 @@ def test_full_size_3d_sampled(periodic, tol, precision):
                                                  (1e-3, 1e-3, "bf16x3"), (1e-5, 1e-3, "bf16x3")])
 def test_full_size_3d_precision(delta, tol, precision):
     pr = _full(False)
-    tg = _sample(pr.levels, n=24, seed=5)
+    tg = _sample(pr.levels, n=24, seed=5, sig=pr.sigma)
     _say(f"precision delta={delta} tol={tol} {precision}: {len(tg)} sampled leaves")
     uo = oracle.oracle_u(pr.levels, pr.coords, pr.p, delta, pr.sigma, targets=tg)
     ug, pl = _run(pr.levels, pr.coords, pr.p, delta, tol, pr.sigma, precision=precision)
