@@ -163,7 +163,7 @@ def precision_form(pr, steps, warmup, log, ntarget=96):
     tg = set(rng.choice(len(pr.levels), min(ntarget, len(pr.levels)), replace=False).tolist())
     tg |= set(np.argsort(-np.abs(pr.sigma).max(axis=1))[:16].tolist())
     tg = np.array(sorted(tg), dtype=np.int64)
-    out = []
+    out = {}
     for delta in (1e-3, 1e-5):
         t0 = time.perf_counter()
         uo = oracle.oracle_u(pr.levels, pr.coords, pr.p, delta, pr.sigma, targets=tg)
@@ -190,7 +190,7 @@ def precision_form(pr, steps, warmup, log, ntarget=96):
         log(f"precision delta={delta:g}: fp64 1e-6 {ms64:.3f} ms err {err64:.1e}; " + "; ".join(
             f"{k} {v['ms']:.3f} ms err {v['rel_l2']:.1e}" for k, v in rec.items()
             if isinstance(v, dict) and "speedup_vs_fp64_tol1e-6" in v))
-        out.append(rec)
+        out[f"delta_{delta:g}"] = rec
     return out
 
 
@@ -450,11 +450,12 @@ def main():
             return float(np.linalg.norm(a[tg] - uo) / np.linalg.norm(uo))
         accuracy["fp64_tol%g" % args.tol] = err(u_head)
         for name, f in forms.items():
-            if "_u" in f:
+            if isinstance(f, dict) and "_u" in f:
                 accuracy[name] = err(f["_u"])
                 f["rel_l2_vs_oracle"] = accuracy[name]
     for f in forms.values():
-        f.pop("_u", None)
+        if isinstance(f, dict):
+            f.pop("_u", None)
 
     out = {
         "metric": "grid points/s at tol=1e-6 (3D adaptive), FP64 vs mixed; p50/p99 latency",
