@@ -397,30 +397,35 @@ def graded_tree(d: int, centers, lmax: int, r0: float, periodic: bool = False):
 
 
 def sized_tree(d: int, centers, nleaves: int, periodic: bool = False):
-    """A graded tree (`graded_tree`) with about `nleaves` leaves: the finest
-    level is the smallest whose uniform tree has enough leaves, and r0 is
-    found by bisection (the leaf count grows with r0)."""
+    """A 2:1-balanced graded tree (`graded_tree`, then `balance_fast`) with
+    about `nleaves` leaves: for finest levels around the smallest whose
+    uniform tree has enough leaves, r0 is found by bisection (the leaf count
+    grows with r0); the closest wins."""
     nleaves = max(1, int(nleaves))
-    lmax = 0
-    while 2 ** (d * lmax) < nleaves:
-        lmax += 1
-    if lmax == 0:
+    l0 = 0
+    while 2 ** (d * l0) < nleaves:
+        l0 += 1
+    if l0 == 0:
         return uniform_tree(d, 0)
-    r_lo = 2.0 * math.sqrt(d) * 2.0 ** -lmax
-    lo, hi = math.log(r_lo), math.log(4.0)
     best = None
-    for _ in range(30):
-        mid = 0.5 * (lo + hi)
-        lv, cs = graded_tree(d, centers, lmax, math.exp(mid), periodic)
-        if best is None or abs(len(lv) - nleaves) < abs(len(best[0]) - nleaves):
-            best = (lv, cs)
-        if len(lv) < nleaves:
-            lo = mid
-        else:
-            hi = mid
-        if abs(len(lv) - nleaves) <= 0.02 * nleaves:
+    for lmax in (l0 - 1, l0, l0 + 1):
+        if lmax < 1:
+            continue
+        lo, hi = math.log(0.25 * 2.0 ** -lmax), math.log(4.0)
+        for _ in range(30):
+            mid = 0.5 * (lo + hi)
+            lv, cs = graded_tree(d, centers, lmax, math.exp(mid), periodic)
+            if best is None or abs(len(lv) - nleaves) < abs(len(best[0]) - nleaves):
+                best = (lv, cs)
+            if len(lv) < nleaves:
+                lo = mid
+            else:
+                hi = mid
+            if abs(len(lv) - nleaves) <= 0.02 * nleaves:
+                break
+        if abs(len(best[0]) - nleaves) <= 0.02 * nleaves:
             break
-    return best
+    return balance_fast(*best, periodic)
 
 
 def sample_separable(levels, coords, p: int, dens: GaussianSum, chunk: int = 8192) -> np.ndarray:
