@@ -443,8 +443,10 @@ def main():
         dt = time.perf_counter() - tc
         cpu = {"value": nt * pr.p ** 3 / dt, "unit": "grid points/s", "cores": oracle.threads_used(),
                "kind": "oracle",
-               "sample": f"{nt} random target leaves ({nt * pr.p ** 3} grid points) of the same "
-                         f"tree, every source leaf within r_cut, {dt:.1f} s"}
+               "sample": (f"all {nt} leaves ({nt * pr.p ** 3} grid points) of the tree"
+                          if nt == len(pr.levels) else
+                          f"{nt} random target leaves ({nt * pr.p ** 3} grid points) of the tree")
+                         + f", every source leaf within r_cut, {dt:.1f} s"}
 
         def err(a):
             return float(np.linalg.norm(a[tg] - uo) / np.linalg.norm(uo))
