@@ -260,6 +260,178 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 }
 
 // ---------------------------------------------------------------------------
+// d = 3 out->in translation fused with the first evaluation contraction.
+// A workgroup owns one cutoff box A and one tile of mode columns (r1, r2):
+// the r1 pair of one axis-1 mode m1 times the r2 pairs of up to 16
+// consecutive axis-2 modes (at most 64 columns, every (cos, sin) partner
+// inside the tile).  Phase 1 gathers psi_A[r3][tile] = sum_{B in P(A)} Rot(c_B - c_A)
+// phi_B[r3][tile] into LDS (a thread owns the 2 x 2 x 2 coefficients of one
+// (m3, m2) unit, as in the plain translation); phase 2 contracts it with the
+// axis-3 evaluation table of every plane of A, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
+// psi_A[r3][c], one 16-column group per wave.  psi never goes to HBM.  Boxes
+// are XCD-contiguous ranges walked tile by tile, as in the plain translation.
+
+// axis-2 modes per tile: at most 16, and M * modes <= 256 so that one pass of
+// the 256 threads covers the tile's (m3, m2) units
+__host__ __device__ inline int transeval_modes(int M) { return M <= 16 ? 16 : (256 / M > 0 ? 256 / M : 1); }
+
+template <typename C, int NT>
+__device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ phi,
+                                                const int32_t* __restrict__ plist_start,
+                                                const int32_t* __restrict__ plist_src,
+                                                const int32_t* __restrict__ plist_dir,
+                                                const elem_t<C>* __restrict__ rot,
+                                                const int32_t* __restrict__ plane_start,
+                                                const int32_t* __restrict__ plane_tab,
+                                                const elem_t<C>* __restrict__ E, int p, int M,
+                                                int nr, int nA, elem_t<C>* __restrict__ Z, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M_;
+  typedef typename M_::acc acc_t;
+  constexpr int Q = 4 * NT;
+  const int TM = transeval_modes(M);
+  constexpr int LDW = 65;  // LDS row stride (columns), odd to spread banks
+  __shared__ T ps[16 * NT * LDW];
+  const int nb2 = (M + TM - 1) / TM;
+  const int ntile = M * nb2;
+  const int nbx = (nA + kXcds - 1) / kXcds;
+  const int xcd = bid % kXcds, local = bid / kXcds;
+  const int A = xcd * nbx + local % nbx;
+  const int tile = local / nbx;
+  if (A >= nA || tile >= ntile) return;  // whole workgroup
+  const int m1 = tile / nb2, b2 = tile - m1 * nb2;
+  const int mlo = b2 * TM, mhi = min(M, mlo + TM), nm2 = mhi - mlo;
+  const int n1 = m1 > 0 ? 2 : 1;
+  const int r2first = mlo > 0 ? 2 * mlo - 1 : 0;
+  const int n2 = 2 * nm2 - (mlo == 0 ? 1 : 0);  // r2 columns of the tile
+  const int ncol = n1 * n2;
+  const int64_t nr2 = (int64_t)nr * nr, ncoef = nr2 * nr;
+  const int tid = threadIdx.x;
+  // ---- phase 1: translations into LDS
+  const int q0 = plist_start[A], q1 = plist_start[A + 1];
+  const T cs1 = rot[2 * m1], sn1 = rot[2 * m1 + 1];
+  for (int unit = tid; unit < M * nm2; unit += blockDim.x) {
+    const int m3 = unit / nm2, m2 = mlo + (unit - (unit / nm2) * nm2);
+    const T cs2 = rot[2 * m2], sn2 = rot[2 * m2 + 1];
+    const T cs3 = rot[2 * m3], sn3 = rot[2 * m3 + 1];
+    // coefficient v = v1 + 2 v2 + 4 v3 (bit a: sin member of the axis pair)
+    int64_t off[8];
+    bool present[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) {
+      const int v1 = v & 1, v2 = (v >> 1) & 1, v3 = v >> 2;
+      present[v] = (v1 == 0 || m1 > 0) && (v2 == 0 || m2 > 0) && (v3 == 0 || m3 > 0);
+      const int c1 = m1 > 0 ? 2 * m1 - 1 + v1 : 0;
+      const int c2 = m2 > 0 ? 2 * m2 - 1 + v2 : 0;
+      const int c3 = m3 > 0 ? 2 * m3 - 1 + v3 : 0;
+      off[v] = c3 * nr2 + (int64_t)c1 * nr + c2;
+    }
+    T acc[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) acc[v] = 0;
+    auto fetch = [&](int q, T (&x)[8]) {
+      const bool okq = q < q1;
+      const T* src = phi + (int64_t)(okq ? plist_src[q] : 0) * ncoef;
+#pragma unroll
+      for (int v = 0; v < 8; v++) x[v] = ld0<T>(src, off[v], okq && present[v]);
+    };
+    auto rotate = [](T c, T s, T& xc, T& xs) {
+      const T a = xc, b = xs;
+      xc = c * a - s * b;
+      xs = s * a + c * b;
+    };
+    auto apply = [&](int q, T (&x)[8]) {
+      const int code = plist_dir[q];
+      const int d1 = code % 3 - 1, d2 = (code / 3) % 3 - 1, d3 = code / 9 - 1;
+      if (d1 != 0 && m1 > 0) {
+        const T s = d1 > 0 ? sn1 : -sn1;
+#pragma unroll
+        for (int v = 0; v < 8; v += 2) rotate(cs1, s, x[v], x[v + 1]);
+      }
+      if (d2 != 0 && m2 > 0) {
+        const T s = d2 > 0 ? sn2 : -sn2;
+#pragma unroll
+        for (int v = 0; v < 8; v++)
+          if (!(v & 2)) rotate(cs2, s, x[v], x[v + 2]);
+      }
+      if (d3 != 0 && m3 > 0) {
+        const T s = d3 > 0 ? sn3 : -sn3;
+#pragma unroll
+        for (int v = 0; v < 4; v++) rotate(cs3, s, x[v], x[v + 4]);
+      }
+#pragma unroll
+      for (int v = 0; v < 8; v++) acc[v] += x[v];
+    };
+    T xa[8], xb[8];
+    fetch(q0, xa);
+    for (int q = q0; q < q1; q += 2) {
+      fetch(q + 1, xb);
+      apply(q, xa);
+      if (q + 1 < q1) {
+        fetch(q + 2, xa);
+        apply(q + 1, xb);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 8; v++) {
+      if (!present[v]) continue;
+      const int v1 = v & 1, v2 = (v >> 1) & 1, v3 = v >> 2;
+      const int r3 = m3 > 0 ? 2 * m3 - 1 + v3 : 0;
+      const int r2 = m2 > 0 ? 2 * m2 - 1 + v2 : 0;
+      ps[r3 * LDW + v1 * n2 + (r2 - r2first)] = acc[v];
+    }
+  }
+  __syncthreads();
+  // ---- phase 2: Z_P[i3][c] = sum_r3 E3_P[i3][r3] psi[r3][c], 16 columns per wave
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int col = 16 * w + lr;
+  if (16 * w >= ncol) return;  // no barrier follows
+  const bool colok = col < ncol;
+  T b[Q];
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int k = 16 * (q >> 2) + M_::kidx(q & 3, lk);
+    const T v = ps[(k < nr && colok ? k * LDW + col : 0)];  // LDS: select, no branch
+    b[q] = k < nr && colok ? v : (T)0;
+  }
+  const int i1 = col < n2 ? 0 : 1;
+  const int r1 = m1 > 0 ? 2 * m1 - 1 + i1 : 0;
+  const int r2 = r2first + col - i1 * n2;
+  const int64_t cglob = (int64_t)r1 * nr + r2;
+  const int P0 = plane_start[A], P1 = plane_start[A + 1];
+  for (int P = P0; P < P1; P++) {
+    const T* E3 = E + (int64_t)plane_tab[P * 3 + 2] * p * nr;
+    acc_t acc;
+    zero4(acc);
+#pragma unroll
+    for (int g = 0; g < NT; g++) {
+      T aq[4], bq[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) {
+        const int k = 16 * g + M_::kidx(kk, lk);
+        aq[kk] = ld0<T>(E3, lr * nr + k, lr < p && k < nr);  // A[i3][r3]
+        bq[kk] = b[4 * g + kk];
+      }
+      acc = M_::template steps<4>(aq, bq, acc);
+    }
+    T* Zp = Z + (int64_t)P * p * nr2;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int i3 = M_::row(lk, t);
+      if (i3 < p && colok) Zp[(int64_t)i3 * nr2 + cglob] = acc[t];
+    }
+  }
+}
+
+int64_t transeval3_blocks(const DeviceArgs& a) {
+  const int tm = transeval_modes(a.M);
+  const int64_t nb2 = (a.M + tm - 1) / tm;
+  const int64_t nbx = (a.nA + kXcds - 1) / kXcds;
+  return kXcds * nbx * a.M * nb2;
+}
+
+// ---------------------------------------------------------------------------
 // first evaluation contraction: Z rows of every leaf of one box for one tile of
 // 64 columns.  The box's psi columns stay in registers while the workgroup
 // walks the stacked leaf rows (s*p + i) two 16-row tiles at a time.  Boxes are
@@ -942,6 +1114,23 @@ __global__ __launch_bounds__(256) void near2_b(FGT_BATCH_PARAMS) {
                     a.p, (int)a.nT, jobs[j].u, bid);
 }
 
+template <typename C, int NT>
+__global__ __launch_bounds__(256) void transeval3(
+    const elem_t<C>* __restrict__ phi, const int32_t* __restrict__ plist_start, const int32_t* __restrict__ plist_src,
+    const int32_t* __restrict__ plist_dir, const elem_t<C>* __restrict__ rot, const int32_t* __restrict__ plane_start,
+    const int32_t* __restrict__ plane_tab, const elem_t<C>* __restrict__ E, int p, int M, int nr, int nA,
+    elem_t<C>* __restrict__ Z) {
+  transeval3_body<C, NT>(phi, plist_start, plist_src, plist_dir, rot, plane_start, plane_tab, E, p, M, nr, nA, Z,
+                         blockIdx.x);
+}
+template <typename C, int NT>
+__global__ __launch_bounds__(256) void transeval3_b(FGT_BATCH_PARAMS) {
+  FGT_BATCH_PROLOGUE
+  typedef elem_t<C> T;
+  transeval3_body<C, NT>(cptr<T>(a.phi), a.plist_start, a.plist_src, a.plist_dir, cptr<T>(a.rot), a.plane_start,
+                         a.plane_tab, cptr<T>(a.E), a.p, a.M, a.nr, (int)a.nA, mptr<T>(a.Y), bid);
+}
+
 #undef FGT_BATCH_PROLOGUE
 #undef FGT_BATCH_PARAMS
 
@@ -970,8 +1159,8 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
     }
     case kFormBox: return pw ? (a.d == 3 ? a.nFI * ((N2 + 127) / 128) : a.nFI) : 0;
     case kReduce: return pw && a.nFR > 0 ? a.nFR * ((N2 * nr + 255) / 256) : 0;
-    case kTranslate: return pw ? translate_blocks(a) : 0;
-    case kEvalBox: return pw && a.d == 3 ? a.nA * ((N2 + 63) / 64) : 0;
+    case kTranslate: return pw ? (a.d == 3 ? transeval3_blocks(a) : translate_blocks(a)) : 0;
+    case kEvalBox: return 0;  // d = 3: fused into the translation stage; d = 2: fused into eval2_leaf
     case kEvalLeaf: return pw ? (a.d == 3 ? a.nPl * ((a.p + 3) / 4) : (a.nL + 3) / 4) : 0;
     case kNear: return a.nT > 0 ? (a.d == 3 ? a.nT : (a.nT + 3) / 4) : 0;
     default: return 0;
@@ -988,8 +1177,7 @@ static void launch_batched_nt(int d, int stage, const BatchJob* jobs, const int3
       case kFormLeaf: hipLaunchKernelGGL((form3_plane_b<C, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kFormBox: hipLaunchKernelGGL((form_box_b<C, 3, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
-      case kTranslate: launch_translate_batched<T>(3, jobs, start, count, njobs, grid, st); break;
-      case kEvalBox: hipLaunchKernelGGL((eval_box_b<C, 3, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kTranslate: hipLaunchKernelGGL((transeval3_b<C, NT>), g, b, 0, st, jobs, start, count, njobs); break;
       case kEvalLeaf: hipLaunchKernelGGL((eval3_plane_b<C, NT>), g, b, 0, st, jobs, start, count, njobs); break;
       case kNear: hipLaunchKernelGGL((near3_b<C, KS>), g, b, 0, st, jobs, start, count, njobs); break;
     }
@@ -1074,11 +1262,10 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
                          a.fitem, a.plane_tab, F, p, nr, ncol128, phi, static_cast<T*>(a.partial));
       launch_reduce<T>(a, st);
       rec(2);
-      launch_translate<T>(a, st);
+      hipLaunchKernelGGL((transeval3<C, NT>), dim3((unsigned)stage_blocks(a, kTranslate)), dim3(256), 0, st,
+                         static_cast<const T*>(a.phi), a.plist_start, a.plist_src, a.plist_dir,
+                         static_cast<const T*>(a.rot), a.plane_start, a.plane_tab, E, p, a.M, nr, (int)a.nA, Y);
       rec(3);
-      const uint32_t pmagic = (uint32_t)((0x100000000ull + p - 1) / p);  // ceil(2^32 / p)
-      hipLaunchKernelGGL((eval_box<C, 3, NT>), dim3((unsigned)stage_blocks(a, kEvalBox)), dim3(256), 0, st, psi,
-                         a.box_order, a.plane_start, a.plane_tab, E, p, nr, ncol, pmagic, Y);
       rec(4);
       hipLaunchKernelGGL((eval3_plane<C, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, Y,
                          a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, E, p, nr, u);
