@@ -82,11 +82,20 @@ def stage_work(info: dict, runs=None) -> dict:
         nU = nL
         lead = nL * sum(2.0 * nr ** a * p ** (d - a + 1) for a in range(1, d))
         last = nL * 2.0 * nr ** d * p
+    tr_flops = (3.0 * d + 1) * nr ** d * nP
+    if d == 3:
+        # the translation is fused with the first evaluation step: phi is read,
+        # the plane intermediate written; psi never leaves the chip
+        translate = {"flops": tr_flops + last, "bytes": ts * nA * nr ** d + ts * nU * p * n2}
+        eval_box = {"flops": 0.0, "bytes": 0.0}
+    else:
+        translate = {"flops": tr_flops, "bytes": 2.0 * ts * nA * nr ** d}
+        eval_box = {"flops": last, "bytes": ts * nA * nr ** d + ts * nU * p * n2}
     return {
         "form_leaf": {"flops": lead, "bytes": 8.0 * npw + ts * nU * p * n2},
         "form_box": {"flops": last, "bytes": ts * nU * p * n2 + ts * nA * nr ** d},
-        "translate": {"flops": (3.0 * d + 1) * nr ** d * nP, "bytes": 2.0 * ts * nA * nr ** d},
-        "eval_box": {"flops": last, "bytes": ts * nA * nr ** d + ts * nU * p * n2},
+        "translate": translate,
+        "eval_box": eval_box,
         "eval_leaf": {"flops": lead, "bytes": ts * nU * p * n2 + 8.0 * npw},
         # sigma of every distinct source once; u of every target written (and
         # read first where the plane-wave evaluation already wrote it)

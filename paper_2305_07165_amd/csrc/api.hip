@@ -105,7 +105,8 @@ int64_t fgt::plan_workspace_bytes(const HostPlan& hp) {
   const int64_t round = 256 / ts;  // each array starts on a 256-byte boundary
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
   const int64_t nU = hp.d == 3 ? hp.n_plane() : hp.n_pwleaf();
-  return ts * (up(nU * hp.p * n2) + 2 * up(hp.n_pwbox() * ncoef) + up((int64_t)hp.nslots * ncoef));
+  const int64_t nbox_arrays = hp.d == 3 ? 1 : 2;  // phi (and psi unless d = 3)
+  return ts * (up(nU * hp.p * n2) + nbox_arrays * up(hp.n_pwbox() * ncoef) + up((int64_t)hp.nslots * ncoef));
 }
 
 namespace {
@@ -159,8 +160,10 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   const size_t n2 = (size_t)ipowd(hp.nr, hp.d - 1);
   const size_t ncoef = n2 * hp.nr;
   const int64_t nU = hp.d == 3 ? hp.n_plane() : a.nL;
+  // d = 3 never stores psi: the translation is fused with the first evaluation step
+  const size_t npsi = hp.d == 3 ? 0 : (size_t)a.nA * ncoef * ts;
   if ((rc = alloc(pl, (size_t)nU * hp.p * n2 * ts, &a.Y)) ||
-      (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.phi)) || (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.psi)) ||
+      (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.phi)) || (rc = alloc(pl, npsi, &a.psi)) ||
       (rc = alloc(pl, (size_t)hp.nslots * ncoef * ts, &a.partial)))
     return rc;
   if (opts && opts->own_stream) {
@@ -254,8 +257,8 @@ int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem
   c += ts * up((hp.d == 3 ? hp.n_plane() : hp.n_pwleaf()) * hp.p * n2);
   args->phi = c;
   c += ts * up(hp.n_pwbox() * ncoef);
-  args->psi = c;
-  c += ts * up(hp.n_pwbox() * ncoef);
+  args->psi = hp.d == 3 ? nullptr : c;
+  if (hp.d != 3) c += ts * up(hp.n_pwbox() * ncoef);
   args->partial = c;
   *mem = m;
   return FGT_OK;
