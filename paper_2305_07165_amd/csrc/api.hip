@@ -104,7 +104,7 @@ int64_t fgt::plan_workspace_bytes(const HostPlan& hp) {
   const int64_t ncoef = n2 * hp.nr;
   const int64_t round = 256 / ts;  // each array starts on a 256-byte boundary
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
-  const int64_t nU = hp.d == 3 ? hp.n_plane() : hp.n_pwleaf();
+  const int64_t nU = hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : hp.n_pwleaf());
   const int64_t nbox_arrays = hp.d == 3 ? 1 : 2;  // phi (and psi unless d = 3)
   return ts * (up(nU * hp.p * n2) + nbox_arrays * up(hp.n_pwbox() * ncoef) + up((int64_t)hp.nslots * ncoef));
 }
@@ -159,7 +159,8 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   a.nPl = hp.n_plane();
   const size_t n2 = (size_t)ipowd(hp.nr, hp.d - 1);
   const size_t ncoef = n2 * hp.nr;
-  const int64_t nU = hp.d == 3 ? hp.n_plane() : a.nL;
+  // the intermediate: per plane for d = 3, none for d = 2 (both axes fused), per leaf for d = 1
+  const int64_t nU = hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : a.nL);
   // d = 3 never stores psi: the translation is fused with the first evaluation step
   const size_t npsi = hp.d == 3 ? 0 : (size_t)a.nA * ncoef * ts;
   if ((rc = alloc(pl, (size_t)nU * hp.p * n2 * ts, &a.Y)) ||
@@ -254,7 +255,7 @@ int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem
   char* c = static_cast<char*>(m);
   *args = pl->args;
   args->Y = c;
-  c += ts * up((hp.d == 3 ? hp.n_plane() : hp.n_pwleaf()) * hp.p * n2);
+  c += ts * up((hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : hp.n_pwleaf())) * hp.p * n2);
   args->phi = c;
   c += ts * up(hp.n_pwbox() * ncoef);
   args->psi = hp.d == 3 ? nullptr : c;
