@@ -83,7 +83,7 @@ def stage_work(info: dict, runs=None) -> dict:
         lead = nL * sum(2.0 * nr ** a * p ** (d - a + 1) for a in range(1, d))
         last = nL * 2.0 * nr ** d * p
     tr_flops = (3.0 * d + 1) * nr ** d * nP
-    if d == 3:
+    if d == 3 and info["fused_translate"]:
         # the translation is fused with the first evaluation step: phi is read,
         # the plane intermediate written; psi never leaves the chip
         translate = {"flops": tr_flops + last, "bytes": ts * nA * nr ** d + ts * nU * p * n2}

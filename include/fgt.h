@@ -93,6 +93,9 @@ typedef struct fgt_info {
                             evaluation apply each 1D table once per group; 0 for d < 3 */
   int64_t n_near_source; /* distinct leaves that are near-field sources */
   int64_t n_near_haspw;  /* near-field targets that also receive a plane-wave evaluation */
+  int32_t fused_translate; /* d = 3: 1 if the out->in translations run fused with the first
+                              evaluation contraction (incoming expansions never stored); chosen
+                              when they would exceed 128 MB */
 } fgt_info_t;
 
 typedef struct fgt_plan fgt_plan_t;

@@ -105,7 +105,7 @@ int64_t fgt::plan_workspace_bytes(const HostPlan& hp) {
   const int64_t round = 256 / ts;  // each array starts on a 256-byte boundary
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
   const int64_t nU = hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : hp.n_pwleaf());
-  const int64_t nbox_arrays = hp.d == 3 ? 1 : 2;  // phi (and psi unless d = 3)
+  const int64_t nbox_arrays = hp.fuse_te ? 1 : 2;  // phi, and psi unless fused away
   return ts * (up(nU * hp.p * n2) + nbox_arrays * up(hp.n_pwbox() * ncoef) + up((int64_t)hp.nslots * ncoef));
 }
 
@@ -132,6 +132,7 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   a.M = hp.pw.M;
   a.fp32 = fp32;
   a.bf3 = hp.precision == FGT_BF16X3;
+  a.fuse_te = hp.fuse_te;
   a.nA = hp.n_pwbox();
   a.nL = hp.n_pwleaf();
   a.nE = (int64_t)hp.echunk.size() / 3;
@@ -161,8 +162,8 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   const size_t ncoef = n2 * hp.nr;
   // the intermediate: per plane for d = 3, none for d = 2 (both axes fused), per leaf for d = 1
   const int64_t nU = hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : a.nL);
-  // d = 3 never stores psi: the translation is fused with the first evaluation step
-  const size_t npsi = hp.d == 3 ? 0 : (size_t)a.nA * ncoef * ts;
+  // no psi when the translation is fused with the first evaluation step
+  const size_t npsi = hp.fuse_te ? 0 : (size_t)a.nA * ncoef * ts;
   if ((rc = alloc(pl, (size_t)nU * hp.p * n2 * ts, &a.Y)) ||
       (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.phi)) || (rc = alloc(pl, npsi, &a.psi)) ||
       (rc = alloc(pl, (size_t)hp.nslots * ncoef * ts, &a.partial)))
@@ -258,8 +259,8 @@ int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem
   c += ts * up((hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : hp.n_pwleaf())) * hp.p * n2);
   args->phi = c;
   c += ts * up(hp.n_pwbox() * ncoef);
-  args->psi = hp.d == 3 ? nullptr : c;
-  if (hp.d != 3) c += ts * up(hp.n_pwbox() * ncoef);
+  args->psi = hp.fuse_te ? nullptr : c;
+  if (!hp.fuse_te) c += ts * up(hp.n_pwbox() * ncoef);
   args->partial = c;
   *mem = m;
   return FGT_OK;
@@ -394,6 +395,7 @@ int fgt_plan_info(const fgt_plan_t* pl, fgt_info_t* info) {
     for (int32_t h : hp.near_haspw) nh += h != 0;
     info->n_near_haspw = nh;
   }
+  info->fused_translate = hp.fuse_te ? 1 : 0;
   info->flops_translate = (3.0 * hp.d + 1.0) * ipowd(hp.nr, hp.d) * hp.n_plist();
   info->flops_near = 2.0 * hp.d * ipowd(hp.p, hp.d + 1) * hp.n_near_pair();
   const double ts = hp.precision != FGT_FP64 ? 4.0 : 8.0;

@@ -12,6 +12,7 @@ constexpr int kMaxDim = 3;
 constexpr int kMaxP = 16;      // nodes per axis handled by the kernels
 constexpr int kMaxModes = 128; // real plane-wave modes per axis (2M-1)
 constexpr int kFormLeaves = 8; // leaves per formation work item
+constexpr double kFuseBytes = 128e6;  // psi bytes above which the 3D translation is fused
 
 // Plane-wave parameters of Theorem 1 for tolerance eps and range R (units of
 // sqrt(delta)): D0 = sqrt(log(3/eps)), h = 2 pi/(R + D0), M = ceil(D0 (R+D0)/pi).
@@ -35,6 +36,10 @@ struct HostPlan {
   PwParams pw;         // eps, D0, R, h, M
   int nr = 0;          // real modes per axis, 2M-1
   double sqrt_delta = 0;
+
+  // d = 3: fuse the translations with the first evaluation step when the
+  // incoming expansions would not stay in the caches (more than kFuseBytes)
+  bool fuse_te = false;
 
   // plane-wave boxes (cutoff level, f = 1), Morton order
   std::vector<int32_t> pwbox_isleaf;  // [nA]

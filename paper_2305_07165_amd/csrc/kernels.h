@@ -14,6 +14,7 @@ struct DeviceArgs {
   int d = 0, p = 0, nr = 0, M = 0;
   bool fp32 = false;  // FP32 storage (FP32 or BF16x3 products)
   bool bf3 = false;   // products as split bf16 matrix-core steps (Bf16x3 in mfma.h)
+  bool fuse_te = false;  // d = 3: translation fused with the first evaluation step (no psi)
   int64_t nA = 0, nL = 0, nE = 0, nT = 0;
   // tables (compute precision)
   const void *F = nullptr, *E = nullptr, *V = nullptr, *rot = nullptr;
@@ -54,12 +55,13 @@ enum Stage { kFormLeaf = 0, kFormBox, kReduce, kTranslate, kEvalBox, kEvalLeaf, 
 // node steps KS.
 struct KernelClass {
   int d = 0;
-  bool fp32 = false, bf3 = false;
+  bool fp32 = false, bf3 = false, fuse_te = false;
   int nt = 0, ks = 0;
   bool operator<(const KernelClass& o) const {
     if (d != o.d) return d < o.d;
     if (fp32 != o.fp32) return fp32 < o.fp32;
     if (bf3 != o.bf3) return bf3 < o.bf3;
+    if (fuse_te != o.fuse_te) return fuse_te < o.fuse_te;
     if (nt != o.nt) return nt < o.nt;
     return ks < o.ks;
   }

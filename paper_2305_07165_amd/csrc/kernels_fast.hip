@@ -1142,6 +1142,7 @@ KernelClass kernel_class(const DeviceArgs& a) {
   c.d = a.d;
   c.fp32 = a.fp32;
   c.bf3 = a.bf3;
+  c.fuse_te = a.fuse_te;
   c.nt = std::min(8, std::max(1, (a.nr + 15) / 16));
   c.ks = a.p <= 8 ? 2 : 4;
   return c;
@@ -1159,8 +1160,9 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
     }
     case kFormBox: return pw ? (a.d == 3 ? a.nFI * ((N2 + 127) / 128) : a.nFI) : 0;
     case kReduce: return pw && a.nFR > 0 ? a.nFR * ((N2 * nr + 255) / 256) : 0;
-    case kTranslate: return pw ? (a.d == 3 ? transeval3_blocks(a) : translate_blocks(a)) : 0;
-    case kEvalBox: return 0;  // d = 3: fused into the translation stage; d = 2: fused into eval2_leaf
+    case kTranslate: return pw ? (a.d == 3 && a.fuse_te ? transeval3_blocks(a) : translate_blocks(a)) : 0;
+    // d = 3: a separate stage unless fused into the translation; d = 2: fused into eval2_leaf
+    case kEvalBox: return pw && a.d == 3 && !a.fuse_te ? a.nA * ((N2 + 63) / 64) : 0;
     case kEvalLeaf: return pw ? (a.d == 3 ? a.nPl * ((a.p + 3) / 4) : (a.nL + 3) / 4) : 0;
     case kNear: return a.nT > 0 ? (a.d == 3 ? a.nT : (a.nT + 3) / 4) : 0;
     default: return 0;
@@ -1168,7 +1170,7 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
 }
 
 template <typename C, int NT, int KS>
-static void launch_batched_nt(int d, int stage, const BatchJob* jobs, const int32_t* start,
+static void launch_batched_nt(int d, bool fuse, int stage, const BatchJob* jobs, const int32_t* start,
                               const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
   typedef elem_t<C> T;
   const dim3 g((unsigned)grid), b(256);
@@ -1177,7 +1179,11 @@ static void launch_batched_nt(int d, int stage, const BatchJob* jobs, const int3
       case kFormLeaf: hipLaunchKernelGGL((form3_plane_b<C, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kFormBox: hipLaunchKernelGGL((form_box_b<C, 3, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
-      case kTranslate: hipLaunchKernelGGL((transeval3_b<C, NT>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kTranslate:
+        if (fuse) hipLaunchKernelGGL((transeval3_b<C, NT>), g, b, 0, st, jobs, start, count, njobs);
+        else launch_translate_batched<T>(3, jobs, start, count, njobs, grid, st);
+        break;
+      case kEvalBox: hipLaunchKernelGGL((eval_box_b<C, 3, NT>), g, b, 0, st, jobs, start, count, njobs); break;
       case kEvalLeaf: hipLaunchKernelGGL((eval3_plane_b<C, NT>), g, b, 0, st, jobs, start, count, njobs); break;
       case kNear: hipLaunchKernelGGL((near3_b<C, KS>), g, b, 0, st, jobs, start, count, njobs); break;
     }
@@ -1198,14 +1204,14 @@ static void launch_batched_ks(const KernelClass& c, int stage, const BatchJob* j
                               const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
   typedef elem_t<C> T;
   switch (c.nt) {
-    case 1: launch_batched_nt<C, 1, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 2: launch_batched_nt<C, 2, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 3: launch_batched_nt<C, 3, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 4: launch_batched_nt<C, 4, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 5: launch_batched_nt<C, 5, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 6: launch_batched_nt<C, 6, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    case 7: launch_batched_nt<C, 7, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
-    default: launch_batched_nt<C, 8, KS>(c.d, stage, jobs, start, count, njobs, grid, st); break;
+    case 1: launch_batched_nt<C, 1, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
+    case 2: launch_batched_nt<C, 2, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
+    case 3: launch_batched_nt<C, 3, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
+    case 4: launch_batched_nt<C, 4, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
+    case 5: launch_batched_nt<C, 5, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
+    case 6: launch_batched_nt<C, 6, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
+    case 7: launch_batched_nt<C, 7, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
+    default: launch_batched_nt<C, 8, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
   }
 }
 
@@ -1262,11 +1268,20 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
                          a.fitem, a.plane_tab, F, p, nr, ncol128, phi, static_cast<T*>(a.partial));
       launch_reduce<T>(a, st);
       rec(2);
-      hipLaunchKernelGGL((transeval3<C, NT>), dim3((unsigned)stage_blocks(a, kTranslate)), dim3(256), 0, st,
-                         static_cast<const T*>(a.phi), a.plist_start, a.plist_src, a.plist_dir,
-                         static_cast<const T*>(a.rot), a.plane_start, a.plane_tab, E, p, a.M, nr, (int)a.nA, Y);
-      rec(3);
-      rec(4);
+      if (a.fuse_te) {
+        hipLaunchKernelGGL((transeval3<C, NT>), dim3((unsigned)stage_blocks(a, kTranslate)), dim3(256), 0, st,
+                           static_cast<const T*>(a.phi), a.plist_start, a.plist_src, a.plist_dir,
+                           static_cast<const T*>(a.rot), a.plane_start, a.plane_tab, E, p, a.M, nr, (int)a.nA, Y);
+        rec(3);
+        rec(4);
+      } else {
+        launch_translate<T>(a, st);
+        rec(3);
+        const uint32_t pmagic = (uint32_t)((0x100000000ull + p - 1) / p);  // ceil(2^32 / p)
+        hipLaunchKernelGGL((eval_box<C, 3, NT>), dim3((unsigned)stage_blocks(a, kEvalBox)), dim3(256), 0, st, psi,
+                           a.box_order, a.plane_start, a.plane_tab, E, p, nr, ncol, pmagic, Y);
+        rec(4);
+      }
       hipLaunchKernelGGL((eval3_plane<C, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, Y,
                          a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, E, p, nr, u);
       rec(5);

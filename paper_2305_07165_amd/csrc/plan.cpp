@@ -312,6 +312,10 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     hp.plane_row.push_back((int32_t)hp.row_tab.size());
     hp.row_start.push_back((int32_t)pl.size());
   }
+  if (d == 3) {
+    const double ts = precision == FGT_FP64 ? 8.0 : 4.0;
+    hp.fuse_te = ts * nA * (double)hp.nr * hp.nr * hp.nr > kFuseBytes;
+  }
   // the units the box-level stages run over: planes for d = 3, leaves otherwise
   const std::vector<int32_t>& unit_start = d == 3 ? hp.plane_start : hp.pw_start;
 
