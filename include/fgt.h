@@ -95,7 +95,7 @@ typedef struct fgt_info {
   int64_t n_near_haspw;  /* near-field targets that also receive a plane-wave evaluation */
   int32_t fused_translate; /* d = 3: 1 if the out->in translations run fused with the first
                               evaluation contraction (incoming expansions never stored); chosen
-                              when they would exceed 128 MB */
+                              when they would exceed 128 MB and nr <= 48 */
 } fgt_info_t;
 
 typedef struct fgt_plan fgt_plan_t;
