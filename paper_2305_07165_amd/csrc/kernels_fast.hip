@@ -262,18 +262,21 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 // ---------------------------------------------------------------------------
 // d = 3 out->in translation fused with the first evaluation contraction.
 // A workgroup owns one cutoff box A and one tile of mode columns (r1, r2):
-// the r1 pair of one axis-1 mode m1 times the r2 pairs of up to 16
-// consecutive axis-2 modes (at most 64 columns, every (cos, sin) partner
-// inside the tile).  Phase 1 gathers psi_A[r3][tile] = sum_{B in P(A)} Rot(c_B - c_A)
+// the r1 pair of one axis-1 mode m1 times the r2 pairs of a run of axis-2
+// modes -- all of them, whole contiguous rows, up to 96 columns -- so every
+// (cos, sin) partner is inside the tile.  Phase 1 gathers psi_A[r3][tile] = sum_{B in P(A)} Rot(c_B - c_A)
 // phi_B[r3][tile] into LDS (a thread owns the 2 x 2 x 2 coefficients of one
 // (m3, m2) unit, as in the plain translation); phase 2 contracts it with the
 // axis-3 evaluation table of every plane of A, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
-// psi_A[r3][c], one 16-column group per wave.  psi never goes to HBM.  Boxes
+// psi_A[r3][c], 16-column groups spread over the waves.  psi never goes to HBM.  Boxes
 // are XCD-contiguous ranges walked tile by tile, as in the plain translation.
 
-// axis-2 modes per tile: at most 16, and M * modes <= 256 so that one pass of
-// the 256 threads covers the tile's (m3, m2) units
-__host__ __device__ inline int transeval_modes(int M) { return M <= 16 ? 16 : (256 / M > 0 ? 256 / M : 1); }
+// axis-2 modes per tile: all of them (whole contiguous r2 rows) while the tile
+// stays within 96 columns; else at most 16 with M * modes <= 256
+__host__ __device__ inline int transeval_modes(int M) {
+  if (M <= 24) return M;
+  return M <= 16 ? 16 : (256 / M > 0 ? 256 / M : 1);
+}
 
 template <typename C, int NT>
 __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ phi,
@@ -290,7 +293,7 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
   typedef typename M_::acc acc_t;
   constexpr int Q = 4 * NT;
   const int TM = transeval_modes(M);
-  constexpr int LDW = 65;  // LDS row stride (columns), odd to spread banks
+  constexpr int LDW = 97;  // LDS row stride (columns), odd to spread banks
   __shared__ T ps[16 * NT * LDW];
   const int nb2 = (M + TM - 1) / TM;
   const int ntile = M * nb2;
@@ -385,8 +388,8 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
   // ---- phase 2: Z_P[i3][c] = sum_r3 E3_P[i3][r3] psi[r3][c], 16 columns per wave
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
-  const int col = 16 * w + lr;
-  if (16 * w >= ncol) return;  // no barrier follows
+  for (int cg = w; 16 * cg < ncol; cg += 4) {  // column groups of 16, no barrier follows
+  const int col = 16 * cg + lr;
   const bool colok = col < ncol;
   T b[Q];
 #pragma unroll
@@ -421,6 +424,7 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
       const int i3 = M_::row(lk, t);
       if (i3 < p && colok) Zp[(int64_t)i3 * nr2 + cglob] = acc[t];
     }
+  }
   }
 }
 
