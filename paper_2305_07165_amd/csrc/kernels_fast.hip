@@ -274,7 +274,7 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 // axis-2 modes per tile: all of them (whole contiguous r2 rows) while the tile
 // stays within 96 columns; else at most 16 with M * modes <= 256
 __host__ __device__ inline int transeval_modes(int M) {
-  if (M <= 24) return M;
+  if (M <= 32) return M;
   return M <= 16 ? 16 : (256 / M > 0 ? 256 / M : 1);
 }
 
@@ -293,7 +293,7 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
   typedef typename M_::acc acc_t;
   constexpr int Q = 4 * NT;
   const int TM = transeval_modes(M);
-  constexpr int LDW = 97;  // LDS row stride (columns), odd to spread banks
+  constexpr int LDW = NT <= 3 ? 97 : 129;  // LDS row stride (columns), odd to spread banks
   __shared__ T ps[16 * NT * LDW];
   const int nb2 = (M + TM - 1) / TM;
   const int ntile = M * nb2;

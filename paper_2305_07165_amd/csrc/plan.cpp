@@ -317,7 +317,7 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     // mode tiles); with wider tiles its tile shape reads phi less contiguously
     // than the plain translation and the pair of kernels is faster
     const double ts = precision == FGT_FP64 ? 8.0 : 4.0;
-    hp.fuse_te = hp.nr <= 48 && ts * nA * (double)hp.nr * hp.nr * hp.nr > kFuseBytes;
+    hp.fuse_te = hp.nr <= 64 && ts * nA * (double)hp.nr * hp.nr * hp.nr > kFuseBytes;
   }
   // the units the box-level stages run over: planes for d = 3, leaves otherwise
   const std::vector<int32_t>& unit_start = d == 3 ? hp.plane_start : hp.pw_start;
