@@ -70,6 +70,9 @@ typedef struct fgt_opts {
                             its own and ignores `stream` */
   int32_t profile;       /* 1 = record HIP events around every stage (fgt_stage_times) */
   int32_t host_only;     /* 1 = build the host plan only (no device memory); for inspection */
+  int32_t no_fuse;       /* 1 = never fuse the 3D translation with the first evaluation step
+                            (fgt_info_t.fused_translate); batches of many transforms run
+                            faster unfused */
 } fgt_opts_t;
 
 typedef struct fgt_info {

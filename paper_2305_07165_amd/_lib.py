@@ -45,7 +45,7 @@ class fgt_opts_t(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("eps_internal", ctypes.c_double),
                 ("force_lc", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("own_stream", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("host_only", ctypes.c_int32)]
+                ("host_only", ctypes.c_int32), ("no_fuse", ctypes.c_int32)]
 
 
 class fgt_info_t(ctypes.Structure):

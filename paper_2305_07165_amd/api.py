@@ -28,7 +28,7 @@ def _ptr(x) -> int:
 def fgt_plan(levels, coords, p: int, delta: float, tol: float, bc: int = FGT_FREE,
              precision: int = FGT_FP64, eps_internal: float = 0.0, force_lc: int = -1,
              stream: int = 0, profile: bool = False, host_only: bool = False,
-             own_stream: bool = False) -> int:
+             own_stream: bool = False, no_fuse: bool = False) -> int:
     """Plans a transform; returns the opaque plan handle (an int)."""
     L = _lib.lib()
     levels = np.ascontiguousarray(levels, dtype=np.int32)
@@ -40,7 +40,7 @@ def fgt_plan(levels, coords, p: int, delta: float, tol: float, bc: int = FGT_FRE
                            coords.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     opts = _lib.fgt_opts_t(int(precision), float(eps_internal), int(force_lc),
                            ctypes.c_void_p(int(stream) or None), int(bool(own_stream)),
-                           int(bool(profile)), int(bool(host_only)))
+                           int(bool(profile)), int(bool(host_only)), int(bool(no_fuse)))
     h = ctypes.c_void_p()
     check(L.fgt_plan(ctypes.byref(tree), int(p), float(delta), float(tol), int(bc),
                      ctypes.byref(opts), ctypes.byref(h)), "fgt_plan")
@@ -110,7 +110,7 @@ class Plan:
     def __init__(self, levels, coords, p: int, delta: float, tol: float,
                  periodic: bool = False, precision: str = "fp64", eps_internal: float = 0.0,
                  force_lc: int = -1, stream=None, profile: bool = False,
-                 host_only: bool = False, own_stream: bool = False):
+                 host_only: bool = False, own_stream: bool = False, no_fuse: bool = False):
         if stream is None and not host_only and not own_stream:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -121,7 +121,7 @@ class Plan:
         self.handle = fgt_plan(levels, coords, p, delta, tol,
                                FGT_PERIODIC if periodic else FGT_FREE,
                                _PRECISION[precision], eps_internal, force_lc,
-                               int(stream or 0), profile, host_only, own_stream)
+                               int(stream or 0), profile, host_only, own_stream, no_fuse)
 
     def execute(self, sigma, u=None):
         if u is None:

@@ -290,7 +290,7 @@ int fgt_plan(const fgt_tree_t* tree, int p, double delta, double tol, int bc, co
   int rc;
   try {
     rc = fgt::build_host_plan(tree->dim, tree->nleaves, tree->level, tree->coord, p, delta, tol, bc,
-                              o.precision, o.eps_internal, o.force_lc, pl->hp, err);
+                              o.precision, o.eps_internal, o.force_lc, o.no_fuse == 0, pl->hp, err);
   } catch (const std::bad_alloc&) {
     rc = FGT_ERR_OOM;
     err = "host allocation";

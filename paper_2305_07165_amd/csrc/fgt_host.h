@@ -100,7 +100,8 @@ struct HostPlan {
 // Validates the tree and fills every field above.  Returns an FGT_* code.
 int build_host_plan(int dim, int64_t nleaves, const int32_t* level, const int32_t* coord,
                     int p, double delta, double tol, int bc, int precision,
-                    double eps_internal, int force_lc, HostPlan& hp, std::string& err);
+                    double eps_internal, int force_lc, bool allow_fuse, HostPlan& hp,
+                    std::string& err);
 
 // Tables (tables.cpp)
 void gauss_legendre(int n, double* x, double* w);

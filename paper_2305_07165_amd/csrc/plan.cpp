@@ -61,7 +61,7 @@ void dir_of(int code, int d, int* dir) {
 
 int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord, int p,
                     double delta, double tol, int bc, int precision, double eps_internal,
-                    int force_lc, HostPlan& hp, std::string& err) {
+                    int force_lc, bool allow_fuse, HostPlan& hp, std::string& err) {
   if (d < 1 || d > kMaxDim) { err = "dim must be 1, 2 or 3"; return FGT_ERR_INVALID_ARG; }
   if (n < 1 || !level || !coord) { err = "empty tree"; return FGT_ERR_INVALID_ARG; }
   if (p < 1 || p > kMaxP) { err = "p must be in [1,16]"; return FGT_ERR_INVALID_ARG; }
@@ -317,7 +317,7 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     // mode tiles); with wider tiles its tile shape reads phi less contiguously
     // than the plain translation and the pair of kernels is faster
     const double ts = precision == FGT_FP64 ? 8.0 : 4.0;
-    hp.fuse_te = hp.nr <= 64 && ts * nA * (double)hp.nr * hp.nr * hp.nr > kFuseBytes;
+    hp.fuse_te = allow_fuse && hp.nr <= 64 && ts * nA * (double)hp.nr * hp.nr * hp.nr > kFuseBytes;
   }
   // the units the box-level stages run over: planes for d = 3, leaves otherwise
   const std::vector<int32_t>& unit_start = d == 3 ? hp.plane_start : hp.pw_start;
