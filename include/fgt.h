@@ -98,7 +98,11 @@ typedef struct fgt_info {
   int64_t n_near_haspw;  /* near-field targets that also receive a plane-wave evaluation */
   int32_t fused_translate; /* d = 3: 1 if the out->in translations run fused with the first
                               evaluation contraction (incoming expansions never stored); chosen
-                              when they would exceed 128 MB and nr <= 48 */
+                              when they would exceed 128 MB and nr <= 64 */
+  int32_t fourier;       /* 1 = periodic transform with cutoff level <= 1, run as the
+                            periodic kernel's truncated Fourier series on the root
+                            (Sections 2.2 and 5): lc = 0, nr = 2 n_p + 1, R = 0,
+                            h = 2 pi sqrt(delta), no near field */
 } fgt_info_t;
 
 typedef struct fgt_plan fgt_plan_t;
@@ -109,8 +113,11 @@ typedef struct fgt_plan fgt_plan_t;
  * bc == FGT_PERIODIC), chooses eps, the cutoff level and the plane-wave modes
  * (Theorem 1), builds the flat per-level lists and the FP64 1D tables, and
  * uploads everything to the current HIP device.  p in [1,16]; delta > 0;
- * tol in (0, 0.1) (Theorem 1 needs eps < 0.1).  Periodic trees need a cutoff
- * level >= 2 (Section 5, image-layer form); otherwise FGT_ERR_UNSUPPORTED.
+ * tol in (0, 0.1) (Theorem 1 needs eps < 0.1).  Periodic trees take one layer
+ * of image boxes at a cutoff level >= 2 and the truncated Fourier series of
+ * the periodic kernel on the root otherwise (Section 5; fgt_info_t.fourier);
+ * FGT_ERR_UNSUPPORTED if that series needs more than 128 real modes
+ * (2 n_p + 1 > 128, only with force_lc on a small delta).
  * opts may be NULL.  *out receives a plan owned by the caller (fgt_destroy).
  */
 int fgt_plan(const fgt_tree_t* tree, int p, double delta, double tol, int bc,

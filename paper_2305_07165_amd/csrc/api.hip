@@ -396,6 +396,7 @@ int fgt_plan_info(const fgt_plan_t* pl, fgt_info_t* info) {
     info->n_near_haspw = nh;
   }
   info->fused_translate = hp.fuse_te ? 1 : 0;
+  info->fourier = hp.fourier ? 1 : 0;
   info->flops_translate = (3.0 * hp.d + 1.0) * ipowd(hp.nr, hp.d) * hp.n_plist();
   info->flops_near = 2.0 * hp.d * ipowd(hp.p, hp.d + 1) * hp.n_near_pair();
   const double ts = hp.precision != FGT_FP64 ? 4.0 : 8.0;
@@ -429,7 +430,7 @@ int fgt_pw_terms(double eps, double r_over_d0) {
 
 int fgt_periodic_terms(double eps, double delta) {
   if (!(eps > 0 && eps < 1) || !(delta > 0)) return FGT_ERR_INVALID_ARG;
-  return (int)std::ceil(std::sqrt(std::log(1.0 / eps)) / (M_PI * std::sqrt(delta)));
+  return fgt::periodic_terms(eps, delta);
 }
 
 int64_t fgt_plan_array(const fgt_plan_t* pl, const char* name, void* dst, int64_t cap) {

@@ -22,6 +22,10 @@ struct PwParams {
 };
 PwParams pw_params(double eps, double R);
 
+// n_p = ceil(sqrt(log(1/eps))/(pi sqrt(delta))): Fourier terms per side of the
+// periodic Gaussian on the unit interval (Section 2.2, Table 2).
+int periodic_terms(double eps, double delta);
+
 struct HostPlan {
   // problem
   int d = 0, p = 0, bc = 0, precision = 0;
@@ -36,6 +40,9 @@ struct HostPlan {
   PwParams pw;         // eps, D0, R, h, M
   int nr = 0;          // real modes per axis, 2M-1
   double sqrt_delta = 0;
+  // periodic with l_c <= 1: the root's Fourier series (lc = 0, h = 2 pi
+  // sqrt(delta), M = n_p + 1, identity translation, no near field)
+  bool fourier = false;
 
   // d = 3: fuse the translations with the first evaluation step when the
   // incoming expansions would not stay in the caches (more than kFuseBytes)

@@ -13,6 +13,10 @@
 
 namespace fgt {
 
+int periodic_terms(double eps, double delta) {
+  return (int)std::ceil(std::sqrt(std::log(1.0 / eps)) / (M_PI * std::sqrt(delta)));
+}
+
 PwParams pw_params(double eps, double R) {
   PwParams q;
   q.eps = eps;
@@ -173,17 +177,30 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     lc = force_lc;
   }
   if (lc > maxlev) lc = maxlev;
-  if (periodic && lc <= 1) {
-    err = "periodic transforms with cutoff level <= 1 (large delta) are not implemented";
-    return FGT_ERR_UNSUPPORTED;
-  }
+  // Periodic with l_c <= 1 (Section 5): the periodic kernel's truncated Fourier
+  // series (Section 2.2) on the root replaces the image layer.  Its terms
+  // sqrt(pi delta) exp(-pi^2 delta n^2) exp(2 pi i n x), |n| <= n_p, are the
+  // plane waves of Theorem 1 with h = 2 pi sqrt(delta) (k_n = 2 pi n, weight
+  // h/(2 sqrt(pi)) exp(-n^2 h^2/4)) and M = n_p + 1: the same tables, one box,
+  // its only translation the identity, and no near field.
+  const bool fourier = periodic && lc <= 1;
+  hp.fourier = fourier;
+  if (fourier) lc = 0;
   hp.lc = lc;
   hp.Llc = std::ldexp(1.0, -lc);
-  // largest per-axis separation between a target in a cutoff box and a source
-  // in one of its colleagues (or the box itself when the root is the only box)
-  double R = (lc == 0 ? 1.0 : 2.0 * hp.Llc) / hp.sqrt_delta;
-  if (R < D0) R = D0;
-  hp.pw = pw_params(eps, R);
+  if (fourier) {
+    hp.pw.eps = eps;
+    hp.pw.D0 = D0;
+    hp.pw.R = 0.0;
+    hp.pw.h = 2.0 * M_PI * hp.sqrt_delta;
+    hp.pw.M = periodic_terms(eps, delta) + 1;
+  } else {
+    // largest per-axis separation between a target in a cutoff box and a source
+    // in one of its colleagues (or the box itself when the root is the only box)
+    double R = (lc == 0 ? 1.0 : 2.0 * hp.Llc) / hp.sqrt_delta;
+    if (R < D0) R = D0;
+    hp.pw = pw_params(eps, R);
+  }
   hp.nr = 2 * hp.pw.M - 1;
   if (hp.nr > kMaxModes) { err = "too many plane-wave modes for this build (nr > 128)"; return FGT_ERR_UNSUPPORTED; }
 
@@ -207,7 +224,7 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     }
   }
   for (auto& b : lcbox) {
-    if (!b.isleaf) { b.f = 1; continue; }
+    if (!b.isleaf || fourier) { b.f = 1; continue; }
     for (int code = 0; code < n3 && !b.f; code++) {
       int dir[3];
       dir_of(code, d, dir);
@@ -313,9 +330,9 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     hp.row_start.push_back((int32_t)pl.size());
   }
   if (d == 3) {
-    // measured: the fused kernel wins while psi is large and n_r <= 48 (three
-    // mode tiles); with wider tiles its tile shape reads phi less contiguously
-    // than the plain translation and the pair of kernels is faster
+    // measured: the fused kernel wins while psi is large and n_r <= 64 (up to
+    // four mode tiles); with wider tiles its tile shape reads phi less
+    // contiguously than the plain translation and the pair of kernels is faster
     const double ts = precision == FGT_FP64 ? 8.0 : 4.0;
     hp.fuse_te = allow_fuse && hp.nr <= 64 && ts * nA * (double)hp.nr * hp.nr * hp.nr > kFuseBytes;
   }
@@ -374,6 +391,15 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
       int dir[3];
       dir_of(code, d, dir);
       int32_t q[3];
+      if (fourier) {
+        // the root's expansion already holds every image: itself, unshifted
+        bool zero = true;
+        for (int a = 0; a < d; a++) zero = zero && dir[a] == 0;
+        if (!zero) continue;
+        hp.plist_src.push_back(A.idx);
+        hp.plist_dir.push_back(code);
+        continue;
+      }
       if (!neighbor(lc, A.c, dir, q, nullptr)) continue;
       auto it = lcmap.find(key(lc, q));
       if (it == lcmap.end()) continue;
@@ -390,7 +416,7 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
   std::unordered_map<uint64_t, int32_t> vtab;  // (source level, type) -> id
   std::vector<int32_t> vtab_lv, vtab_ty;
   std::vector<std::pair<int64_t, int32_t>> tgt;  // (morton, leaf)
-  for (int64_t i = 0; i < n; i++)
+  for (int64_t i = 0; i < n && !fourier; i++)
     if (level[i] <= lc) tgt.push_back({(int64_t)morton(&coord[i * d], d, lmax - level[i]), (int32_t)i});
   std::sort(tgt.begin(), tgt.end());
   hp.near_start.push_back(0);

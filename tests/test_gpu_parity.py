@@ -49,6 +49,12 @@ def _adaptive_3d(periodic=False, p=6, maxl=5):
     return lv, cs, synth.sample(lv, cs, p, dens)
 
 
+def _adaptive_1d_periodic():
+    dens = synth.GaussianSum(np.array([[0.47]]), np.array([0.01]), np.array([1.0]), periodic=True)
+    lv, cs = synth.resolve_tree(dens, 1, 9, 1e-12, max_level=9, periodic=True)
+    return lv, cs, synth.sample(lv, cs, 9, dens)
+
+
 CASES = [
     # name, builder, p, delta, tol, periodic, force_lc
     ("2d-uniform-direct", lambda: (synth.small_2d(0).levels, synth.small_2d(0).coords, synth.small_2d(0).sigma), 8, 1e-3, 1e-6, False, -1),
@@ -64,6 +70,12 @@ CASES = [
     ("3d-adaptive-periodic-p6", lambda: _adaptive_3d(True), 6, 1e-3, 1e-6, True, -1),
     ("3d-adaptive-free-p6-1e-10", lambda: _adaptive_3d(False), 6, 1e-3, 1e-10, False, -1),
     ("3d-adaptive-free-p16", lambda: _adaptive_3d(False, p=16, maxl=4), 16, 1e-3, 1e-10, False, -1),
+    # periodic with cutoff level <= 1: the root Fourier series (automatic or forced)
+    ("2d-periodic-fourier", lambda: _adaptive_2d(True), 8, 0.05, 1e-6, True, -1),
+    ("2d-periodic-fourier-forced", lambda: _adaptive_2d(True), 8, 2e-3, 1e-8, True, 0),
+    ("3d-periodic-fourier", lambda: _adaptive_3d(True, maxl=4), 6, 0.02, 1e-6, True, -1),
+    ("3d-periodic-fourier-forced", lambda: _adaptive_3d(True), 6, 4e-3, 1e-6, True, 1),
+    ("1d-periodic-fourier", lambda: _adaptive_1d_periodic(), 9, 0.2, 1e-10, True, -1),
     ("1d-adaptive", lambda: (lambda t: (t[0], t[1], synth.sample(t[0], t[1], 9, synth.GaussianSum(np.array([[0.13]]), np.array([0.01]), np.array([1.0])))))(synth.resolve_tree(synth.GaussianSum(np.array([[0.13]]), np.array([0.01]), np.array([1.0])), 1, 9, 1e-12, max_level=9)), 9, 1e-4, 1e-10, False, -1),
 ]
 
@@ -151,6 +163,10 @@ def test_single_leaf_root():
     assert cf.rel_l2(ug, uo) < 1e-8
     x = synth.leaf_points(lv, cs, 8)
     assert cf.rel_l2(ug, cf.const_free(x, 0.02)) < 1e-8
+    # periodic, large delta: the root Fourier series; sigma = 1 gives (pi delta)^(d/2)
+    ug, pl = _run(lv, cs, 8, 0.1, 1e-10, sig, periodic=True)
+    assert pl.info()["fourier"] == 1
+    assert np.max(np.abs(ug / (np.pi * 0.1) - 1.0)) < 1e-10
 
 
 def test_errors_surface():

@@ -75,6 +75,48 @@ def test_table2_periodic_terms():
         assert [api.fgt_periodic_terms(e, delta) for e in epss] == counts
 
 
+def test_table2_through_the_periodic_plan():
+    """A periodic plan with cutoff level <= 1 uses n_p Fourier terms per side
+    (Table 2): 2 n_p + 1 real modes, one root box, one translation (the
+    identity) and no near field.  The automatic cutoff level reaches that
+    route for large deltas; a forced level 0 reaches it for any."""
+    lv, cs = synth.uniform_tree(2, 2)
+    epss = [1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12]
+    for row in _golden("table2.txt"):
+        delta, counts = row[0], row[1:]
+        for eps, n_p in zip(epss, counts):
+            for flc in (0, -1):
+                info = _plan(lv, cs, 4, delta, eps, periodic=True, force_lc=flc).info()
+                if flc == -1 and info["fourier"] == 0:
+                    assert info["lc"] >= 2  # the image-layer form
+                    continue
+                assert info["fourier"] == 1 and info["lc"] == 0
+                assert info["nr"] == 2 * n_p + 1 and info["nf"] == 2 * (n_p + 1)
+                assert info["n_pwbox"] == 1 and info["n_plist"] == 1
+                assert info["n_near_target"] == 0 and info["n_pwleaf"] == len(lv)
+                assert info["h"] == pytest.approx(2 * math.pi * math.sqrt(delta), rel=1e-15)
+    # free space with the same deltas keeps Theorem 1's modes
+    assert _plan(lv, cs, 4, 0.1, 1e-6).info()["fourier"] == 0
+
+
+def test_fourier_modes_bound_the_image_sum():
+    """The plan's Fourier modes (weights of Theorem 1 at h = 2 pi sqrt(delta))
+    reproduce the image sum of the periodic kernel (Eq. (gper_kernel)) to eps
+    on a whole period; the two agree by Poisson summation."""
+    lv, cs = synth.uniform_tree(1, 3)
+    for delta in (0.3, 0.1, 1e-2, 1e-3):
+        for eps in (1e-2, 1e-6, 1e-12):
+            info = _plan(lv, cs, 4, delta, eps, periodic=True, force_lc=0).info()
+            h, M = info["h"], (info["nr"] + 1) // 2
+            x = np.linspace(-1.0, 1.0, 4001)
+            j = np.arange(-40, 41)
+            img = np.sum(np.exp(-(x[:, None] - j[None, :]) ** 2 / delta), 1)
+            m = np.arange(1, M)
+            w = h / (2 * math.sqrt(math.pi)) * np.exp(-(m * h) ** 2 / 4)
+            ser = h / (2 * math.sqrt(math.pi)) + 2 * np.cos(np.outer(x, m * h / math.sqrt(delta))) @ w
+            assert np.max(np.abs(ser - img)) <= eps
+
+
 @pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-10])
 @pytest.mark.parametrize("delta", [1e-3, 3e-4, 1e-4])
 def test_theorem1_bound_with_plan_modes(tol, delta):
@@ -266,8 +308,10 @@ def test_validation_errors():
     lvu = [1, 1, 1] + [2] * 3 + [3] * 4
     csu = [[1, 0], [0, 1], [1, 1], [0, 0], [1, 0], [0, 1], [2, 2], [3, 2], [2, 3], [3, 3]]
     assert _code(lambda: mk(np.array(lvu, np.int32), np.array(csu, np.int32))) == _lib.FGT_ERR_NOT_BALANCED
-    # periodic with a cutoff level <= 1 (large delta) is not implemented
-    assert _code(lambda: mk(lv, cs, delta=0.05, periodic=True)) == _lib.FGT_ERR_UNSUPPORTED
+    # periodic with a cutoff level <= 1 runs the root Fourier series; forced onto a
+    # small delta it would need more than 128 real modes
+    assert mk(lv, cs, delta=0.05, periodic=True).info()["fourier"] == 1
+    assert _code(lambda: mk(lv, cs, delta=1e-5, periodic=True, force_lc=0)) == _lib.FGT_ERR_UNSUPPORTED
     # a valid plan works
     assert mk(lv, cs).info()["nleaves"] == 16
     assert ok
@@ -306,6 +350,25 @@ def test_fflags_plists_dlists_small_tree():
 
 # ---------------------------------------------------------------------------
 # the host plan, walked in numpy, against the oracle
+
+
+@pytest.mark.parametrize("d,delta,tol,flc", [(1, 0.2, 1e-10, -1), (2, 0.05, 1e-6, -1),
+                                             (2, 2e-3, 1e-8, 1), (3, 0.02, 1e-6, -1)])
+def test_fourier_route_matches_oracle(d, delta, tol, flc):
+    """Periodic transforms with cutoff level <= 1 (the root Fourier series)
+    against the oracle's image sums, on adaptive trees near the boundary."""
+    c = {1: [[0.47]], 2: [[0.46, -0.17], [-0.2, 0.49]], 3: [[0.45, -0.12, 0.05]]}[d]
+    dens = synth.GaussianSum(np.array(c), np.array([0.02, 0.04][:len(c)]),
+                             np.array([1.0, -0.5][:len(c)]), periodic=True)
+    p = {1: 8, 2: 8, 3: 5}[d]
+    lv, cs = synth.resolve_tree(dens, d, p, 1e-9, max_level={1: 8, 2: 6, 3: 3}[d], periodic=True)
+    sig = synth.sample(lv, cs, p, dens)
+    pl = _plan(lv, cs, p, delta, tol, periodic=True, force_lc=flc)
+    assert pl.info()["fourier"] == 1
+    uo = oracle.oracle_u(lv, cs, p, delta, sig, periodic=True)
+    assert cf.rel_l2(host_exec.run(pl, sig), uo) < tol
+    if d == 3:
+        assert cf.rel_l2(host_exec.run(pl, sig, grouped=True), uo) < tol
 
 
 @pytest.mark.parametrize("case", ["2d-pw", "2d-adaptive", "2d-periodic", "3d"])

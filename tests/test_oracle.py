@@ -50,7 +50,7 @@ def test_constant_free(d, delta, p):
     assert np.max(np.abs(u - ref)) < 1e-13 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("d,delta", [(1, 1e-2), (2, 5e-3), (2, 8e-2), (3, 1e-2)])
+@pytest.mark.parametrize("d,delta", [(1, 1e-2), (1, 0.5), (2, 5e-3), (2, 8e-2), (3, 1e-2), (3, 0.1)])
 def test_constant_periodic(d, delta):
     lv, cs = synth.point_refined_tree(d, [0.49] * d, 3, periodic=True)
     u, x, _ = _run(lv, cs, 4, delta, synth.Constant(1.0), periodic=True)
@@ -88,7 +88,7 @@ def test_blob_periodized_periodic_2d():
     assert cf.rel_l2(u, ref) < 1e-11
 
 
-@pytest.mark.parametrize("d,nu,delta", [(2, 2, 3e-3), (3, 1, 2e-2)])
+@pytest.mark.parametrize("d,nu,delta", [(2, 2, 3e-3), (3, 1, 2e-2), (2, 1, 0.1), (1, 3, 0.05)])
 def test_sincos_eigenfunction_periodic(d, nu, delta):
     lv, cs = synth.uniform_tree(d, 2)
     p = 14 if d == 2 else 10
