@@ -11,6 +11,10 @@ with the GPU path (``paper_2305_07165_amd``) and never imports it.
 with s_S the tensor Legendre interpolant of the samples on leaf S (Eq. (bgt)
 with the leaf model of Eq. (papprox)), computed by the plain definition in
 ``oracle.c`` (Lemma directbox with adaptive Gauss-Legendre 1D integrals).
+``oracle_u_boxes`` returns the same u at the nodes of arbitrary target boxes
+(the boxes of an output tree, Section 4.2).  ``oracle_interp`` evaluates a
+function given by values on a tree's leaves (the leaf model of Eq. (papprox))
+at arbitrary points, in numpy.
 """
 
 from __future__ import annotations
@@ -51,6 +55,11 @@ def _load():
                                        ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                        ctypes.c_double, f64p, ctypes.c_int64, i64p,
                                        f64p, ctypes.c_int]
+        lib.oracle_box_fgt_boxes.restype = ctypes.c_int64
+        lib.oracle_box_fgt_boxes.argtypes = [ctypes.c_int, ctypes.c_int64, i32p, i32p,
+                                             ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_double, f64p, ctypes.c_int64, i32p, i32p,
+                                             f64p, ctypes.c_int]
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_gauss_legendre.restype = None
         lib.oracle_gauss_legendre.argtypes = [ctypes.c_int, f64p, f64p]
@@ -88,6 +97,83 @@ def oracle_u(levels, coords, p: int, delta: float, sigma, periodic: bool = False
     if npair < 0:
         raise RuntimeError(f"oracle_box_fgt failed ({npair})")
     return (u, int(npair)) if return_pairs else u
+
+
+def oracle_u_boxes(levels, coords, p: int, delta: float, sigma, blevels, bcoords,
+                   periodic: bool = False, rcut: float = 0.0, nthreads: int = 0):
+    """u at the nodes of the boxes (blevels, bcoords), ``[nbox, p**d]``; the
+    sources are the leaves (levels, coords) with samples sigma."""
+    lib = _load()
+    levels = np.ascontiguousarray(levels, dtype=np.int32)
+    coords = np.ascontiguousarray(coords, dtype=np.int32)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    blevels = np.ascontiguousarray(blevels, dtype=np.int32)
+    bcoords = np.ascontiguousarray(bcoords, dtype=np.int32)
+    n, d = coords.shape
+    if sigma.shape != (n, p ** d) or bcoords.shape != (len(blevels), d):
+        raise ValueError("shape mismatch")
+    u = np.zeros((len(blevels), p ** d), dtype=np.float64)
+    r = lib.oracle_box_fgt_boxes(d, n, _ptr(levels, ctypes.c_int32), _ptr(coords, ctypes.c_int32),
+                                 p, float(delta), int(bool(periodic)), float(rcut),
+                                 _ptr(sigma, ctypes.c_double), len(blevels),
+                                 _ptr(blevels, ctypes.c_int32), _ptr(bcoords, ctypes.c_int32),
+                                 _ptr(u, ctypes.c_double), int(nthreads))
+    if r < 0:
+        raise RuntimeError(f"oracle_box_fgt_boxes failed ({r})")
+    return u
+
+
+def oracle_interp(levels, coords, p: int, values, x, chunk: int = 65536):
+    """The piecewise polynomial given by ``values[nleaves, p**d]`` at the
+    tensor Gauss-Legendre nodes of each leaf (degree p-1 per axis, Eq.
+    (papprox)), evaluated at the points ``x[npts, d]`` of [-1/2, 1/2]^d.
+
+    Each point is located in the leaf that contains it (a point on a shared
+    face goes to the leaf on its upper side, the top face of the unit box to
+    the last leaf); the leaf's Legendre coefficients come from a Vandermonde
+    solve on the nodes, and the polynomial is summed at the point's local
+    coordinates."""
+    from numpy.polynomial import legendre as npleg
+    levels = np.asarray(levels, dtype=np.int64)
+    coords = np.asarray(coords, dtype=np.int64)
+    values = np.asarray(values, dtype=np.float64)
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    n, d = coords.shape
+    eta = gauss_legendre(p)[0]
+    Vinv = np.linalg.inv(npleg.legvander(eta, p - 1))
+    # locate: for every level present, the cell of each point and a lookup of
+    # (cell) among the leaves of that level
+    leaf = np.full(len(x), -1, dtype=np.int64)
+    for l in np.unique(levels):
+        sel = np.where(levels == l)[0]
+        nb = 1 << int(l)
+        cell = np.clip(np.floor((x + 0.5) * nb).astype(np.int64), 0, nb - 1)
+        key = np.zeros(len(x), dtype=np.int64)
+        lkey = np.zeros(len(sel), dtype=np.int64)
+        for a in range(d):
+            key = key * nb + cell[:, a]
+            lkey = lkey * nb + coords[sel, a]
+        order = np.argsort(lkey)
+        pos = np.clip(np.searchsorted(lkey[order], key), 0, len(sel) - 1)
+        hit = lkey[order][pos] == key
+        leaf[hit] = sel[order][pos[hit]]
+    if np.any(leaf < 0):
+        raise ValueError("a point lies outside the leaves")
+    out = np.empty(len(x))
+    for s in range(0, len(x), chunk):
+        xs, ls = x[s:s + chunk], leaf[s:s + chunk]
+        L = 2.0 ** -levels[ls]
+        lo = -0.5 + coords[ls] * L[:, None]
+        t = 2.0 * (xs - lo) / L[:, None] - 1.0
+        c = values[ls].reshape((len(ls),) + (p,) * d)        # [m, i_d, ..., i_1]
+        for ax in range(1, d + 1):
+            c = np.moveaxis(np.tensordot(Vinv, c, axes=([1], [ax])), 0, ax)
+        # contract axis d first (array axis 1), then d-1, ..., 1
+        for a in range(d - 1, -1, -1):
+            P = npleg.legvander(t[:, a], p - 1)              # [m, p]
+            c = np.einsum("mn,mn...->m...", P, c)
+        out[s:s + chunk] = c
+    return out
 
 
 def threads_used() -> int:

@@ -14,7 +14,9 @@
  * where s_S is the degree-(p-1)-per-axis Legendre interpolant of the samples
  * of sigma at the tensor Gauss-Legendre nodes of leaf S, and G is the free
  * space Gaussian exp(-|x|^2/delta) (Eq. (gkernel)) or its periodization over
- * Z^d (Eq. (gper_kernel)).  Targets are the nodes of the requested leaves.
+ * Z^d (Eq. (gper_kernel)).  Targets are the tensor Gauss-Legendre nodes of
+ * requested boxes: leaves of the source tree, or any other boxes (the boxes
+ * of a refined or coarsened output tree, Section 4.2).
  *
  * How (each step is the plain definition, no fast method):
  *  1. Gauss-Legendre nodes/weights on [-1,1] by Newton's method on P_p.
@@ -282,17 +284,22 @@ int oracle_threads(void) { return or_threads_used; }
  * level[nleaves], coord[nleaves*d]: leaf i is the box of side 2^-level[i]
  * with lower corner -1/2 + coord*2^-level on each axis.  sigma[nleaves][p^d]
  * holds the samples at the leaf's tensor Gauss-Legendre nodes, multi-index
- * (i_1..i_d) at i_1 + p*i_2 + p^2*i_3.  targets[ntarget] lists the leaves whose
- * nodes receive u (NULL = all leaves in order); u[ntarget][p^d].
- * rcut <= 0 selects sqrt(delta*ln(1e17)).  Returns the number of (target,
- * source) leaf pairs summed, or a negative value on bad arguments.
+ * (i_1..i_d) at i_1 + p*i_2 + p^2*i_3.
+ *
+ * Targets are boxes given the same way, blevel[nbox], bcoord[nbox*d]: any box
+ * of [-1/2,1/2]^d, not necessarily a leaf (Section 4.2 evaluates u on the
+ * tensor grids of boxes of a refined output tree).  u[nbox][p^d] receives u at
+ * each box's tensor Gauss-Legendre nodes.  rcut <= 0 selects
+ * sqrt(delta*ln(1e17)).  Returns the number of (target box, source leaf)
+ * pairs summed, or a negative value on bad arguments.
  */
-int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32_t *coord,
-                       int p, double delta, int periodic, double rcut,
-                       const double *sigma, int64_t ntarget, const int64_t *targets,
-                       double *u, int nthreads)
+int64_t oracle_box_fgt_boxes(int d, int64_t nleaves, const int32_t *level, const int32_t *coord,
+                             int p, double delta, int periodic, double rcut,
+                             const double *sigma, int64_t nbox, const int32_t *blevel,
+                             const int32_t *bcoord, double *u, int nthreads)
 {
-    if (d < 1 || d > 3 || p < 1 || p > OR_MAXP || delta <= 0.0 || nleaves < 1) return -1;
+    if (d < 1 || d > 3 || p < 1 || p > OR_MAXP || delta <= 0.0 || nleaves < 1 || nbox < 0)
+        return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
     or_threads_used = omp_get_max_threads();
@@ -301,7 +308,7 @@ int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32
     or_threads_used = 1;
 #endif
     if (rcut <= 0.0) rcut = sqrt(delta * log(1e17));
-    if (!targets) ntarget = nleaves;
+    const int64_t ntarget = nbox;
     const int64_t np = or_ipow(p, d);
 
     double eta[OR_MAXP], wgl[OR_MAXP], xq[OR_NQ], wq[OR_NQ];
@@ -313,15 +320,24 @@ int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32
         if (level[i] < 0 || level[i] > 40) return -1;
         if (level[i] > lmax) lmax = level[i];
     }
+    for (int64_t i = 0; i < nbox; i++) {
+        if (blevel[i] < 0 || blevel[i] > 40) return -1;
+        if (blevel[i] > lmax) lmax = blevel[i];
+    }
     /* centers in units of 2^-(lmax+1): c = (2*coord+1)*2^(lmax-level) - 2^lmax */
     const int64_t unit_per_one = (int64_t)1 << (lmax + 1);
     const double unit = 1.0 / (double)unit_per_one;
     int64_t *cint = (int64_t *)malloc(sizeof(int64_t) * nleaves * d);
+    int64_t *tint = (int64_t *)malloc(sizeof(int64_t) * (nbox > 0 ? nbox : 1) * d);
     double *coef = (double *)malloc(sizeof(double) * nleaves * np);
-    if (!cint || !coef) { free(cint); free(coef); return -2; }
+    if (!cint || !tint || !coef) { free(cint); free(tint); free(coef); return -2; }
     for (int64_t i = 0; i < nleaves; i++)
         for (int a = 0; a < d; a++)
             cint[i * d + a] = (2 * (int64_t)coord[i * d + a] + 1) * ((int64_t)1 << (lmax - level[i]))
+                              - ((int64_t)1 << lmax);
+    for (int64_t i = 0; i < nbox; i++)
+        for (int a = 0; a < d; a++)
+            tint[i * d + a] = (2 * (int64_t)bcoord[i * d + a] + 1) * ((int64_t)1 << (lmax - blevel[i]))
                               - ((int64_t)1 << lmax);
 
     /* step 2 for every source leaf */
@@ -346,21 +362,19 @@ int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32
     uint64_t *klist = (uint64_t *)malloc(sizeof(uint64_t) * kcap);
 
     for (int64_t ti = 0; ti < ntarget; ti++) {
-        int64_t T = targets ? targets[ti] : ti;
         tstart[ti] = npair;
-        if (T < 0 || T >= nleaves) continue;
         for (int64_t S = 0; S < nleaves; S++) {
             int ok = 1;
             int64_t off[3];
             for (int a = 0; a < d && ok; a++) {
-                int64_t o = cint[T * d + a] - cint[S * d + a];
+                int64_t o = tint[ti * d + a] - cint[S * d + a];
                 if (periodic) { /* normalize to (-1/2, 1/2] in units */
                     o %= unit_per_one;
                     if (o > unit_per_one / 2) o -= unit_per_one;
                     if (o <= -unit_per_one / 2) o += unit_per_one;
                 }
                 off[a] = o;
-                double reach = 0.5 * (ldexp(1.0, -level[T]) + ldexp(1.0, -level[S])) + rcut;
+                double reach = 0.5 * (ldexp(1.0, -blevel[ti]) + ldexp(1.0, -level[S])) + rcut;
                 double od = fabs((double)o * unit);
                 /* nearest image is j = 0 after normalization */
                 if (od > reach) ok = 0;
@@ -375,7 +389,7 @@ int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32
             pt[npair] = ti;
             ps[npair] = S;
             for (int a = 0; a < d; a++) {
-                uint64_t key = ((uint64_t)level[S] << 56) | ((uint64_t)level[T] << 48)
+                uint64_t key = ((uint64_t)level[S] << 56) | ((uint64_t)blevel[ti] << 48)
                                | (uint64_t)(off[a] + ((int64_t)1 << 46));
                 int64_t idx = or_map_get(&memo, key);
                 if (idx == memo.n - 1 && idx >= 0) {
@@ -443,6 +457,7 @@ int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32
     }
 
     free(cint);
+    free(tint);
     free(coef);
     free(pt);
     free(ps);
@@ -453,6 +468,34 @@ int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32
     free(memo.keys);
     free(memo.vals);
     return bad ? -2 : npair;
+}
+
+/*
+ * The same transform with the targets given as leaves of the source tree:
+ * targets[ntarget] lists the leaves whose nodes receive u (NULL = all leaves
+ * in order); u[ntarget][p^d].
+ */
+int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32_t *coord,
+                       int p, double delta, int periodic, double rcut,
+                       const double *sigma, int64_t ntarget, const int64_t *targets,
+                       double *u, int nthreads)
+{
+    if (d < 1 || d > 3 || nleaves < 1) return -1;
+    if (!targets) ntarget = nleaves;
+    int32_t *bl = (int32_t *)malloc(sizeof(int32_t) * (ntarget > 0 ? ntarget : 1));
+    int32_t *bc = (int32_t *)malloc(sizeof(int32_t) * (ntarget > 0 ? ntarget : 1) * d);
+    if (!bl || !bc) { free(bl); free(bc); return -2; }
+    for (int64_t ti = 0; ti < ntarget; ti++) {
+        int64_t T = targets ? targets[ti] : ti;
+        if (T < 0 || T >= nleaves) { free(bl); free(bc); return -1; }
+        bl[ti] = level[T];
+        for (int a = 0; a < d; a++) bc[ti * d + a] = coord[T * d + a];
+    }
+    int64_t r = oracle_box_fgt_boxes(d, nleaves, level, coord, p, delta, periodic, rcut, sigma,
+                                     ntarget, bl, bc, u, nthreads);
+    free(bl);
+    free(bc);
+    return r;
 }
 
 /* The Gauss-Legendre rule used above, exported so tests can pin it. */

@@ -213,3 +213,71 @@ def test_periodic_shift_2d():
     uf = oracle.oracle_u(lv, cs, p, delta, sig)
     uf2 = oracle.oracle_u(lv, cs2, p, delta, sig)
     assert np.max(np.abs(uf2 - uf)) > 1e-6 * np.max(np.abs(uf))
+
+
+# ---------------------------------------------------------------------------
+# targets that are not leaves of the source tree (output trees, Section 4.2)
+
+
+def _random_boxes(rng, d, n, lmin, lmax):
+    bl = rng.integers(lmin, lmax + 1, n).astype(np.int32)
+    bc = np.stack([rng.integers(0, 1 << int(l), d) for l in bl]).astype(np.int32)
+    return bl, bc
+
+
+def test_boxes_equal_leaves_when_targets_are_leaves():
+    dens = synth.GaussianSum(np.array([[0.11, -0.17]]), np.array([0.05]), np.array([1.0]))
+    lv, cs = synth.resolve_tree(dens, 2, 6, 1e-8, max_level=6)
+    sig = synth.sample(lv, cs, 6, dens)
+    a = oracle.oracle_u(lv, cs, 6, 2e-3, sig)
+    b = oracle.oracle_u_boxes(lv, cs, 6, 2e-3, sig, lv, cs)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("d,periodic", [(1, False), (2, False), (3, False), (2, True)])
+def test_boxes_constant_closed_form(d, periodic):
+    """sigma = 1 at boxes finer and coarser than the leaves they overlap."""
+    rng = np.random.default_rng(7 + d)
+    lv, cs = synth.point_refined_tree(d, [0.131] * d, 4 if d < 3 else 3, periodic=periodic)
+    p, delta = 5, 4e-3
+    bl, bc = _random_boxes(rng, d, 40 if d < 3 else 12, 0, 7 if d < 3 else 5)
+    sig = np.ones((len(lv), p ** d))
+    u = oracle.oracle_u_boxes(lv, cs, p, delta, sig, bl, bc, periodic=periodic)
+    x = synth.leaf_points(bl, bc, p)
+    ref = cf.const_periodic(x, delta) if periodic else cf.const_free(x, delta)
+    assert np.max(np.abs(u - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_boxes_blob_closed_form_2d():
+    dens = synth.GaussianSum(np.array([[0.11, -0.17], [-0.2, 0.05]]),
+                             np.array([0.05, 0.08]), np.array([0.7, -0.4]))
+    lv, cs = synth.resolve_tree(dens, 2, 12, 1e-13, max_level=7)
+    rng = np.random.default_rng(3)
+    bl, bc = _random_boxes(rng, 2, 60, 2, 9)
+    delta = 2e-3
+    sig = synth.sample(lv, cs, 12, dens)
+    u = oracle.oracle_u_boxes(lv, cs, 12, delta, sig, bl, bc)
+    ref = cf.gaussian_sum_free(synth.leaf_points(bl, bc, 12), delta, dens)
+    assert cf.rel_l2(u, ref) < 1e-11
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_interp_reproduces_nodes_and_polynomials(d):
+    """At a leaf's own nodes the interpolant returns the values; a polynomial
+    of degree < p per axis is reproduced exactly anywhere (numpy polyval)."""
+    rng = np.random.default_rng(20 + d)
+    lv, cs = synth.point_refined_tree(d, [0.31] * d, 4 if d < 3 else 3)
+    p = 5
+    coefs = [rng.normal(size=p) for _ in range(d)]
+
+    def f(x):
+        return np.prod([np.polynomial.polynomial.polyval(x[..., a], coefs[a]) for a in range(d)], 0)
+
+    xn = synth.leaf_points(lv, cs, p)                     # [n, p^d, d]
+    vals = f(xn)
+    got = oracle.oracle_interp(lv, cs, p, vals, xn.reshape(-1, d))
+    assert np.max(np.abs(got - vals.ravel())) < 1e-12 * np.max(np.abs(vals))
+    x = rng.uniform(-0.5, 0.5, (2000, d))
+    x[:3] = 0.5                                           # the top corner
+    x[3:6] = -0.5
+    assert np.max(np.abs(oracle.oracle_interp(lv, cs, p, vals, x) - f(x))) < 1e-12 * np.max(np.abs(vals))
