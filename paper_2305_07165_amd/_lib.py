@@ -1,5 +1,5 @@
-"""ctypes declarations of the C ABI in include/fgt.h, include/fgt_serve.h and
-include/fgt_batch.h (argument marshalling only).
+"""ctypes declarations of the C ABI in include/fgt.h, include/fgt_serve.h,
+include/fgt_batch.h and include/fgt_output.h (argument marshalling only).
 
 Every step of the transform runs in libfgt.so's HIP kernels; there is no CPU
 fallback.  If the library is missing this module raises on first use.
@@ -32,7 +32,9 @@ EXPORTED = ["fgt_plan", "fgt_execute", "fgt_sync", "fgt_plan_info", "fgt_stage_t
             "fgt_server_create", "fgt_server_submit", "fgt_server_poll", "fgt_server_wait",
             "fgt_server_drain", "fgt_server_stats", "fgt_server_destroy",
             "fgt_batch_create", "fgt_batch_bind", "fgt_batch_execute", "fgt_batch_tune",
-            "fgt_batch_info", "fgt_batch_destroy"]
+            "fgt_batch_info", "fgt_batch_destroy",
+            "fgt_output_resolve", "fgt_output_info", "fgt_output_tree", "fgt_output_values",
+            "fgt_output_destroy", "fgt_interp", "fgt_tree_balance"]
 
 
 class fgt_tree_t(ctypes.Structure):
@@ -121,6 +123,24 @@ class fgt_batch_info_t(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class fgt_output_opts_t(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("refine", ctypes.c_int32),
+                ("coarsen", ctypes.c_int32), ("max_passes", ctypes.c_int32)]
+
+
+class fgt_output_info_t(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("p", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("nleaves_in", ctypes.c_int64), ("nleaves", ctypes.c_int64),
+                ("nboxes_in", ctypes.c_int64), ("nboxes", ctypes.c_int64),
+                ("added_refine", ctypes.c_int64), ("added_refine_balance", ctypes.c_int64),
+                ("deleted_coarsen", ctypes.c_int64), ("added_balance", ctypes.c_int64),
+                ("u_l2", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("max_leaf_error", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -186,6 +206,22 @@ def lib():
         L.fgt_batch_info.argtypes = [vp, ctypes.POINTER(fgt_batch_info_t)]
         L.fgt_batch_destroy.restype = ctypes.c_int
         L.fgt_batch_destroy.argtypes = [vp]
+        L.fgt_output_resolve.restype = ctypes.c_int
+        L.fgt_output_resolve.argtypes = [ctypes.POINTER(fgt_tree_t), ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.POINTER(fgt_opts_t),
+                                         ctypes.POINTER(fgt_output_opts_t), vp, ctypes.POINTER(vp)]
+        L.fgt_output_info.restype = ctypes.c_int
+        L.fgt_output_info.argtypes = [vp, ctypes.POINTER(fgt_output_info_t)]
+        L.fgt_output_tree.restype = ctypes.c_int
+        L.fgt_output_tree.argtypes = [vp, vp, vp]
+        L.fgt_output_values.restype = ctypes.c_int
+        L.fgt_output_values.argtypes = [vp, vp]
+        L.fgt_output_destroy.restype = None
+        L.fgt_output_destroy.argtypes = [vp]
+        L.fgt_interp.restype = ctypes.c_int
+        L.fgt_interp.argtypes = [ctypes.POINTER(fgt_tree_t), ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp]
+        L.fgt_tree_balance.restype = ctypes.c_int64
+        L.fgt_tree_balance.argtypes = [ctypes.POINTER(fgt_tree_t), ctypes.c_int, vp, vp, ctypes.c_int64]
         _lib = L
     return _lib
 

@@ -1,4 +1,4 @@
-"""Python binding of the C ABI (include/fgt.h), argument marshalling only.
+"""Python binding of the C ABI (include/*.h), argument marshalling only.
 
 Functions carry the C names (``fgt_plan``, ``fgt_execute``, ...).  ``Plan`` is
 a small owner object on top of them.  sigma/u are torch tensors on the GPU
@@ -23,6 +23,18 @@ def _ptr(x) -> int:
     if isinstance(x, int):
         return x
     return int(x.data_ptr())
+
+
+def _tree(levels, coords):
+    """(fgt_tree_t, the arrays it points to) for host leaf arrays."""
+    levels = np.ascontiguousarray(levels, dtype=np.int32)
+    coords = np.ascontiguousarray(coords, dtype=np.int32)
+    if coords.ndim != 2 or coords.shape[0] != levels.shape[0]:
+        raise ValueError("coords must be [nleaves, dim] matching levels")
+    tree = _lib.fgt_tree_t(coords.shape[1], levels.shape[0],
+                           levels.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           coords.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return tree, (levels, coords)
 
 
 def fgt_plan(levels, coords, p: int, delta: float, tol: float, bc: int = FGT_FREE,
@@ -390,3 +402,121 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# output trees (include/fgt_output.h)
+
+
+def fgt_output_resolve(levels, coords, p: int, delta: float, tol: float, sigma,
+                       bc: int = FGT_FREE, precision: int = FGT_FP64, stream: int = 0,
+                       eps: float = 0.0, refine: bool = True, coarsen: bool = True,
+                       max_passes: int = 0, force_lc: int = -1) -> int:
+    """Runs the transform and resolves u on an output tree; returns the handle."""
+    L = _lib.lib()
+    tree, keep = _tree(levels, coords)
+    opts = _lib.fgt_opts_t(int(precision), 0.0, int(force_lc), ctypes.c_void_p(int(stream) or None),
+                           0, 0, 0, 0)
+    oo = _lib.fgt_output_opts_t(float(eps), int(bool(refine)), int(bool(coarsen)), int(max_passes))
+    h = ctypes.c_void_p()
+    check(L.fgt_output_resolve(ctypes.byref(tree), int(p), float(delta), float(tol), int(bc),
+                               ctypes.byref(opts), ctypes.byref(oo), _ptr(sigma), ctypes.byref(h)),
+          "fgt_output_resolve")
+    del keep
+    return h.value
+
+
+def fgt_output_info(out: int) -> dict:
+    info = _lib.fgt_output_info_t()
+    check(_lib.lib().fgt_output_info(out, ctypes.byref(info)), "fgt_output_info")
+    return info.as_dict()
+
+
+def fgt_output_tree(out: int):
+    info = fgt_output_info(out)
+    n, d = info["nleaves"], info["dim"]
+    lv = np.zeros(n, dtype=np.int32)
+    cs = np.zeros((n, d), dtype=np.int32)
+    check(_lib.lib().fgt_output_tree(out, lv.ctypes.data, cs.ctypes.data), "fgt_output_tree")
+    return lv, cs
+
+
+def fgt_output_values(out: int, u) -> None:
+    check(_lib.lib().fgt_output_values(out, _ptr(u)), "fgt_output_values")
+
+
+def fgt_output_destroy(out: int) -> None:
+    if out:
+        _lib.lib().fgt_output_destroy(out)
+
+
+def fgt_interp(levels, coords, p: int, u, x, out, stream: int = 0) -> None:
+    """out[i] = the tree's piecewise polynomial (values u) at x[i]; device arrays."""
+    tree, keep = _tree(levels, coords)
+    npts = int(x.shape[0]) if hasattr(x, "shape") else 0
+    check(_lib.lib().fgt_interp(ctypes.byref(tree), int(p), _ptr(u), npts, _ptr(x), _ptr(out),
+                                int(stream) or None), "fgt_interp")
+    del keep
+
+
+def fgt_tree_balance(levels, coords, periodic: bool = False):
+    """The 2:1 balanced tree (host arrays), leaves in Morton order."""
+    L = _lib.lib()
+    tree, keep = _tree(levels, coords)
+    bc = FGT_PERIODIC if periodic else FGT_FREE
+    n = check(L.fgt_tree_balance(ctypes.byref(tree), bc, None, None, 0), "fgt_tree_balance")
+    d = keep[1].shape[1]
+    lv = np.zeros(n, dtype=np.int32)
+    cs = np.zeros((n, d), dtype=np.int32)
+    check(L.fgt_tree_balance(ctypes.byref(tree), bc, lv.ctypes.data, cs.ctypes.data, n),
+          "fgt_tree_balance")
+    return lv, cs
+
+
+class OutputTree:
+    """u resolved on its own adaptive tree (Section 4.2).  ``levels``,
+    ``coords`` and ``u`` (a tensor on sigma's device) are filled on
+    construction; ``info`` holds the box counts and error figures."""
+
+    def __init__(self, levels, coords, p: int, delta: float, tol: float, sigma,
+                 periodic: bool = False, precision: str = "fp64", eps: float = 0.0,
+                 refine: bool = True, coarsen: bool = True, max_passes: int = 0,
+                 force_lc: int = -1, stream=None):
+        import torch
+        n, d = np.asarray(coords).reshape(len(levels), -1).shape
+        if tuple(sigma.shape) != (n, int(p) ** d) or sigma.dtype != torch.float64 or not sigma.is_cuda:
+            raise ValueError(f"sigma must be a float64 device tensor of shape {(n, int(p) ** d)}")
+        sigma = sigma.contiguous()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = fgt_output_resolve(levels, coords, p, delta, tol, sigma,
+                               FGT_PERIODIC if periodic else FGT_FREE, _PRECISION[precision],
+                               stream, eps, refine, coarsen, max_passes, force_lc)
+        try:
+            self.info = fgt_output_info(h)
+            self.levels, self.coords = fgt_output_tree(h)
+            self.p = int(p)
+            self.u = torch.empty((len(self.levels), self.p ** self.coords.shape[1]),
+                                 dtype=torch.float64, device=sigma.device)
+            fgt_output_values(h, self.u)
+        finally:
+            fgt_output_destroy(h)
+
+    def interp(self, x):
+        """u at the points x (a [npts, dim] float64 tensor on the device)."""
+        return interp(self.levels, self.coords, self.p, self.u, x)
+
+
+def interp(levels, coords, p: int, u, x):
+    """The tree's piecewise polynomial (values u) at the points x; returns a
+    new tensor on x's device."""
+    import torch
+    n, d = np.asarray(coords).reshape(len(levels), -1).shape
+    if x.dim() != 2 or x.shape[1] != d or x.dtype != torch.float64 or not x.is_cuda:
+        raise ValueError(f"x must be a float64 device tensor of shape [npts, {d}]")
+    if u.numel() != n * int(p) ** d or u.dtype != torch.float64 or not u.is_cuda:
+        raise ValueError(f"u must be a float64 device tensor of {n} x {int(p) ** d} values")
+    x = x.contiguous()
+    out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    fgt_interp(levels, coords, p, u.contiguous(), x, out, torch.cuda.current_stream().cuda_stream)
+    return out

@@ -444,3 +444,44 @@ def test_grouped_walk_equals_per_leaf_walk():
         assert cf.rel_l2(b, a) < 1e-13
     uo = oracle.oracle_u(lv, cs, 4, 5e-2, sig)
     assert cf.rel_l2(host_exec.run(_plan(lv, cs, 4, 5e-2, 1e-6), sig, grouped=True), uo) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# 2:1 rebalancing of the output trees (host logic of include/fgt_output.h)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_tree_balance_matches_the_input_generator(d):
+    """fgt_tree_balance (C++) against the input generator's plain balance
+    (Python), on unbalanced trees refined around random points."""
+    import itertools
+    rng = np.random.default_rng(40 + d)
+    for _ in range(8):
+        pts = rng.uniform(-0.5, 0.5, (int(rng.integers(1, 4)), d))
+        maxl = int(rng.integers(3, 8 if d < 3 else 5))
+        leaves, boxes = [], [(0, (0,) * d)]
+        while boxes:
+            l, c = boxes.pop()
+            lo = -0.5 + np.array(c) * 2.0 ** -l
+            inside = any(np.all(pt >= lo) and np.all(pt < lo + 2.0 ** -l) for pt in pts)
+            if inside and l < maxl:
+                for o in itertools.product((0, 1), repeat=d):
+                    boxes.append((l + 1, tuple(2 * c[a] + o[a] for a in range(d))))
+            else:
+                leaves.append((l, c))
+        lv = np.array([l for l, _ in leaves], np.int32)
+        cs = np.array([c for _, c in leaves], np.int32).reshape(-1, d)
+        for periodic in (False, True):
+            a = synth.balance(lv, cs, periodic)
+            b = api.fgt_tree_balance(lv, cs, periodic)
+            assert set(zip(a[0].tolist(), map(tuple, a[1].tolist()))) == \
+                set(zip(b[0].tolist(), map(tuple, b[1].tolist())))
+            # Morton order of the lower corners
+            lmax = int(b[0].max())
+            key = [sum(((int(c[a]) << (lmax - int(l))) >> bit & 1) << (bit * d + a)
+                       for bit in range(lmax) for a in range(d)) for l, c in zip(*b)]
+            assert key == sorted(key)
+    # an already balanced tree is returned unchanged
+    lv, cs = synth.uniform_tree(d, 2)
+    b = api.fgt_tree_balance(lv, cs)
+    assert len(b[0]) == len(lv)
