@@ -278,6 +278,11 @@ __host__ __device__ inline int transeval_modes(int M) {
   return M <= 16 ? 16 : (256 / M > 0 ? 256 / M : 1);
 }
 
+// LDS of the psi tile: nr rows of LDW = 2 nr + 1 columns (odd, to spread the
+// banks; a tile holds at most 2 nr columns since fused plans have M <= 32)
+__host__ __device__ inline int transeval_ldw(int nr) { return 2 * nr + 1; }
+inline size_t transeval_lds(int nr, size_t ts) { return (size_t)nr * transeval_ldw(nr) * ts; }
+
 template <typename C, int NT>
 __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ phi,
                                                 const int32_t* __restrict__ plist_start,
@@ -287,14 +292,14 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
                                                 const int32_t* __restrict__ plane_start,
                                                 const int32_t* __restrict__ plane_tab,
                                                 const elem_t<C>* __restrict__ E, int p, int M,
-                                                int nr, int nA, elem_t<C>* __restrict__ Z, int bid) {
+                                                int nr, int nA, elem_t<C>* __restrict__ Z,
+                                                elem_t<C>* __restrict__ ps, int bid) {
   typedef elem_t<C> T;
   typedef Mfma<C> M_;
   typedef typename M_::acc acc_t;
   constexpr int Q = 4 * NT;
   const int TM = transeval_modes(M);
-  constexpr int LDW = NT <= 3 ? 97 : 129;  // LDS row stride (columns), odd to spread banks
-  __shared__ T ps[16 * NT * LDW];
+  const int LDW = transeval_ldw(nr);
   const int nb2 = (M + TM - 1) / TM;
   const int ntile = M * nb2;
   const int nbx = (nA + kXcds - 1) / kXcds;
@@ -1124,15 +1129,19 @@ __global__ __launch_bounds__(256) void transeval3(
     const int32_t* __restrict__ plist_dir, const elem_t<C>* __restrict__ rot, const int32_t* __restrict__ plane_start,
     const int32_t* __restrict__ plane_tab, const elem_t<C>* __restrict__ E, int p, int M, int nr, int nA,
     elem_t<C>* __restrict__ Z) {
+  extern __shared__ __align__(16) unsigned char te_lds[];
   transeval3_body<C, NT>(phi, plist_start, plist_src, plist_dir, rot, plane_start, plane_tab, E, p, M, nr, nA, Z,
-                         blockIdx.x);
+                         reinterpret_cast<elem_t<C>*>(te_lds), blockIdx.x);
 }
+// batched: the launch provides the LDS of the class's largest nr (16 NT)
 template <typename C, int NT>
 __global__ __launch_bounds__(256) void transeval3_b(FGT_BATCH_PARAMS) {
+  extern __shared__ __align__(16) unsigned char te_lds[];
   FGT_BATCH_PROLOGUE
   typedef elem_t<C> T;
   transeval3_body<C, NT>(cptr<T>(a.phi), a.plist_start, a.plist_src, a.plist_dir, cptr<T>(a.rot), a.plane_start,
-                         a.plane_tab, cptr<T>(a.E), a.p, a.M, a.nr, (int)a.nA, mptr<T>(a.Y), bid);
+                         a.plane_tab, cptr<T>(a.E), a.p, a.M, a.nr, (int)a.nA, mptr<T>(a.Y),
+                         reinterpret_cast<T*>(te_lds), bid);
 }
 
 #undef FGT_BATCH_PROLOGUE
@@ -1184,7 +1193,9 @@ static void launch_batched_nt(int d, bool fuse, int stage, const BatchJob* jobs,
       case kFormBox: hipLaunchKernelGGL((form_box_b<C, 3, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
       case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
       case kTranslate:
-        if (fuse) hipLaunchKernelGGL((transeval3_b<C, NT>), g, b, 0, st, jobs, start, count, njobs);
+        if (fuse)
+          hipLaunchKernelGGL((transeval3_b<C, NT>), g, b, transeval_lds(16 * NT, sizeof(T)), st, jobs, start, count,
+                             njobs);
         else launch_translate_batched<T>(3, jobs, start, count, njobs, grid, st);
         break;
       case kEvalBox: hipLaunchKernelGGL((eval_box_b<C, 3, NT>), g, b, 0, st, jobs, start, count, njobs); break;
@@ -1273,8 +1284,8 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
       launch_reduce<T>(a, st);
       rec(2);
       if (a.fuse_te) {
-        hipLaunchKernelGGL((transeval3<C, NT>), dim3((unsigned)stage_blocks(a, kTranslate)), dim3(256), 0, st,
-                           static_cast<const T*>(a.phi), a.plist_start, a.plist_src, a.plist_dir,
+        hipLaunchKernelGGL((transeval3<C, NT>), dim3((unsigned)stage_blocks(a, kTranslate)), dim3(256),
+                           transeval_lds(nr, sizeof(T)), st, static_cast<const T*>(a.phi), a.plist_start, a.plist_src, a.plist_dir,
                            static_cast<const T*>(a.rot), a.plane_start, a.plane_tab, E, p, a.M, nr, (int)a.nA, Y);
         rec(3);
         rec(4);
