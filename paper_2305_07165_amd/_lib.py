@@ -1,5 +1,4 @@
-"""ctypes declarations of the C ABI in include/fgt.h, include/fgt_serve.h,
-include/fgt_batch.h and include/fgt_output.h (argument marshalling only).
+"""ctypes declarations of the C ABI in include/*.h (argument marshalling only).
 
 Every step of the transform runs in libfgt.so's HIP kernels; there is no CPU
 fallback.  If the library is missing this module raises on first use.
@@ -34,7 +33,9 @@ EXPORTED = ["fgt_plan", "fgt_execute", "fgt_sync", "fgt_plan_info", "fgt_stage_t
             "fgt_batch_create", "fgt_batch_bind", "fgt_batch_execute", "fgt_batch_tune",
             "fgt_batch_info", "fgt_batch_destroy",
             "fgt_output_resolve", "fgt_output_info", "fgt_output_tree", "fgt_output_values",
-            "fgt_output_destroy", "fgt_interp", "fgt_tree_balance"]
+            "fgt_output_destroy", "fgt_interp", "fgt_tree_balance",
+            "fgt_resolve_gaussians", "fgt_density_info", "fgt_density_tree", "fgt_density_values",
+            "fgt_density_destroy", "fgt_sample_gaussians"]
 
 
 class fgt_tree_t(ctypes.Structure):
@@ -141,6 +142,29 @@ class fgt_output_info_t(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class fgt_gaussians_t(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("centers", ctypes.POINTER(ctypes.c_double)),
+                ("widths", ctypes.POINTER(ctypes.c_double)),
+                ("amps", ctypes.POINTER(ctypes.c_double)), ("periodic", ctypes.c_int32)]
+
+
+class fgt_resolve_opts_t(ctypes.Structure):
+    _fields_ = [("min_level", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("max_leaves", ctypes.c_int64), ("norm", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class fgt_density_info_t(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("p", ctypes.c_int32), ("nleaves", ctypes.c_int64),
+                ("nleaves_unbalanced", ctypes.c_int64), ("boxes_sampled", ctypes.c_int64),
+                ("lmin", ctypes.c_int32), ("lmax", ctypes.c_int32),
+                ("norm", ctypes.c_double), ("threshold", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -222,6 +246,20 @@ def lib():
         L.fgt_interp.argtypes = [ctypes.POINTER(fgt_tree_t), ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp]
         L.fgt_tree_balance.restype = ctypes.c_int64
         L.fgt_tree_balance.argtypes = [ctypes.POINTER(fgt_tree_t), ctypes.c_int, vp, vp, ctypes.c_int64]
+        L.fgt_resolve_gaussians.restype = ctypes.c_int
+        L.fgt_resolve_gaussians.argtypes = [ctypes.POINTER(fgt_gaussians_t), ctypes.c_int, ctypes.c_double,
+                                            ctypes.POINTER(fgt_resolve_opts_t), ctypes.POINTER(vp)]
+        L.fgt_density_info.restype = ctypes.c_int
+        L.fgt_density_info.argtypes = [vp, ctypes.POINTER(fgt_density_info_t)]
+        L.fgt_density_tree.restype = ctypes.c_int
+        L.fgt_density_tree.argtypes = [vp, vp, vp]
+        L.fgt_density_values.restype = ctypes.c_int
+        L.fgt_density_values.argtypes = [vp, vp]
+        L.fgt_density_destroy.restype = None
+        L.fgt_density_destroy.argtypes = [vp]
+        L.fgt_sample_gaussians.restype = ctypes.c_int
+        L.fgt_sample_gaussians.argtypes = [ctypes.POINTER(fgt_gaussians_t), ctypes.POINTER(fgt_tree_t),
+                                           ctypes.c_int, vp, vp]
         _lib = L
     return _lib
 

@@ -520,3 +520,64 @@ def interp(levels, coords, p: int, u, x):
     out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
     fgt_interp(levels, coords, p, u.contiguous(), x, out, torch.cuda.current_stream().cuda_stream)
     return out
+
+
+# ---------------------------------------------------------------------------
+# input trees on the device (include/fgt_density.h)
+
+
+def _gaussians(centers, widths, amps, periodic: bool):
+    c = np.ascontiguousarray(np.atleast_2d(centers), dtype=np.float64)
+    w = np.ascontiguousarray(widths, dtype=np.float64).ravel()
+    a = np.ascontiguousarray(amps, dtype=np.float64).ravel()
+    if c.shape[0] != len(w) or len(w) != len(a):
+        raise ValueError("centers [n, dim], widths [n] and amps [n] must agree")
+    dp = ctypes.POINTER(ctypes.c_double)
+    g = _lib.fgt_gaussians_t(c.shape[1], c.shape[0], c.ctypes.data_as(dp), w.ctypes.data_as(dp),
+                             a.ctypes.data_as(dp), int(bool(periodic)))
+    return g, (c, w, a)
+
+
+def resolve_gaussians(centers, widths, amps, p: int, eps: float, periodic: bool = False,
+                      min_level: int = 0, max_level: int = 12, max_leaves: int = 0,
+                      norm: float = 0.0, stream=None):
+    """Algorithm 3 on the device for sigma = sum_i a_i exp(-|x - c_i|^2/w_i^2):
+    returns (levels, coords, sigma, info) with sigma a float64 tensor on the
+    current device."""
+    import torch
+    L = _lib.lib()
+    g, keep = _gaussians(centers, widths, amps, periodic)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    o = _lib.fgt_resolve_opts_t(int(min_level), int(max_level), int(max_leaves), float(norm),
+                                ctypes.c_void_p(int(stream) or None))
+    h = ctypes.c_void_p()
+    check(L.fgt_resolve_gaussians(ctypes.byref(g), int(p), float(eps), ctypes.byref(o), ctypes.byref(h)),
+          "fgt_resolve_gaussians")
+    try:
+        info = _lib.fgt_density_info_t()
+        check(L.fgt_density_info(h, ctypes.byref(info)), "fgt_density_info")
+        info = info.as_dict()
+        n, d = info["nleaves"], info["dim"]
+        lv = np.zeros(n, dtype=np.int32)
+        cs = np.zeros((n, d), dtype=np.int32)
+        check(L.fgt_density_tree(h, lv.ctypes.data, cs.ctypes.data), "fgt_density_tree")
+        sig = torch.empty((n, int(p) ** d), dtype=torch.float64, device="cuda")
+        check(L.fgt_density_values(h, _ptr(sig)), "fgt_density_values")
+    finally:
+        L.fgt_density_destroy(h)
+    del keep
+    return lv, cs, sig, info
+
+
+def sample_gaussians(centers, widths, amps, levels, coords, p: int, periodic: bool = False):
+    """sigma at the nodes of the leaves (a new float64 tensor on the device)."""
+    import torch
+    g, keep = _gaussians(centers, widths, amps, periodic)
+    tree, tkeep = _tree(levels, coords)
+    sig = torch.empty((len(tkeep[0]), int(p) ** tkeep[1].shape[1]), dtype=torch.float64, device="cuda")
+    check(_lib.lib().fgt_sample_gaussians(ctypes.byref(g), ctypes.byref(tree), int(p), _ptr(sig),
+                                          torch.cuda.current_stream().cuda_stream),
+          "fgt_sample_gaussians")
+    del keep, tkeep
+    return sig

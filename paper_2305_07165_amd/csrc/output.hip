@@ -1,6 +1,7 @@
-// Output-tree refinement and coarsening of the box Gauss transform (Section
-// 4.2, Algorithms 5 and 6), and point evaluation of a tree's piecewise
-// polynomial (the leaf model of Eq. (papprox)).
+// Adaptive trees on the device: resolving a Gaussian-sum density (Algorithm
+// 3), output-tree refinement and coarsening of the box Gauss transform
+// (Section 4.2, Algorithms 5 and 6), and point evaluation of a tree's
+// piecewise polynomial (the leaf model of Eq. (papprox)).
 //
 // Device work: the coefficient-tail error estimate of Eq. (funerr) per box,
 // polynomial prolongation of leaf values to descendants, restriction of four
@@ -18,6 +19,7 @@
 #include <vector>
 
 #include "../../include/fgt.h"
+#include "../../include/fgt_density.h"
 #include "../../include/fgt_output.h"
 #include "fgt_host.h"
 #include "output_host.h"
@@ -29,6 +31,13 @@ struct fgt_output {
   int device = 0;
   double* u = nullptr;
   fgt_output_info_t info{};
+};
+
+struct fgt_density {
+  fgt::LeafTree tree;
+  int p = 0;
+  double* sigma = nullptr;
+  fgt_density_info_t info{};
 };
 
 namespace {
@@ -223,6 +232,45 @@ __global__ __launch_bounds__(kThreads) void k_restrict(double* __restrict__ pool
     }
     __syncthreads();
   }
+}
+
+// sigma(x) = sum_i a_i exp(-|x - c_i - s|^2 / w_i^2) at node j of box b, one
+// node per thread; the shifts s are {-1,0,1}^d when periodic, else 0.
+__global__ __launch_bounds__(kThreads) void k_sample_gauss(const int32_t* __restrict__ level,
+                                                           const int32_t* __restrict__ coord, int64_t nbox,
+                                                           int p, int d, const double* __restrict__ eta,
+                                                           const double* __restrict__ gc,
+                                                           const double* __restrict__ gw,
+                                                           const double* __restrict__ ga, int64_t ng,
+                                                           int periodic, double* __restrict__ out) {
+  const int np = ipow_i(p, d);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbox * np) return;
+  const int64_t b = t / np;
+  int j = (int)(t - b * np);
+  const double L = ldexp(1.0, -level[b]);
+  double x[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < d; a++) {
+    x[a] = -0.5 + ((double)coord[b * d + a] + 0.5) * L + 0.5 * L * eta[j % p];
+    j /= p;
+  }
+  const int nimg = periodic ? (d == 1 ? 3 : (d == 2 ? 9 : 27)) : 1;
+  double s = 0.0;
+  for (int64_t i = 0; i < ng; i++) {
+    const double w2 = gw[i] * gw[i];
+    for (int im = 0; im < nimg; im++) {
+      int code = im;
+      double r2 = 0.0;
+      for (int a = 0; a < d; a++) {
+        const double sh = periodic ? (double)(code % 3 - 1) : 0.0;
+        code /= 3;
+        const double dx = x[a] - (gc[i * d + a] + sh);
+        r2 += dx * dx;
+      }
+      s += ga[i] * exp(-r2 / w2);
+    }
+  }
+  out[t] = s;
 }
 
 // One point per thread: locate the leaf (last Morton start <= the point's
@@ -771,6 +819,183 @@ int resolve(const fgt_tree_t* tree, int p, double delta, double tol, int bc, con
   return FGT_OK;
 }
 
+// Device copies of a Gaussian sum and of the node positions.
+struct GaussDev {
+  int d = 0, periodic = 0;
+  int64_t n = 0;
+  double *c = nullptr, *w = nullptr, *a = nullptr, *eta = nullptr;
+};
+
+int check_gaussians(const fgt_gaussians_t* g) {
+  if (!g || g->dim < 1 || g->dim > 3 || g->n < 1 || !g->centers || !g->widths || !g->amps)
+    return fgt::set_error(FGT_ERR_INVALID_ARG, "gaussians NULL, empty or of dim outside 1..3");
+  for (int64_t i = 0; i < g->n; i++)
+    if (!(g->widths[i] > 0) || !std::isfinite(g->widths[i]) || !std::isfinite(g->amps[i]))
+      return fgt::set_error(FGT_ERR_INVALID_ARG, "gaussian widths must be > 0 and amplitudes finite");
+  for (int64_t i = 0; i < g->n * g->dim; i++)
+    if (!std::isfinite(g->centers[i])) return fgt::set_error(FGT_ERR_INVALID_ARG, "non-finite center");
+  return FGT_OK;
+}
+
+int gauss_upload(DevArena& ar, const fgt_gaussians_t* g, int p, hipStream_t st, GaussDev& gd) {
+  std::vector<double> eta(p), w(p);
+  fgt::gauss_legendre(p, eta.data(), w.data());
+  std::vector<double> c(g->centers, g->centers + g->n * g->dim), wd(g->widths, g->widths + g->n),
+      a(g->amps, g->amps + g->n);
+  gd.d = g->dim;
+  gd.n = g->n;
+  gd.periodic = g->periodic ? 1 : 0;
+  int rc;
+  if ((rc = ar.upload(c, &gd.c, st)) || (rc = ar.upload(wd, &gd.w, st)) || (rc = ar.upload(a, &gd.a, st)) ||
+      (rc = ar.upload(eta, &gd.eta, st)))
+    return rc;
+  // the host vectors are about to go out of scope
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(e, "gaussian upload");
+  return FGT_OK;
+}
+
+// sigma at the nodes of boxes (level[i], coord[i*d..]) into out[nbox][p^d]
+int sample_run(DevArena& ar, const GaussDev& gd, int p, const std::vector<int32_t>& level,
+               const std::vector<int32_t>& coord, double* out, hipStream_t st) {
+  const int64_t nbox = (int64_t)level.size();
+  if (nbox == 0) return FGT_OK;
+  int32_t *d_l, *d_c;
+  int rc;
+  if ((rc = ar.upload(level, &d_l, st)) || (rc = ar.upload(coord, &d_c, st))) return rc;
+  const int64_t nt = nbox * ipow_i(p, gd.d);
+  const int64_t nblk = (nt + kThreads - 1) / kThreads;
+  if (nblk >= ((int64_t)1 << 31)) return fgt::set_error(FGT_ERR_UNSUPPORTED, "too many nodes in one launch");
+  hipLaunchKernelGGL(k_sample_gauss, dim3((unsigned)nblk), dim3(kThreads), 0, st, d_l, d_c, nbox, p, gd.d, gd.eta,
+                     gd.c, gd.w, gd.a, gd.n, gd.periodic, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, "k_sample_gauss launch");
+  if ((e = hipStreamSynchronize(st))) return hip_err(e, "sample");
+  ar.release(d_l);
+  ar.release(d_c);
+  return FGT_OK;
+}
+
+// (int_{R^d} sigma^2)^(1/2) of the non-periodized sum, in closed form
+double gaussian_l2(const fgt_gaussians_t* g) {
+  const int d = g->dim;
+  double s = 0.0;
+  for (int64_t i = 0; i < g->n; i++)
+    for (int64_t j = 0; j < g->n; j++) {
+      const double wi2 = g->widths[i] * g->widths[i], wj2 = g->widths[j] * g->widths[j];
+      double r2 = 0.0;
+      for (int a = 0; a < d; a++) {
+        const double dx = g->centers[i * d + a] - g->centers[j * d + a];
+        r2 += dx * dx;
+      }
+      s += g->amps[i] * g->amps[j] * std::pow(M_PI * wi2 * wj2 / (wi2 + wj2), 0.5 * d) *
+           std::exp(-r2 / (wi2 + wj2));
+    }
+  return std::sqrt(std::max(s, 1e-300));
+}
+
+int resolve_density(const fgt_gaussians_t* g, int p, double eps, const fgt_resolve_opts_t& o,
+                    fgt_density* res) {
+  const int d = g->dim;
+  const int nd = 1 << d;
+  hipStream_t st = static_cast<hipStream_t>(o.stream);
+  DevArena ar(st);
+  TailCtx tc;
+  int rc = tail_setup(ar, p, d, st, tc);
+  if (rc) return rc;
+  if ((rc = lds_check(tc.lds))) return rc;
+  GaussDev gd;
+  if ((rc = gauss_upload(ar, g, p, st, gd))) return rc;
+  const int np = tc.np;
+  fgt_density_info_t& info = res->info;
+  info = fgt_density_info_t{};
+  info.dim = d;
+  info.p = p;
+  info.norm = o.norm > 0 ? o.norm : gaussian_l2(g);
+  info.threshold = eps * info.norm;
+
+  // level min_level: every box
+  std::vector<int32_t> bc;  // coords of the boxes of the current level
+  {
+    const int64_t nb = (int64_t)1 << o.min_level;
+    int64_t total = 1;
+    for (int a = 0; a < d; a++) total *= nb;
+    bc.resize(total * d);
+    for (int64_t i = 0; i < total; i++) {
+      int64_t r = i;
+      for (int a = 0; a < d; a++) {
+        bc[i * d + a] = (int32_t)(r % nb);
+        r /= nb;
+      }
+    }
+  }
+  fgt::LeafTree T;
+  T.d = d;
+  const int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 27) / np);  // <= 1 GiB of samples per launch
+  void* vals = nullptr;
+  int64_t vals_cap = 0;  // boxes the sample buffer holds
+  for (int l = o.min_level; !bc.empty(); l++) {
+    const int64_t nb = (int64_t)bc.size() / d;
+    std::vector<int32_t> next;
+    for (int64_t s0 = 0; s0 < nb; s0 += chunk) {
+      const int64_t m = std::min(chunk, nb - s0);
+      std::vector<uint8_t> split(m, 0);
+      if (l < o.max_level) {
+        if (m > vals_cap) {
+          if (vals) ar.release(vals);
+          vals = nullptr;
+          vals_cap = std::min(chunk, std::max(m, 2 * vals_cap));
+          if ((rc = ar.alloc(sizeof(double) * (size_t)np * vals_cap, &vals))) return rc;
+        }
+        std::vector<int32_t> lv(m, l), cs(bc.begin() + s0 * d, bc.begin() + (s0 + m) * d);
+        if ((rc = sample_run(ar, gd, p, lv, cs, static_cast<double*>(vals), st))) return rc;
+        std::vector<double> e, l2;
+        if ((rc = tail_run(ar, tc, static_cast<double*>(vals), nullptr, lv, st, e, l2))) return rc;
+        for (int64_t i = 0; i < m; i++) split[i] = e[i] > info.threshold;
+        info.boxes_sampled += m;
+      }
+      for (int64_t i = 0; i < m; i++) {
+        const int32_t* c = &bc[(s0 + i) * d];
+        if (!split[i]) {
+          T.level.push_back(l);
+          for (int a = 0; a < d; a++) T.coord.push_back(c[a]);
+          continue;
+        }
+        for (int k = 0; k < nd; k++)
+          for (int a = 0; a < d; a++) next.push_back(2 * c[a] + ((k >> a) & 1));
+      }
+    }
+    if (o.max_leaves > 0 && T.size() + (int64_t)next.size() / d > o.max_leaves)
+      return fgt::set_error(FGT_ERR_UNSUPPORTED, "the tree would exceed max_leaves");
+    bc.swap(next);
+  }
+  if (vals) ar.release(vals);
+  info.nleaves_unbalanced = T.size();
+  fgt::LeafTree B;
+  std::vector<int32_t> src;
+  fgt::split_and_balance(T, {}, g->periodic != 0, B, src, nullptr, nullptr);
+  void* sig = nullptr;
+  if ((rc = ar.alloc(sizeof(double) * (size_t)np * B.size(), &sig))) return rc;
+  for (int64_t s0 = 0; s0 < B.size(); s0 += chunk) {
+    const int64_t m = std::min(chunk, B.size() - s0);
+    std::vector<int32_t> lv(B.level.begin() + s0, B.level.begin() + s0 + m),
+        cs(B.coord.begin() + s0 * d, B.coord.begin() + (s0 + m) * d);
+    if ((rc = sample_run(ar, gd, p, lv, cs, static_cast<double*>(sig) + s0 * np, st))) return rc;
+  }
+  info.nleaves = B.size();
+  info.lmin = 1 << 30;
+  info.lmax = 0;
+  for (int32_t l : B.level) {
+    info.lmin = std::min(info.lmin, (int32_t)l);
+    info.lmax = std::max(info.lmax, (int32_t)l);
+  }
+  res->tree = std::move(B);
+  res->p = p;
+  res->sigma = static_cast<double*>(sig);
+  ar.keep(sig);
+  return FGT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -902,6 +1127,90 @@ int64_t fgt_tree_balance(const fgt_tree_t* tree, int bc, int32_t* level_out, int
   } catch (const std::bad_alloc&) {
     return fgt::set_error(FGT_ERR_OOM, "host allocation");
   }
+}
+
+int fgt_resolve_gaussians(const fgt_gaussians_t* g, int p, double eps, const fgt_resolve_opts_t* opts,
+                          fgt_density_t** out) {
+  if (!out) return fgt::set_error(FGT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_gaussians(g);
+  if (rc) return rc;
+  if (p < 1 || p > fgt::kMaxP) return fgt::set_error(FGT_ERR_INVALID_ARG, "p must be in [1,16]");
+  if (!(eps > 0 && eps < 1)) return fgt::set_error(FGT_ERR_INVALID_ARG, "eps must be in (0, 1)");
+  fgt_resolve_opts_t o{0, 12, 0, 0.0, nullptr};
+  if (opts) o = *opts;
+  const int maxlev = g->dim == 3 ? 19 : (g->dim == 2 ? 28 : 30);
+  if (o.min_level < 0 || o.max_level < o.min_level || o.max_level > maxlev || o.max_leaves < 0 || o.norm < 0)
+    return fgt::set_error(FGT_ERR_INVALID_ARG, "need 0 <= min_level <= max_level <= the dimension's limit");
+  if ((int64_t)g->dim * o.min_level > 24)
+    return fgt::set_error(FGT_ERR_UNSUPPORTED, "min_level gives more than 2^24 boxes");
+  fgt_density* res = new (std::nothrow) fgt_density();
+  if (!res) return fgt::set_error(FGT_ERR_OOM, "host allocation");
+  try {
+    rc = resolve_density(g, p, eps, o, res);
+  } catch (const std::bad_alloc&) {
+    rc = fgt::set_error(FGT_ERR_OOM, "host allocation");
+  }
+  if (rc) {
+    delete res;
+    return rc;
+  }
+  *out = res;
+  return FGT_OK;
+}
+
+int fgt_density_info(const fgt_density_t* r, fgt_density_info_t* info) {
+  if (!r || !info) return fgt::set_error(FGT_ERR_INVALID_ARG, "NULL argument");
+  *info = r->info;
+  return FGT_OK;
+}
+
+int fgt_density_tree(const fgt_density_t* r, int32_t* level, int32_t* coord) {
+  if (!r || !level || !coord) return fgt::set_error(FGT_ERR_INVALID_ARG, "NULL argument");
+  std::copy(r->tree.level.begin(), r->tree.level.end(), level);
+  std::copy(r->tree.coord.begin(), r->tree.coord.end(), coord);
+  return FGT_OK;
+}
+
+int fgt_density_values(const fgt_density_t* r, double* sigma_dev) {
+  if (!r || !sigma_dev) return fgt::set_error(FGT_ERR_INVALID_ARG, "NULL argument");
+  const size_t bytes = sizeof(double) * (size_t)r->tree.size() * ipow_i(r->p, r->tree.d);
+  hipError_t e = hipMemcpy(sigma_dev, r->sigma, bytes, hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) return hip_err(e, "hipMemcpy");
+  return FGT_OK;
+}
+
+void fgt_density_destroy(fgt_density_t* r) {
+  if (!r) return;
+  if (r->sigma) (void)hipFree(r->sigma);
+  delete r;
+}
+
+int fgt_sample_gaussians(const fgt_gaussians_t* g, const fgt_tree_t* tree, int p, double* sigma_dev,
+                         void* stream) {
+  int rc = check_gaussians(g);
+  if (rc || (rc = check_tree(tree))) return rc;
+  if (tree->dim != g->dim) return fgt::set_error(FGT_ERR_INVALID_ARG, "tree and gaussians differ in dim");
+  if (p < 1 || p > fgt::kMaxP) return fgt::set_error(FGT_ERR_INVALID_ARG, "p must be in [1,16]");
+  if (!sigma_dev) return fgt::set_error(FGT_ERR_INVALID_ARG, "sigma is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  try {
+    DevArena ar(st);
+    GaussDev gd;
+    if ((rc = gauss_upload(ar, g, p, st, gd))) return rc;
+    const int d = tree->dim;
+    const int64_t np = ipow_i(p, d);
+    const int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 27) / np);
+    for (int64_t s0 = 0; s0 < tree->nleaves; s0 += chunk) {
+      const int64_t m = std::min(chunk, tree->nleaves - s0);
+      std::vector<int32_t> lv(tree->level + s0, tree->level + s0 + m),
+          cs(tree->coord + s0 * d, tree->coord + (s0 + m) * d);
+      if ((rc = sample_run(ar, gd, p, lv, cs, sigma_dev + s0 * np, st))) return rc;
+    }
+  } catch (const std::bad_alloc&) {
+    return fgt::set_error(FGT_ERR_OOM, "host allocation");
+  }
+  return FGT_OK;
 }
 
 }  // extern "C"
