@@ -158,6 +158,13 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
 // ---------------------------------------------------------------------------
 // last-axis formation merged over the leaves of a cutoff box (a grouped GEMM)
 
+// 16-column slabs per wave of form_box; a workgroup covers 64 x slabs columns.
+// Measured on the 3D benchmark tree: 4 slabs beat 2 (the former choice), 3 and,
+// for nt <= 3, 8 -- independent product chains per wave matter more here than
+// occupancy (4 slabs leave one wave per SIMD at p = 16 in FP64)
+__host__ __device__ constexpr int form_box_slabs(int) { return 4; }
+__host__ __device__ constexpr int form_box_cols(int nt) { return 64 * form_box_slabs(nt); }
+
 template <typename C, int D, int NT, int KS>
 __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
                                                 const int32_t* __restrict__ fitem,
@@ -166,34 +173,34 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
                                                 int ncoltiles, elem_t<C>* __restrict__ phi,
                                                 elem_t<C>* __restrict__ partial, int bid) {
   typedef elem_t<C> T;
-  // one work item (<= kFormLeaves leaves of a box) x 128 columns per workgroup;
-  // every wave owns two 16-column slabs, sharing the table operand between them
+  // one work item (<= kFormLeaves leaves of a box) x form_box_cols(NT) columns
+  // per workgroup; every wave owns H 16-column slabs, sharing the table operand
   typedef Mfma<C> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<C, KS>::value;
+  constexpr int H = form_box_slabs(NT);
   const int item = bid / ncoltiles;
   const int ct = bid % ncoltiles;
   const int A = fitem[4 * item], slot = fitem[4 * item + 3];
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
   const int N2 = D == 3 ? nr * nr : nr;
-  int col[2];
-  bool colok[2];
+  int col[H];
+  bool colok[H];
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
-    col[h] = ct * 128 + w * 32 + 16 * h + lr;
+  for (int h = 0; h < H; h++) {
+    col[h] = ct * form_box_cols(NT) + w * (16 * H) + 16 * h + lr;
     colok[h] = col[h] < N2;
   }
-  acc_t acc[NT][2];
+  acc_t acc[NT][H];
 #pragma unroll
-  for (int ti = 0; ti < NT; ti++) {
-    zero4(acc[ti][0]);
-    zero4(acc[ti][1]);
-  }
+  for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+    for (int h = 0; h < H; h++) zero4(acc[ti][h]);
   const int s0 = fitem[4 * item + 1], s1 = fitem[4 * item + 2];
   // operands of leaf s; loads are masked, not branched, so that no control-flow
   // join forces a wait for the prefetched leaf before the current products
-  auto load = [&](int s, T (&aa)[NT][S], T (&bb)[S][2]) {
+  auto load = [&](int s, T (&aa)[NT][S], T (&bb)[S][H]) {
     const bool ls = s < s1;
     const int sc = ls ? s : s0;
     const T* Fs = F + (int64_t)leaf_tab[sc * D + (D - 1)] * nr * p;
@@ -202,7 +209,7 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
     for (int kk = 0; kk < S; kk++) {
       const int k = M::kidx(kk, lk);
 #pragma unroll
-      for (int h = 0; h < 2; h++) bb[kk][h] = ld0<T>(Ys, (int64_t)k * N2 + col[h], ls && k < p && colok[h]);
+      for (int h = 0; h < H; h++) bb[kk][h] = ld0<T>(Ys, (int64_t)k * N2 + col[h], ls && k < p && colok[h]);
 #pragma unroll
       for (int ti = 0; ti < NT; ti++) {
         const int r = 16 * ti + lr;
@@ -210,13 +217,13 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
       }
     }
   };
-  T a[NT][S], b[S][2];
+  T a[NT][S], b[S][H];
   load(s0, a, b);
   for (int s = s0; s < s1; s++) {
-    T an[NT][S], bn[S][2];
+    T an[NT][S], bn[S][H];
     load(s + 1, an, bn);
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
+    for (int h = 0; h < H; h++) {
       T bh[S];
 #pragma unroll
       for (int kk = 0; kk < S; kk++) bh[kk] = b[kk][h];
@@ -225,8 +232,8 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
     }
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
-      b[kk][0] = bn[kk][0];
-      b[kk][1] = bn[kk][1];
+#pragma unroll
+      for (int h = 0; h < H; h++) b[kk][h] = bn[kk][h];
 #pragma unroll
       for (int ti = 0; ti < NT; ti++) a[ti][kk] = an[ti][kk];
     }
@@ -239,7 +246,7 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
     for (int t = 0; t < 4; t++) {
       const int r = 16 * ti + M::row(lk, t);
 #pragma unroll
-      for (int h = 0; h < 2; h++)
+      for (int h = 0; h < H; h++)
         if (r < nr && colok[h]) out[(int64_t)r * N2 + col[h]] = acc[ti][h][t];
     }
 }
@@ -1002,7 +1009,7 @@ template <typename C, int D, int NT, int KS>
 __global__ __launch_bounds__(256) void form_box_b(FGT_BATCH_PARAMS) {
   typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  const int ncol128 = (n2_of(D, a.nr) + 127) / 128;
+  const int ncol128 = (n2_of(D, a.nr) + form_box_cols(NT) - 1) / form_box_cols(NT);
   form_box_body<C, D, NT, KS>(cptr<T>(a.Y), a.fitem, D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
                               ncol128,
                               mptr<T>(a.phi), mptr<T>(a.partial), bid);
@@ -1171,7 +1178,12 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
       const int nt = kernel_class(a).nt, tg = form3_tile_group(nt);
       return a.nPl * ((a.p * ((nt + tg - 1) / tg) + 3) / 4);
     }
-    case kFormBox: return pw ? (a.d == 3 ? a.nFI * ((N2 + 127) / 128) : a.nFI) : 0;
+    case kFormBox: {
+      if (!pw) return 0;
+      if (a.d != 3) return a.nFI;
+      const int cols = form_box_cols(kernel_class(a).nt);
+      return a.nFI * ((N2 + cols - 1) / cols);
+    }
     case kReduce: return pw && a.nFR > 0 ? a.nFR * ((N2 * nr + 255) / 256) : 0;
     case kTranslate: return pw ? (a.d == 3 && a.fuse_te ? transeval3_blocks(a) : translate_blocks(a)) : 0;
     // d = 3: a separate stage unless fused into the translation; d = 2: fused into eval2_leaf
@@ -1275,7 +1287,7 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
   rec(0);
   if (a.nL > 0) {
     if (D == 3) {
-      const int N2 = nr * nr, ncol = (N2 + 63) / 64, ncol128 = (N2 + 127) / 128;
+      const int N2 = nr * nr, ncol = (N2 + 63) / 64, ncol128 = (N2 + form_box_cols(NT) - 1) / form_box_cols(NT);
       hipLaunchKernelGGL((form3_plane<C, NT, KS>), dim3((unsigned)stage_blocks(a, kFormLeaf)), dim3(256), 0, st, sigma,
                          a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, F, p, nr, Y);
       rec(1);
