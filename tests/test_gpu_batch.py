@@ -132,3 +132,26 @@ def test_batch_rejects_host_only_plans():
     hp = api.Plan(t.levels, t.coords, t.p, t.delta, t.tol, host_only=True)
     with pytest.raises(api.FgtError):
         api.Batch([hp])
+
+
+def test_batch_with_a_fused_plan_equals_alone():
+    """A large 3D plan whose translation runs fused with the first evaluation
+    step (fgt_info_t.fused_translate) batched with a small 2D plan: the fused
+    batched kernel must reproduce the plan's own result bitwise."""
+    pr = synth.adaptive_3d(0)
+    small = _problems()[0]
+    plans = [api.Plan(pr.levels, pr.coords, pr.p, pr.delta, 1e-6),
+             api.Plan(small.levels, small.coords, small.p, small.delta, small.tol, precision=small.precision)]
+    assert plans[0].info()["fused_translate"] == 1
+    sig = [torch.from_numpy(pr.sigma).cuda(), torch.from_numpy(small.sigma).cuda()]
+    ref = _alone(plans, sig)
+    for use_graph in (True, False):
+        b = api.Batch(plans, use_graph=use_graph)
+        us = [torch.full_like(s, float("nan")) for s in sig]
+        b.bind(sig, us)
+        b.execute()
+        torch.cuda.synchronize()
+        _say(f"fused batch graph={use_graph}: {b.info()}")
+        for i, (u, r) in enumerate(zip(us, ref)):
+            assert torch.equal(u, r), f"job {i} differs from its result alone"
+        b.close()
