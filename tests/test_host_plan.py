@@ -485,3 +485,40 @@ def test_tree_balance_matches_the_input_generator(d):
     lv, cs = synth.uniform_tree(d, 2)
     b = api.fgt_tree_balance(lv, cs)
     assert len(b[0]) == len(lv)
+
+
+def test_tree_entry_points_validate_arguments_before_any_device_call():
+    """The output-tree, density and interpolation entry points reject bad
+    arguments on the host (no device is touched, so this runs on a CPU)."""
+    L = _lib.lib()
+    lv, cs = synth.uniform_tree(2, 2)
+    tree, keep = api._tree(lv, cs)
+    out = ctypes.c_void_p()
+    oo = _lib.fgt_output_opts_t(0.0, 1, 1, 0)
+    # NULL sigma, p out of range, eps out of range
+    assert L.fgt_output_resolve(ctypes.byref(tree), 4, 1e-3, 1e-6, 0, None, ctypes.byref(oo), None,
+                                ctypes.byref(out)) == _lib.FGT_ERR_INVALID_ARG
+    assert L.fgt_output_resolve(ctypes.byref(tree), 0, 1e-3, 1e-6, 0, None, ctypes.byref(oo), 8,
+                                ctypes.byref(out)) == _lib.FGT_ERR_INVALID_ARG
+    bad = _lib.fgt_output_opts_t(1.5, 1, 1, 0)
+    assert L.fgt_output_resolve(ctypes.byref(tree), 4, 1e-3, 1e-6, 0, None, ctypes.byref(bad), 8,
+                                ctypes.byref(out)) == _lib.FGT_ERR_INVALID_ARG
+    # a coordinate outside its level's range
+    cs2 = cs.copy()
+    cs2[0, 0] = 9
+    tree2, keep2 = api._tree(lv, cs2)
+    assert L.fgt_interp(ctypes.byref(tree2), 4, 8, 1, 8, 8, None) == _lib.FGT_ERR_NOT_TILING
+    assert L.fgt_interp(ctypes.byref(tree), 4, 8, -1, 8, 8, None) == _lib.FGT_ERR_INVALID_ARG
+    assert L.fgt_interp(ctypes.byref(tree), 4, 8, 0, None, None, None) == _lib.FGT_OK  # nothing to do
+    assert L.fgt_tree_balance(ctypes.byref(tree), 7, None, None, 0) == _lib.FGT_ERR_INVALID_ARG
+    # gaussians: zero width, eps, level range
+    g, gk = api._gaussians(np.array([[0.0, 0.0]]), np.array([0.0]), np.array([1.0]), False)
+    assert L.fgt_resolve_gaussians(ctypes.byref(g), 8, 1e-8, None, ctypes.byref(out)) == _lib.FGT_ERR_INVALID_ARG
+    g, gk = api._gaussians(np.array([[0.0, 0.0]]), np.array([0.1]), np.array([1.0]), False)
+    assert L.fgt_resolve_gaussians(ctypes.byref(g), 8, 0.0, None, ctypes.byref(out)) == _lib.FGT_ERR_INVALID_ARG
+    o = _lib.fgt_resolve_opts_t(5, 3, 0, 0.0, None)
+    assert L.fgt_resolve_gaussians(ctypes.byref(g), 8, 1e-8, ctypes.byref(o), ctypes.byref(out)) == \
+        _lib.FGT_ERR_INVALID_ARG
+    assert L.fgt_sample_gaussians(ctypes.byref(g), ctypes.byref(tree), 8, None, None) == _lib.FGT_ERR_INVALID_ARG
+    assert out.value is None
+    del keep, keep2, gk
