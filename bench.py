@@ -335,8 +335,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this transform runs on one GPU; a figure at several GPUs is not "
-              "part of this build (the sharded design is described in DESIGN.md).",
+        print("bench.py: the transform runs on one GPU only; there is no multi-GPU run "
+              "(it would shard by cutoff-level subtrees with a one-box halo of sigma).",
               file=sys.stderr)
         sys.exit(2)
 
