@@ -304,16 +304,22 @@ def small_2d(seed: int = 0) -> Problem:
                    sample(lv, cs, 8, dens), dens)
 
 
+def adaptive_3d_density(seed: int = 0, nblobs: int = 8, wrap_blobs: bool = False) -> GaussianSum:
+    """The density of the 3D workload: 8 Gaussians with widths log-uniform in
+    [1e-3,1e-2], amplitudes U(-1,1) and centers U[-0.4,0.4]^3, or U[-0.5,0.5]^3
+    periodized over Z^3 when wrap_blobs."""
+    rng = np.random.default_rng(seed)
+    lo, hi = (-0.5, 0.5) if wrap_blobs else (-0.4, 0.4)
+    return GaussianSum(*_blobs(rng, nblobs, 3, lo, hi, 1e-3, 1e-2, True), periodic=wrap_blobs)
+
+
 def adaptive_3d(seed: int = 0, periodic: bool = False, eps: float = 1e-9,
                 max_level: int = 7, delta: float = 1e-4, tol: float = 1e-10,
                 nblobs: int = 8, wrap_blobs: bool = False) -> Problem:
     """3D adaptive tree, p=16, resolving sigma = sum of 8 Gaussians (widths
     log-uniform in [1e-3,1e-2], centers U[-0.4,0.4]^3, amplitudes U(-1,1)) to
     a Legendre-tail RMS of eps*||sigma||_2, levels capped at max_level."""
-    rng = np.random.default_rng(seed)
-    lo, hi = (-0.5, 0.5) if wrap_blobs else (-0.4, 0.4)
-    dens = GaussianSum(*_blobs(rng, nblobs, 3, lo, hi, 1e-3, 1e-2, True),
-                       periodic=wrap_blobs)
+    dens = adaptive_3d_density(seed, nblobs, wrap_blobs)
     lv, cs = resolve_tree(dens, 3, 16, eps, max_level=max_level, periodic=periodic)
     name = f"3d-adaptive-p16-{'periodic' if periodic else 'free'}"
     return Problem(name, 3, 16, delta, tol, periodic, lv, cs,
