@@ -256,7 +256,8 @@ def batched_form(probs, steps, log):
     info = b.info()
     log(f"batched: {1e3 * dt:.2f} ms per batch ({npts / dt:.3e} pts/s), tuned {tuned:.2f} ms, "
         f"{info['nclasses']} classes, {info['nlaunches']} launches, streams {info['nstreams']}, "
-        f"class-major {info['class_major']}, bitwise equal to sequential: {same}")
+        f"class-major {info['class_major']}, alternative form tile in {info['tile_alt_classes']} classes, "
+        f"bitwise equal to sequential: {same}")
     b.close()
     for pl in plans:
         pl.close()
@@ -264,7 +265,8 @@ def batched_form(probs, steps, log):
             "npoints": npts, "sequential_fp64_ms": 1e3 * dt64, "sequential_same_precision_ms": 1e3 * dtmix,
             "speedup_vs_sequential_fp64": dt64 / dt, "speedup_vs_sequential_same_precision": dtmix / dt,
             "bitwise_equal_to_sequential": same, "tuned_ms": tuned,
-            "schedule": {"nstreams": info["nstreams"], "class_major": bool(info["class_major"])},
+            "schedule": {"nstreams": info["nstreams"], "class_major": bool(info["class_major"]),
+                         "form_tile_alt_classes": info["tile_alt_classes"]},
             "nclasses": info["nclasses"], "nlaunches": info["nlaunches"],
             "precisions": {"fp32": sum(t.precision == "fp32" for t in probs),
                            "fp64": sum(t.precision == "fp64" for t in probs)}}

@@ -14,7 +14,11 @@
  *
  * An autotuner (fgt_batch_tune) times the legal launch schedules -- how many
  * streams the classes are spread over and whether a stream runs its classes
- * stage by stage or class by class -- and keeps the fastest.
+ * stage by stage or class by class -- and keeps the fastest; then, per kernel
+ * class, the tile shape of the d = 3 box formation (four or two 16-column
+ * slabs per wave), keeping the other shape where it measures faster.  Tile
+ * shapes change neither the columns nor the order of any sum: results stay
+ * bitwise identical.
  *
  * 1D plans are accepted and run with their own (non-batched) launches inside
  * the same graph.  Every function returns FGT_OK or a negative FGT_ERR_* code.
@@ -37,6 +41,9 @@ typedef struct fgt_batch_opts {
   int32_t nstreams;    /* schedule: streams the classes are spread over (1..8; 0 = 1) */
   int32_t class_major; /* schedule: 1 = each stream runs its classes one after the other,
                           0 = stage by stage across its classes */
+  int32_t form_tile;   /* box-formation tile shape of every d = 3 class until fgt_batch_tune
+                          chooses per class: 0 (default) = four 16-column slabs per wave,
+                          as fgt_execute; 1 = two */
 } fgt_batch_opts_t;
 
 typedef struct fgt_batch_info {
@@ -46,6 +53,7 @@ typedef struct fgt_batch_info {
   int32_t nlaunches;    /* kernel launches per execution */
   int32_t nstreams, class_major, use_graph;
   double tuned_ms;      /* best time per execution found by fgt_batch_tune (0 if not tuned) */
+  int32_t tile_alt_classes; /* classes whose box formation runs the alternative tile shape */
 } fgt_batch_info_t;
 
 /* Builds a batch over nplans resident plans (not host-only, all on the current
@@ -63,9 +71,11 @@ int fgt_batch_bind(fgt_batch_t* b, const double* const* sigma, double* const* u)
 int fgt_batch_execute(fgt_batch_t* b);
 
 /* Times every schedule (nstreams in {1, 2, 4} x {stage by stage, class by
-   class}) with `reps` executions each after one warm-up, keeps the fastest
-   and returns its mean time per execution in *best_ms (may be NULL).  The
-   batch must be bound.  Synchronizes the batch's stream. */
+   class}) with `reps` executions each after one warm-up and keeps the
+   fastest; then tries the alternative box-formation tile of each d = 3 class
+   (largest first) and keeps it where the execution gets more than 0.5%
+   faster.  Returns the best mean time per execution in *best_ms (may be
+   NULL).  The batch must be bound.  Synchronizes the batch's stream. */
 int fgt_batch_tune(fgt_batch_t* b, int32_t reps, double* best_ms);
 
 int fgt_batch_info(const fgt_batch_t* b, fgt_batch_info_t* info);

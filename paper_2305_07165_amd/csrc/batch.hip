@@ -6,7 +6,7 @@
 // stream and replayed on the batch's stream.  A schedule spreads the classes
 // over one or more streams (a fork/join inside the graph) and orders each
 // stream's launches stage by stage or class by class; fgt_batch_tune picks
-// the schedule by timing.
+// the schedule by timing, then the box-formation tile shape of each class.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,11 +23,15 @@ struct ClassRun {
   fgt::KernelClass kc;
   std::vector<int> members;                 // plan indices
   int64_t grid[fgt::kNumStages] = {};       // blocks of each stage's launch
-  std::vector<int32_t> start, count;        // [kNumStages][n], host copies
+  std::vector<int32_t> start, count;        // [kNumStages + 1][n], host copies; the last
+                                            // row: box formation with tile 1
+  int64_t grid_alt = 0;                     // blocks of box formation with tile 1
+  int tile = 0;                             // box-formation tile shape (kFormBoxTileSlabs)
   double work = 0;                          // blocks over all stages (schedule weight)
   fgt::BatchJob* jobs = nullptr;            // device [n]
-  int32_t* dstart = nullptr;                // device [kNumStages][n]
+  int32_t* dstart = nullptr;                // device [kNumStages + 1][n]
   int32_t* dcount = nullptr;
+  bool has_tiles() const { return kc.d == 3 && grid[fgt::kFormBox] > 0; }
 };
 
 int herr(hipError_t e, const char* what) {
@@ -112,8 +116,10 @@ int enqueue(fgt_batch* b, hipStream_t st) {
       ClassRun& cr = b->classes[c];
       if (cr.grid[stage] == 0) return FGT_OK;
       const int n = (int)cr.members.size();
-      hipError_t le = fgt::launch_stage_batched(cr.kc, stage, cr.jobs, cr.dstart + (size_t)stage * n,
-                                                cr.dcount + (size_t)stage * n, n, cr.grid[stage], s);
+      const bool alt = stage == fgt::kFormBox && cr.tile == 1;
+      const size_t row = alt ? (size_t)fgt::kNumStages : (size_t)stage;
+      hipError_t le = fgt::launch_stage_batched(cr.kc, stage, cr.jobs, cr.dstart + row * n, cr.dcount + row * n, n,
+                                                alt ? cr.grid_alt : cr.grid[stage], s, alt ? 1 : 0);
       if (le != hipSuccess) return herr(le, "batched launch");
       launches++;
       return FGT_OK;
@@ -202,6 +208,8 @@ int fgt_batch_create(fgt_plan_t* const* plans, int64_t nplans, const fgt_batch_o
   if (opts) o = *opts;
   if (o.nstreams == 0) o.nstreams = 1;
   if (o.nstreams < 1 || o.nstreams > 8) return fgt::set_error(FGT_ERR_INVALID_ARG, "nstreams must be 1..8");
+  if (o.form_tile < 0 || o.form_tile >= fgt::kFormBoxTiles)
+    return fgt::set_error(FGT_ERR_INVALID_ARG, "form_tile must be 0 or 1");
   fgt_batch* b = new (std::nothrow) fgt_batch();
   if (!b) return fgt::set_error(FGT_ERR_OOM, "host allocation");
   hipError_t e = hipGetDevice(&b->device);
@@ -242,23 +250,28 @@ int fgt_batch_create(fgt_plan_t* const* plans, int64_t nplans, const fgt_batch_o
   }
   for (ClassRun& cr : b->classes) {
     const int n = (int)cr.members.size();
-    cr.start.assign((size_t)fgt::kNumStages * n, 0);
-    cr.count.assign((size_t)fgt::kNumStages * n, 0);
-    for (int stage = 0; stage < fgt::kNumStages; stage++) {
+    cr.start.assign((size_t)(fgt::kNumStages + 1) * n, 0);
+    cr.count.assign((size_t)(fgt::kNumStages + 1) * n, 0);
+    // row kNumStages: box formation with the alternative tile shape
+    for (int stage = 0; stage <= fgt::kNumStages; stage++) {
       int64_t at = 0;
       for (int j = 0; j < n; j++) {
-        const int64_t nb = fgt::stage_blocks(plans[cr.members[j]]->args, stage);
+        const fgt::DeviceArgs& ja = plans[cr.members[j]]->args;
+        const int64_t nb = stage < fgt::kNumStages ? fgt::stage_blocks(ja, stage)
+                                                   : (cr.kc.d == 3 ? fgt::form_box_blocks(ja, fgt::kFormBoxTileSlabs[1])
+                                                                   : fgt::stage_blocks(ja, fgt::kFormBox));
         at = (at + 7) / 8 * 8;  // keep block % 8 == XCD of the transform's own blocks
         cr.start[(size_t)stage * n + j] = (int32_t)at;
         cr.count[(size_t)stage * n + j] = (int32_t)nb;
         at += nb;
-        cr.work += (double)nb;
+        if (stage < fgt::kNumStages) cr.work += (double)nb;
       }
       if (at > 0x7fffffff) {
         release(b);
         return fgt::set_error(FGT_ERR_UNSUPPORTED, "a batched launch would exceed 2^31 workgroups");
       }
-      cr.grid[stage] = at;
+      if (stage < fgt::kNumStages) cr.grid[stage] = at;
+      else cr.grid_alt = at;
     }
     void* m = nullptr;
     const size_t jb = sizeof(fgt::BatchJob) * n, ib = sizeof(int32_t) * cr.start.size();
@@ -277,6 +290,8 @@ int fgt_batch_create(fgt_plan_t* const* plans, int64_t nplans, const fgt_batch_o
       return herr(e, "hipMemcpy");
     }
   }
+  for (ClassRun& cr : b->classes)
+    if (cr.has_tiles()) cr.tile = o.form_tile;
   b->sigma.assign(nplans, nullptr);
   b->u.assign(nplans, nullptr);
   int rc;
@@ -340,6 +355,7 @@ int fgt_batch_tune(fgt_batch_t* b, int32_t reps, double* best_ms) {
     (void)hipEventDestroy(t0);
     return herr(e, "hipEventCreate");
   }
+  for (ClassRun& cr : b->classes) cr.tile = 0;  // schedules are timed with the default tiles
   const int cand_ns[3] = {1, 2, 4};
   double best = -1;
   int best_ns = b->nstreams;
@@ -367,10 +383,42 @@ int fgt_batch_tune(fgt_batch_t* b, int32_t reps, double* best_ms) {
       }
     }
   }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
   b->nstreams = best_ns;
   b->class_major = best_cm;
+  drop_graph(b);
+  if (rc == FGT_OK) rc = ensure_side_streams(b);
+  // tile shapes: with the schedule fixed, try the alternative box-formation
+  // tile for each class that has one, largest class first, and keep it when
+  // the whole execution gets faster by more than the timing noise (0.5%)
+  std::vector<int> order;
+  for (size_t c = 0; c < b->classes.size(); c++)
+    if (b->classes[c].has_tiles()) order.push_back((int)c);
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return b->classes[x].work > b->classes[y].work; });
+  auto time_once = [&](double* per) -> int {
+    drop_graph(b);
+    int r = launch(b);  // warm-up (and capture)
+    if (r != FGT_OK) return r;
+    if ((e = hipEventRecord(t0, b->stream)) != hipSuccess) return herr(e, "hipEventRecord");
+    for (int k = 0; k < reps && r == FGT_OK; k++) r = launch(b);
+    if (r != FGT_OK) return r;
+    if ((e = hipEventRecord(t1, b->stream)) != hipSuccess) return herr(e, "hipEventRecord");
+    if ((e = hipEventSynchronize(t1)) != hipSuccess) return herr(e, "hipEventSynchronize");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    *per = ms / reps;
+    return FGT_OK;
+  };
+  if (rc == FGT_OK && !order.empty()) rc = time_once(&best);  // the fixed schedule, tiles 0
+  for (size_t k = 0; k < order.size() && rc == FGT_OK; k++) {
+    ClassRun& cr = b->classes[order[k]];
+    cr.tile = 1;
+    double per = 0;
+    if ((rc = time_once(&per)) != FGT_OK) break;
+    if (per < 0.995 * best) best = per;
+    else cr.tile = 0;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
   drop_graph(b);
   if (rc != FGT_OK) return rc;
   b->tuned_ms = best;
@@ -397,6 +445,7 @@ int fgt_batch_info(const fgt_batch_t* b, fgt_batch_info_t* info) {
   info->class_major = b->class_major ? 1 : 0;
   info->use_graph = b->use_graph ? 1 : 0;
   info->tuned_ms = b->tuned_ms;
+  for (const ClassRun& cr : b->classes) info->tile_alt_classes += cr.tile == 1;
   return FGT_OK;
 }
 

@@ -72,6 +72,11 @@ KernelClass kernel_class(const DeviceArgs& a);
 // not run); the grids of launch_fast.
 int64_t stage_blocks(const DeviceArgs& a, int stage);
 int64_t translate_blocks(const DeviceArgs& a);
+// Workgroups of the d = 3 box formation with `slabs` 16-column slabs per wave
+// (tile 0 of a batched launch: 4 slabs, as fgt_execute; tile 1: 2 slabs).
+int64_t form_box_blocks(const DeviceArgs& a, int slabs);
+constexpr int kFormBoxTiles = 2;
+constexpr int kFormBoxTileSlabs[kFormBoxTiles] = {4, 2};
 
 // Block b of a batched launch belongs to the last job j with start[j] <= b.
 __device__ __forceinline__ int batch_job_of(const int32_t* __restrict__ start, int njobs, int b) {
@@ -87,9 +92,11 @@ __device__ __forceinline__ int batch_job_of(const int32_t* __restrict__ start, i
 // Launches one stage for njobs transforms of class c.  jobs, start and count
 // are device arrays: job j owns blocks [start[j], start[j] + count[j]) of a
 // grid of `grid` blocks, start[j] a multiple of 8 (blocks past count[j] exit).
+// tile selects the tile shape of stages that have two (the d = 3 box
+// formation: kFormBoxTileSlabs[tile] slabs per wave); the grid must match it.
 hipError_t launch_stage_batched(const KernelClass& c, int stage, const BatchJob* jobs,
                                 const int32_t* start, const int32_t* count, int njobs,
-                                int64_t grid, hipStream_t st);
+                                int64_t grid, hipStream_t st, int tile = 0);
 template <typename T>
 void launch_translate_batched(int d, const BatchJob* jobs, const int32_t* start,
                               const int32_t* count, int njobs, int64_t grid, hipStream_t st);

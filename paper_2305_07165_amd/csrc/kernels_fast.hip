@@ -158,14 +158,18 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
 // ---------------------------------------------------------------------------
 // last-axis formation merged over the leaves of a cutoff box (a grouped GEMM)
 
-// 16-column slabs per wave of form_box; a workgroup covers 64 x slabs columns.
-// Measured on the 3D benchmark tree: 4 slabs beat 2 (the former choice), 3 and,
-// for nt <= 3, 8 -- independent product chains per wave matter more here than
-// occupancy (4 slabs leave one wave per SIMD at p = 16 in FP64)
-__host__ __device__ constexpr int form_box_slabs(int) { return 4; }
-__host__ __device__ constexpr int form_box_cols(int nt) { return 64 * form_box_slabs(nt); }
+// Tile shape of form_box: 16-column slabs per wave (H); a workgroup covers
+// 64 H columns.  fgt_execute uses kFormBoxSlabs: on the 3D benchmark tree 4
+// slabs beat 2, 3 and (for nt <= 3) 8 -- independent product chains per wave
+// matter more than occupancy (4 slabs leave one wave per SIMD at p = 16 in
+// FP64).  Batches may run a class with the other shape, kFormBoxSlabsAlt, when
+// the autotuner measures it faster; the columns and the order of every sum
+// are the same, so results are identical.
+constexpr int kFormBoxSlabs = kFormBoxTileSlabs[0];
+constexpr int kFormBoxSlabsAlt = kFormBoxTileSlabs[1];
+__host__ __device__ constexpr int form_box_cols_of(int slabs) { return 64 * slabs; }
 
-template <typename C, int D, int NT, int KS>
+template <typename C, int D, int NT, int KS, int H>
 __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
                                                 const int32_t* __restrict__ fitem,
                                                 const int32_t* __restrict__ leaf_tab,
@@ -173,12 +177,11 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
                                                 int ncoltiles, elem_t<C>* __restrict__ phi,
                                                 elem_t<C>* __restrict__ partial, int bid) {
   typedef elem_t<C> T;
-  // one work item (<= kFormLeaves leaves of a box) x form_box_cols(NT) columns
-  // per workgroup; every wave owns H 16-column slabs, sharing the table operand
+  // one work item (<= kFormLeaves leaves of a box) x 64 H columns per
+  // workgroup; every wave owns H 16-column slabs, sharing the table operand
   typedef Mfma<C> M;
   typedef typename M::acc acc_t;
   constexpr int S = Steps<C, KS>::value;
-  constexpr int H = form_box_slabs(NT);
   const int item = bid / ncoltiles;
   const int ct = bid % ncoltiles;
   const int A = fitem[4 * item], slot = fitem[4 * item + 3];
@@ -189,7 +192,7 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
   bool colok[H];
 #pragma unroll
   for (int h = 0; h < H; h++) {
-    col[h] = ct * form_box_cols(NT) + w * (16 * H) + 16 * h + lr;
+    col[h] = ct * form_box_cols_of(H) + w * (16 * H) + 16 * h + lr;
     colok[h] = col[h] < N2;
   }
   acc_t acc[NT][H];
@@ -1003,14 +1006,14 @@ __global__ __launch_bounds__(256) void form_box(const elem_t<C>* __restrict__ Y,
                                                 int p, int nr, int ncoltiles, elem_t<C>* __restrict__ phi,
                                                 elem_t<C>* __restrict__ partial) {
   typedef elem_t<C> T;
-  form_box_body<C, D, NT, KS>(Y, fitem, leaf_tab, F, p, nr, ncoltiles, phi, partial, blockIdx.x);
+  form_box_body<C, D, NT, KS, kFormBoxSlabs>(Y, fitem, leaf_tab, F, p, nr, ncoltiles, phi, partial, blockIdx.x);
 }
-template <typename C, int D, int NT, int KS>
+template <typename C, int D, int NT, int KS, int H>
 __global__ __launch_bounds__(256) void form_box_b(FGT_BATCH_PARAMS) {
   typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  const int ncol128 = (n2_of(D, a.nr) + form_box_cols(NT) - 1) / form_box_cols(NT);
-  form_box_body<C, D, NT, KS>(cptr<T>(a.Y), a.fitem, D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
+  const int ncol128 = (n2_of(D, a.nr) + form_box_cols_of(H) - 1) / form_box_cols_of(H);
+  form_box_body<C, D, NT, KS, H>(cptr<T>(a.Y), a.fitem, D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
                               ncol128,
                               mptr<T>(a.phi), mptr<T>(a.partial), bid);
 }
@@ -1168,6 +1171,13 @@ KernelClass kernel_class(const DeviceArgs& a) {
   return c;
 }
 
+int64_t form_box_blocks(const DeviceArgs& a, int slabs) {
+  if (a.nL <= 0) return 0;
+  if (a.d != 3) return a.nFI;
+  const int64_t N2 = (int64_t)a.nr * a.nr, cols = form_box_cols_of(slabs);
+  return a.nFI * ((N2 + cols - 1) / cols);
+}
+
 int64_t stage_blocks(const DeviceArgs& a, int stage) {
   const int64_t nr = a.nr;
   const int64_t N2 = a.d == 3 ? nr * nr : nr;
@@ -1178,12 +1188,7 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
       const int nt = kernel_class(a).nt, tg = form3_tile_group(nt);
       return a.nPl * ((a.p * ((nt + tg - 1) / tg) + 3) / 4);
     }
-    case kFormBox: {
-      if (!pw) return 0;
-      if (a.d != 3) return a.nFI;
-      const int cols = form_box_cols(kernel_class(a).nt);
-      return a.nFI * ((N2 + cols - 1) / cols);
-    }
+    case kFormBox: return form_box_blocks(a, kFormBoxSlabs);
     case kReduce: return pw && a.nFR > 0 ? a.nFR * ((N2 * nr + 255) / 256) : 0;
     case kTranslate: return pw ? (a.d == 3 && a.fuse_te ? transeval3_blocks(a) : translate_blocks(a)) : 0;
     // d = 3: a separate stage unless fused into the translation; d = 2: fused into eval2_leaf
@@ -1196,13 +1201,18 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
 
 template <typename C, int NT, int KS>
 static void launch_batched_nt(int d, bool fuse, int stage, const BatchJob* jobs, const int32_t* start,
-                              const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+                              const int32_t* count, int njobs, int64_t grid, hipStream_t st, int tile) {
   typedef elem_t<C> T;
   const dim3 g((unsigned)grid), b(256);
   if (d == 3) {
     switch (stage) {
       case kFormLeaf: hipLaunchKernelGGL((form3_plane_b<C, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
-      case kFormBox: hipLaunchKernelGGL((form_box_b<C, 3, NT, KS>), g, b, 0, st, jobs, start, count, njobs); break;
+      case kFormBox:
+        if (tile == 1)
+          hipLaunchKernelGGL((form_box_b<C, 3, NT, KS, kFormBoxSlabsAlt>), g, b, 0, st, jobs, start, count, njobs);
+        else
+          hipLaunchKernelGGL((form_box_b<C, 3, NT, KS, kFormBoxSlabs>), g, b, 0, st, jobs, start, count, njobs);
+        break;
       case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
       case kTranslate:
         if (fuse)
@@ -1228,33 +1238,33 @@ static void launch_batched_nt(int d, bool fuse, int stage, const BatchJob* jobs,
 
 template <typename C, int KS>
 static void launch_batched_ks(const KernelClass& c, int stage, const BatchJob* jobs, const int32_t* start,
-                              const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+                              const int32_t* count, int njobs, int64_t grid, hipStream_t st, int tile) {
   typedef elem_t<C> T;
   switch (c.nt) {
-    case 1: launch_batched_nt<C, 1, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
-    case 2: launch_batched_nt<C, 2, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
-    case 3: launch_batched_nt<C, 3, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
-    case 4: launch_batched_nt<C, 4, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
-    case 5: launch_batched_nt<C, 5, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
-    case 6: launch_batched_nt<C, 6, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
-    case 7: launch_batched_nt<C, 7, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
-    default: launch_batched_nt<C, 8, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st); break;
+    case 1: launch_batched_nt<C, 1, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st, tile); break;
+    case 2: launch_batched_nt<C, 2, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st, tile); break;
+    case 3: launch_batched_nt<C, 3, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st, tile); break;
+    case 4: launch_batched_nt<C, 4, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st, tile); break;
+    case 5: launch_batched_nt<C, 5, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st, tile); break;
+    case 6: launch_batched_nt<C, 6, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st, tile); break;
+    case 7: launch_batched_nt<C, 7, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st, tile); break;
+    default: launch_batched_nt<C, 8, KS>(c.d, c.fuse_te, stage, jobs, start, count, njobs, grid, st, tile); break;
   }
 }
 
 hipError_t launch_stage_batched(const KernelClass& c, int stage, const BatchJob* jobs, const int32_t* start,
-                                const int32_t* count, int njobs, int64_t grid, hipStream_t st) {
+                                const int32_t* count, int njobs, int64_t grid, hipStream_t st, int tile) {
   if (grid <= 0 || njobs <= 0) return hipSuccess;
   if (c.d != 2 && c.d != 3) return hipErrorInvalidValue;
   if (c.bf3) {
-    if (c.ks == 2) launch_batched_ks<Bf16x3, 2>(c, stage, jobs, start, count, njobs, grid, st);
-    else launch_batched_ks<Bf16x3, 4>(c, stage, jobs, start, count, njobs, grid, st);
+    if (c.ks == 2) launch_batched_ks<Bf16x3, 2>(c, stage, jobs, start, count, njobs, grid, st, tile);
+    else launch_batched_ks<Bf16x3, 4>(c, stage, jobs, start, count, njobs, grid, st, tile);
   } else if (c.fp32) {
-    if (c.ks == 2) launch_batched_ks<float, 2>(c, stage, jobs, start, count, njobs, grid, st);
-    else launch_batched_ks<float, 4>(c, stage, jobs, start, count, njobs, grid, st);
+    if (c.ks == 2) launch_batched_ks<float, 2>(c, stage, jobs, start, count, njobs, grid, st, tile);
+    else launch_batched_ks<float, 4>(c, stage, jobs, start, count, njobs, grid, st, tile);
   } else {
-    if (c.ks == 2) launch_batched_ks<double, 2>(c, stage, jobs, start, count, njobs, grid, st);
-    else launch_batched_ks<double, 4>(c, stage, jobs, start, count, njobs, grid, st);
+    if (c.ks == 2) launch_batched_ks<double, 2>(c, stage, jobs, start, count, njobs, grid, st, tile);
+    else launch_batched_ks<double, 4>(c, stage, jobs, start, count, njobs, grid, st, tile);
   }
   return hipGetLastError();
 }
@@ -1287,7 +1297,8 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
   rec(0);
   if (a.nL > 0) {
     if (D == 3) {
-      const int N2 = nr * nr, ncol = (N2 + 63) / 64, ncol128 = (N2 + form_box_cols(NT) - 1) / form_box_cols(NT);
+      const int N2 = nr * nr, ncol = (N2 + 63) / 64;
+      const int ncol128 = (N2 + form_box_cols_of(kFormBoxSlabs) - 1) / form_box_cols_of(kFormBoxSlabs);
       hipLaunchKernelGGL((form3_plane<C, NT, KS>), dim3((unsigned)stage_blocks(a, kFormLeaf)), dim3(256), 0, st, sigma,
                          a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, F, p, nr, Y);
       rec(1);

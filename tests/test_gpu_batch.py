@@ -127,6 +127,34 @@ def test_batch_matches_oracle():
     b.close()
 
 
+def test_batch_alternative_tile_equals_alone():
+    """Every d = 3 class on the alternative box-formation tile (two slabs per
+    wave): the same columns and sums, so results stay bitwise equal."""
+    dens = synth.GaussianSum(np.array([[0.1, -0.12, 0.05], [-0.3, 0.2, 0.1]]),
+                             np.array([0.02, 0.05]), np.array([1.0, -0.6]))
+    lv, cs = synth.resolve_tree(dens, 3, 6, 1e-8, max_level=5)
+    probs = [synth.RequestType(200, 3, 6, 1e-3, 1e-6, "fp64", lv, cs, synth.sample(lv, cs, 6, dens)),
+             synth.RequestType(201, 3, 6, 1e-3, 1e-3, "fp32", lv, cs, synth.sample(lv, cs, 6, dens))]
+    probs += [t for t in _problems() if t.d == 3][:4] + [_problems()[-1]]
+    plans = _plans(probs)
+    assert plans[0].info()["n_pwleaf"] > 0
+    sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
+    ref = _alone(plans, sig)
+    b = api.Batch(plans, form_tile=1)
+    us = [torch.full_like(s, float("nan")) for s in sig]
+    b.bind(sig, us)
+    info = b.info()
+    _say(f"alternative tile: {info}")
+    assert info["tile_alt_classes"] > 0
+    b.execute()
+    torch.cuda.synchronize()
+    for u, r in zip(us, ref):
+        assert torch.equal(u, r)
+    b.close()
+    with pytest.raises(api.FgtError):
+        api.Batch(plans, form_tile=2)
+
+
 def test_batch_rejects_host_only_plans():
     t = _problems()[0]
     hp = api.Plan(t.levels, t.coords, t.p, t.delta, t.tol, host_only=True)
