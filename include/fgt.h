@@ -168,10 +168,12 @@ int fgt_periodic_terms(double eps, double delta);
 /*
  * Copies a host-side array of a plan (host-only or full) for inspection:
  * name is one of "F", "E", "V", "rot" (double) or "pwbox_isleaf", "pw_start",
- * "pwleaf_id", "pwleaf_tab", "plist_start", "plist_src", "plist_dir",
- * "echunk", "near_tgt", "near_haspw", "near_start", "near_src", "near_tab",
- * "ftab_meta", "vtab_meta" (int32).  Writes at most cap elements to dst
- * (may be NULL to query) and returns the array's length, or a negative code.
+ * "pwleaf_id", "pwleaf_tab", "pwleaf_box", "box_order", "plist_start",
+ * "plist_src", "plist_dir", "echunk", "fitem", "fred", "near_tgt",
+ * "near_haspw", "near_start", "near_src", "near_tab", "ftab_meta", "vtab_meta",
+ * "plane_start", "plane_tab", "plane_row", "row_start", "row_tab" (int32).
+ * Writes at most cap elements to dst (may be NULL to query) and returns the
+ * array's length, or a negative code.
  */
 int64_t fgt_plan_array(const fgt_plan_t* plan, const char* name, void* dst, int64_t cap);
 
