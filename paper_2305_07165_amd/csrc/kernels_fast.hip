@@ -37,9 +37,17 @@ __device__ __forceinline__ int wave_of() { return threadIdx.x >> 6; }
 // (NT x TG tiles) stay small, fewer for large NT.
 __host__ __device__ constexpr int form3_tile_group(int nt) { return nt <= 4 ? nt : (nt == 5 ? 3 : 2); }
 
+// k-steps of a node contraction (K = p <= 4 KS): chained operands need the
+// register layout, which for FP32 and BF16x3 spreads K over all four steps;
+// when both operands come from memory (MemSteps, k = Mfma::kmem) FP32 needs
+// only KS.  BF16x3 products always span four steps.
 template <typename C, int KS>
 struct Steps {
   static constexpr int value = std::is_same<C, double>::value ? KS : 4;
+};
+template <typename C, int KS>
+struct MemSteps {
+  static constexpr int value = std::is_same<C, Bf16x3>::value ? 4 : KS;
 };
 
 // ---------------------------------------------------------------------------
@@ -64,7 +72,8 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
   typedef elem_t<C> T;
   typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<C, KS>::value;
+  constexpr int S = Steps<C, KS>::value;      // chained (X^T as the B operand of Y)
+  constexpr int SM = MemSteps<C, KS>::value;  // sigma x F2, both from memory
   constexpr int TG = form3_tile_group(NT), NG = (NT + TG - 1) / TG;
   const int nitem = p * NG, nsplit = (nitem + 3) / 4;
   const int P = bid / nsplit;
@@ -77,14 +86,14 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
   const int s_begin = row_start[rw0], s_end = row_start[rw1];
   const int64_t ppp = (int64_t)p * p * p;
   // operands of leaf s; masked loads (no branches)
-  auto load = [&](int s, T (&av)[S], T (&b2)[TG][S]) {
+  auto load = [&](int s, T (&av)[SM], T (&b2)[TG][SM]) {
     const bool ls = s < s_end;
     const int sc = ls ? s : s_begin;
     const double* sg = sigma + (int64_t)leaf_id[sc] * ppp;
     const T* F2 = F + (int64_t)leaf_tab[sc * 3 + 1] * nr * p;
 #pragma unroll
-    for (int kk = 0; kk < S; kk++) {
-      const int k = M::kidx(kk, lk);
+    for (int kk = 0; kk < SM; kk++) {
+      const int k = M::kmem(kk, lk);
       av[kk] = ld0<T>(sg, (j3 * p + k) * p + lr, ls && lr < p && k < p);  // A[j1][j2]
 #pragma unroll
       for (int g = 0; g < TG; g++) {
@@ -101,16 +110,16 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
   acc_t x[TG];
 #pragma unroll
   for (int g = 0; g < TG; g++) zero4(x[g]);
-  T av[S], b2[TG][S];
+  T av[SM], b2[TG][SM];
   load(s_begin, av, b2);
   int rw = rw0;
   int row_end = row_start[rw0 + 1];
   for (int s = s_begin; s < s_end; s++) {
-    T avn[S], b2n[TG][S];
+    T avn[SM], b2n[TG][SM];
     load(s + 1, avn, b2n);
 #pragma unroll
     for (int g = 0; g < TG; g++)
-      x[g] = M::template steps<S>(av, b2[g], x[g]);
+      x[g] = M::template steps<SM>(av, b2[g], x[g]);
     if (s + 1 == row_end) {
       const T* F1 = F + (int64_t)row_tab[rw] * nr * p;
 #pragma unroll
@@ -135,7 +144,7 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
       if (rw < rw1) row_end = row_start[rw + 1];
     }
 #pragma unroll
-    for (int kk = 0; kk < S; kk++) {
+    for (int kk = 0; kk < SM; kk++) {
       av[kk] = avn[kk];
 #pragma unroll
       for (int g = 0; g < TG; g++) b2[g][kk] = b2n[g][kk];
@@ -181,7 +190,7 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
   // workgroup; every wave owns H 16-column slabs, sharing the table operand
   typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<C, KS>::value;
+  constexpr int S = MemSteps<C, KS>::value;  // Y and F3 both come from memory
   const int item = bid / ncoltiles;
   const int ct = bid % ncoltiles;
   const int A = fitem[4 * item], slot = fitem[4 * item + 3];
@@ -210,7 +219,7 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
     const T* Ys = Y + (int64_t)sc * p * N2;
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
-      const int k = M::kidx(kk, lk);
+      const int k = M::kmem(kk, lk);
 #pragma unroll
       for (int h = 0; h < H; h++) bb[kk][h] = ld0<T>(Ys, (int64_t)k * N2 + col[h], ls && k < p && colok[h]);
 #pragma unroll
@@ -641,7 +650,8 @@ __device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
   typedef elem_t<C> T;
   typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<C, KS>::value;
+  constexpr int S = Steps<C, KS>::value;      // level B: the chained T^T as B operand
+  constexpr int SM = MemSteps<C, KS>::value;  // levels A and C: operands from memory / LDS
   constexpr int RS = 17;            // padded i2 stride of the LDS tile
   constexpr int US = 16 * RS + 4;   // padded j3 stride
   __shared__ T Us[16 * US];         // U[j3][i2][i1]
@@ -663,25 +673,25 @@ __device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
     const int t1 = near_tab[q * 3 + 0], t2 = near_tab[q * 3 + 1], t3 = near_tab[q * 3 + 2];
     const double* sg = sigma + (int64_t)near_src[q] * pp * p;
     const T* V2 = V + (int64_t)t2 * pp;
-    T b2[S];
+    T b2[SM];
 #pragma unroll
-    for (int kk = 0; kk < S; kk++) {
-      const int k = M::kidx(kk, lk);
+    for (int kk = 0; kk < SM; kk++) {
+      const int k = M::kmem(kk, lk);
       b2[kk] = ld0<T>(V2, lr * p + k, lr < p && k < p);  // B[j2][i2] = V2[i2][j2]
     }
-    T av[KS][S];
+    T av[KS][SM];
 #pragma unroll
     for (int c = 0; c < KS; c++) {
       const int j3 = w + 4 * c;
 #pragma unroll
-      for (int kk = 0; kk < S; kk++) {
-        const int k = M::kidx(kk, lk);
+      for (int kk = 0; kk < SM; kk++) {
+        const int k = M::kmem(kk, lk);
         av[c][kk] = ld0<T>(sg, (j3 * p + k) * p + lr, j3 < p && lr < p && k < p);  // A[j1][j2]
       }
     }
 #pragma unroll
     for (int c = 0; c < KS; c++)
-      tacc[c] = M::template steps<S>(av[c], b2, tacc[c]);
+      tacc[c] = M::template steps<SM>(av[c], b2, tacc[c]);
     const bool last = q + 1 == q1;
     const bool end1 = last || near_tab[q * 3 + 5] != t3 || near_tab[q * 3 + 3] != t1;
     const bool end3 = last || near_tab[q * 3 + 5] != t3;
@@ -717,23 +727,23 @@ __device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
       }
       __syncthreads();
       const T* V3 = V + (int64_t)t3 * pp;
-      T a3[S];
+      T a3[SM];
 #pragma unroll
-      for (int kk = 0; kk < S; kk++) {
-        const int k = M::kidx(kk, lk);
+      for (int kk = 0; kk < SM; kk++) {
+        const int k = M::kmem(kk, lk);
         a3[kk] = ld0<T>(V3, lr * p + k, lr < p && k < p);  // A[i3][j3]
       }
 #pragma unroll
       for (int c = 0; c < KS; c++) {
         const int i2 = w + 4 * c;  // column tile (i2, i1 = lr); rows i2 >= p are never stored
-        T bq[S];
+        T bq[SM];
 #pragma unroll
-        for (int kk = 0; kk < S; kk++) {
-          const int j3 = M::kidx(kk, lk);
+        for (int kk = 0; kk < SM; kk++) {
+          const int j3 = M::kmem(kk, lk);
           const T uv = Us[j3 < p && i2 < p ? j3 * US + i2 * RS + lr : 0];  // LDS: select, no branch
           bq[kk] = j3 < p ? uv : (T)0;
         }
-        oacc[c] = M::template steps<S>(a3, bq, oacc[c]);
+        oacc[c] = M::template steps<SM>(a3, bq, oacc[c]);
       }
     }
   }

@@ -26,6 +26,9 @@ template <> struct Mfma<double> {
   }
   static __device__ __forceinline__ int row(int lk, int t) { return 4 * t + lk; }
   static __device__ __forceinline__ int kidx(int kk, int lk) { return 4 * kk + lk; }
+  // K index of step kk when neither operand is a chained result (both come
+  // from memory or LDS): k = 4kk + lk, so ceil(K/4) steps cover K
+  static __device__ __forceinline__ int kmem(int kk, int lk) { return 4 * kk + lk; }
   // N consecutive k-steps
   template <int N>
   static __device__ __forceinline__ acc steps(const double (&a)[N], const double (&b)[N], acc c) {
@@ -42,6 +45,8 @@ template <> struct Mfma<float> {
   }
   static __device__ __forceinline__ int row(int lk, int t) { return 4 * lk + t; }
   static __device__ __forceinline__ int kidx(int kk, int lk) { return 4 * lk + kk; }
+  // as for FP64: with both operands from memory, K = 8 takes two steps, not four
+  static __device__ __forceinline__ int kmem(int kk, int lk) { return 4 * kk + lk; }
   template <int N>
   static __device__ __forceinline__ acc steps(const float (&a)[N], const float (&b)[N], acc c) {
 #pragma unroll
@@ -69,6 +74,8 @@ template <> struct Mfma<Bf16x3> {
   typedef f4 acc;
   static __device__ __forceinline__ int row(int lk, int t) { return 4 * lk + t; }
   static __device__ __forceinline__ int kidx(int kk, int lk) { return 4 * lk + kk; }
+  // one bf16 product spans K = 16: memory operands keep the same layout
+  static __device__ __forceinline__ int kmem(int kk, int lk) { return 4 * lk + kk; }
   template <int N>
   static __device__ __forceinline__ acc steps(const float (&a)[N], const float (&b)[N], acc c) {
     static_assert(N == 4, "BF16x3 products run four k-steps at a time");
