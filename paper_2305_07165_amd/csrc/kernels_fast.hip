@@ -784,7 +784,8 @@ __device__ __forceinline__ void form2_box_body(const double* __restrict__ sigma,
   typedef elem_t<C> T;
   typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<C, KS>::value;
+  constexpr int S = Steps<C, KS>::value;      // F2 x X (X chained as the B operand)
+  constexpr int SM = MemSteps<C, KS>::value;  // sigma x F1, both from memory
   constexpr int TW = (NT + 3) / 4;  // r1 tiles per wave
   const int item = bid;
   const int A = fitem[4 * item], slot = fitem[4 * item + 3];
@@ -800,11 +801,15 @@ __device__ __forceinline__ void form2_box_body(const double* __restrict__ sigma,
     const T* F1 = F + (int64_t)leaf_tab[s * 2 + 0] * nr * p;
     const T* F2 = F + (int64_t)leaf_tab[s * 2 + 1] * nr * p;
     const double* sg = sigma + (int64_t)leaf_id[s] * p * p;
-    T av[S], a2[NT][S];
+    T av[SM], a2[NT][S];
+#pragma unroll
+    for (int kk = 0; kk < SM; kk++) {
+      const int k = M::kmem(kk, lk);
+      av[kk] = ld0<T>(sg, lr * p + k, lr < p && k < p);
+    }
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
       const int k = M::kidx(kk, lk);
-      av[kk] = ld0<T>(sg, lr * p + k, lr < p && k < p);
 #pragma unroll
       for (int ti = 0; ti < NT; ti++) {
         const int r = 16 * ti + lr;
@@ -818,13 +823,13 @@ __device__ __forceinline__ void form2_box_body(const double* __restrict__ sigma,
         // X[j2][r1] = sum_j1 sigma[j2][j1] F1[r1][j1]
         acc_t x;
         zero4(x);
-        T bq[S];
+        T bq[SM];
 #pragma unroll
-        for (int kk = 0; kk < S; kk++) {
-          const int k = M::kidx(kk, lk), r = 16 * tj + lr;
+        for (int kk = 0; kk < SM; kk++) {
+          const int k = M::kmem(kk, lk), r = 16 * tj + lr;
           bq[kk] = ld0<T>(F1, r * p + k, r < nr && k < p);
         }
-        x = M::template steps<S>(av, bq, x);
+        x = M::template steps<SM>(av, bq, x);
         // phi[r2][r1] += sum_j2 F2[r2][j2] X[j2][r1]
         T xb[S];
 #pragma unroll
@@ -930,7 +935,8 @@ __device__ __forceinline__ void near2_body(const double* __restrict__ sigma,
   typedef elem_t<C> T;
   typedef Mfma<C> M;
   typedef typename M::acc acc_t;
-  constexpr int S = Steps<C, KS>::value;
+  constexpr int S = Steps<C, KS>::value;      // V2 x T (T chained as the B operand)
+  constexpr int SM = MemSteps<C, KS>::value;  // sigma x V1, both from memory
   const int lane = lane_of(), w = wave_of();
   const int t = bid * 4 + w;
   if (t >= ntgt) return;
@@ -945,14 +951,14 @@ __device__ __forceinline__ void near2_body(const double* __restrict__ sigma,
     const double* sg = sigma + (int64_t)near_src[q] * pp;
     const T* V1 = V + (int64_t)t1 * pp;
     {
-      T aq[S], bq[S];
+      T aq[SM], bq[SM];
 #pragma unroll
-      for (int kk = 0; kk < S; kk++) {
-        const int k = M::kidx(kk, lk);
+      for (int kk = 0; kk < SM; kk++) {
+        const int k = M::kmem(kk, lk);
         aq[kk] = ld0<T>(sg, lr * p + k, lr < p && k < p);
         bq[kk] = ld0<T>(V1, lr * p + k, lr < p && k < p);
       }
-      tacc = M::template steps<S>(aq, bq, tacc);  // T[j2][i1]
+      tacc = M::template steps<SM>(aq, bq, tacc);  // T[j2][i1]
     }
     if (q + 1 == q1 || near_tab[q * 2 + 3] != t2) {
       const T* V2 = V + (int64_t)t2 * pp;
