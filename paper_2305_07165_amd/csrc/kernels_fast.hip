@@ -287,8 +287,7 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 // phi_B[r3][tile] into LDS (a thread owns the 2 x 2 x 2 coefficients of one
 // (m3, m2) unit, as in the plain translation); phase 2 contracts it with the
 // axis-3 evaluation table of every plane of A, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
-// psi_A[r3][c], 16-column groups spread over the waves.  psi never goes to HBM.  Boxes
-// are XCD-contiguous ranges walked tile by tile, as in the plain translation.
+// psi_A[r3][c], 16-column groups spread over the waves.  psi never goes to HBM.
 
 // axis-2 modes per tile: all of them (whole contiguous r2 rows) while the tile
 // stays within 96 columns; else at most 16 with M * modes <= 256
@@ -321,10 +320,23 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
   const int LDW = transeval_ldw(nr);
   const int nb2 = (M + TM - 1) / TM;
   const int ntile = M * nb2;
+  // XCD x first sweeps every box (Morton order) for tiles x, x + 8, ... of the
+  // full rounds, so each such phi slice is fetched into one L2 only; the
+  // remaining ntile % 8 tiles are split into 8 contiguous box ranges, one per
+  // XCD, which keeps the work of the XCDs equal
   const int nbx = (nA + kXcds - 1) / kXcds;
+  const int rounds = ntile / kXcds;
   const int xcd = bid % kXcds, local = bid / kXcds;
-  const int A = xcd * nbx + local % nbx;
-  const int tile = local / nbx;
+  int A, tile;
+  if (local < rounds * nA) {
+    const int r = local / nA;
+    A = local - r * nA;
+    tile = kXcds * r + xcd;
+  } else {
+    const int j = local - rounds * nA;
+    A = xcd * nbx + j % nbx;
+    tile = kXcds * rounds + j / nbx;
+  }
   if (A >= nA || tile >= ntile) return;  // whole workgroup
   const int m1 = tile / nb2, b2 = tile - m1 * nb2;
   const int mlo = b2 * TM, mhi = min(M, mlo + TM), nm2 = mhi - mlo;
@@ -454,9 +466,10 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
 
 int64_t transeval3_blocks(const DeviceArgs& a) {
   const int tm = transeval_modes(a.M);
-  const int64_t nb2 = (a.M + tm - 1) / tm;
+  const int64_t nb2 = (a.M + tm - 1) / tm, ntile = a.M * nb2;
   const int64_t nbx = (a.nA + kXcds - 1) / kXcds;
-  return kXcds * nbx * a.M * nb2;
+  const int64_t rounds = ntile / kXcds, rem = ntile - rounds * kXcds;
+  return kXcds * (rounds * a.nA + rem * nbx);
 }
 
 // ---------------------------------------------------------------------------
