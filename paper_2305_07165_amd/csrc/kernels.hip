@@ -202,16 +202,29 @@ __device__ __forceinline__ void translate_body(const T* __restrict__ phi,
                                                const int32_t* __restrict__ plist_dir,
                                                const T* __restrict__ rot, int M, int nr, int nA,
                                                T* __restrict__ psi, int bid) {
-  // Every XCD owns a contiguous (Morton) range of nbx target boxes and walks
-  // it chunk of modes by chunk of modes, so a source's slice is fetched into
-  // that XCD's L2 once and reused by all its neighbors in the range.
-  const int nbx = (nA + kXcds - 1) / kXcds;
-  const int xcd = bid % kXcds, local = bid / kXcds;
-  const int A = xcd * nbx + local % nbx;
-  const int b = (local / nbx) * blockDim.x + threadIdx.x;
+  // Chunks of modes are dealt to the XCDs: XCD x sweeps every target box (in
+  // Morton order) for chunks x, x + 8, ..., so each source slice of those
+  // chunks is fetched into one L2 and reused by all its targets there; the
+  // nchunk % 8 leftover chunks are split into eight contiguous box ranges, one
+  // per XCD, so the XCDs get equal work.
   int nblk = 1;
   for (int a = 0; a < D; a++) nblk *= M;
-  if (A >= nA || b >= nblk) return;
+  const int nch = (nblk + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int nbx = (nA + kXcds - 1) / kXcds;
+  const int rounds = nch / kXcds;
+  const int xcd = bid % kXcds, local = bid / kXcds;
+  int A, chunk;
+  if (local < rounds * nA) {
+    const int r = local / nA;
+    A = local - r * nA;
+    chunk = kXcds * r + xcd;
+  } else {
+    const int j = local - rounds * nA;
+    A = xcd * nbx + j % nbx;
+    chunk = kXcds * rounds + j / nbx;
+  }
+  const int b = chunk * (int)blockDim.x + (int)threadIdx.x;
+  if (A >= nA || chunk >= nch || b >= nblk) return;
   int m[3] = {0, 0, 0};
   {
     int q = b;
@@ -316,7 +329,7 @@ __global__ __launch_bounds__(256) void k_translate(const T* __restrict__ phi,
 
 // The same stage for many transforms in one launch.  Every transform's block
 // range starts at a multiple of 8, so block b of a transform still runs on XCD
-// b % 8 and the XCD-contiguous box ranges above are kept.
+// b % 8 and the deal of chunks and box ranges above is kept.
 template <typename T, int D, bool R2F>
 __global__ __launch_bounds__(256) void k_translate_batched(const BatchJob* __restrict__ jobs,
                                                            const int32_t* __restrict__ start,
@@ -349,8 +362,9 @@ template void launch_translate_batched<float>(int, const BatchJob*, const int32_
 int64_t translate_blocks(const DeviceArgs& a) {
   int64_t nblk = 1;
   for (int i = 0; i < a.d; i++) nblk *= a.M;
-  const int64_t nbx = (a.nA + kXcds - 1) / kXcds;
-  return kXcds * nbx * ((nblk + 255) / 256);
+  const int64_t nch = (nblk + 255) / 256, nbx = (a.nA + kXcds - 1) / kXcds;
+  const int64_t rounds = nch / kXcds, rem = nch - rounds * kXcds;
+  return kXcds * (rounds * a.nA + rem * nbx);
 }
 
 // ---------------------------------------------------------------------------
