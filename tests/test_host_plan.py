@@ -58,6 +58,29 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(_lib.EXPORTED)
 
 
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library the transform raises; there is no fallback."""
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(HERE, "no_such_dir", "libfgt.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    lv, cs = synth.uniform_tree(2, 1)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        api.Plan(lv, cs, 4, 1e-2, 1e-6, host_only=True)
+
+
+def test_product_package_does_not_use_the_oracle():
+    """The oracle is test infrastructure: nothing in the package imports,
+    loads or links it."""
+    pkg = os.path.join(ROOT, "paper_2305_07165_amd")
+    pat = re.compile(r"^\s*(import\s+oracle|from\s+oracle)|oracle\.c|liboracle|oracle/", re.M)
+    hits = []
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                if pat.search(open(os.path.join(dirpath, f), errors="replace").read()):
+                    hits.append(f)
+    assert not hits, hits
+
+
 # ---------------------------------------------------------------------------
 # Theorem 1 and Tables 1-2
 
