@@ -68,7 +68,13 @@ void drop_graph(fgt_batch* b) {
   b->exec = nullptr;
 }
 
+// Keeps exactly nstreams - 1 side streams (the tuner changes nstreams).
 int ensure_side_streams(fgt_batch* b) {
+  while ((int)b->side.size() > b->nstreams - 1) {
+    (void)hipStreamSynchronize(b->side.back());
+    (void)hipStreamDestroy(b->side.back());
+    b->side.pop_back();
+  }
   while ((int)b->side.size() < b->nstreams - 1) {
     hipStream_t s = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
@@ -105,10 +111,13 @@ int enqueue(fgt_batch* b, hipStream_t st) {
   const std::vector<std::vector<int>> per = assign(b);
   hipError_t e;
   int launches = 0;
+  // fork exactly the nstreams - 1 side streams that are joined below: under
+  // capture, a stream that waits on the fork event joins the capture
   if (b->nstreams > 1) {
     if ((e = hipEventRecord(b->ev[0], st)) != hipSuccess) return herr(e, "hipEventRecord");
-    for (hipStream_t s : b->side)
-      if ((e = hipStreamWaitEvent(s, b->ev[0], 0)) != hipSuccess) return herr(e, "hipStreamWaitEvent");
+    for (int si = 1; si < b->nstreams; si++)
+      if ((e = hipStreamWaitEvent(b->side[si - 1], b->ev[0], 0)) != hipSuccess)
+        return herr(e, "hipStreamWaitEvent");
   }
   for (int si = 0; si < b->nstreams; si++) {
     hipStream_t s = si == 0 ? st : b->side[si - 1];
