@@ -109,6 +109,32 @@ def test_batch_rebind_and_tune():
     b.close()
 
 
+def test_batch_graph_replays_after_repeated_tuning():
+    """Tuning leaves any of 1, 2 or 4 streams (a fork/join in the graph); the
+    replays after each tuning, with eager work between them, stay exact."""
+    probs = _problems()
+    plans = _plans(probs)
+    sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
+    ref = _alone(plans, sig)
+    b = api.Batch(plans, nstreams=4)
+    us = [torch.full_like(s, float("nan")) for s in sig]
+    b.bind(sig, us)
+    picked = []
+    for rnd in range(3):
+        b.tune(reps=1)
+        picked.append(b.info()["nstreams"])
+        for rep in range(2):
+            b.execute()
+            torch.cuda.synchronize()
+            for i, (u, r) in enumerate(zip(us, ref)):
+                assert torch.equal(u, r), f"tuning {rnd} replay {rep} job {i} differs from its result alone"
+            for u in us:
+                u.fill_(float("nan"))
+            torch.cuda.synchronize()
+    _say(f"streams picked by three tunings: {picked}")
+    b.close()
+
+
 def test_batch_matches_oracle():
     probs = [t for t in _problems() if t.d == 2 and t.npoints <= 40_000][:2]
     assert probs
