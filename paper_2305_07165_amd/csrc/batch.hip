@@ -68,13 +68,9 @@ void drop_graph(fgt_batch* b) {
   b->exec = nullptr;
 }
 
-// Keeps exactly nstreams - 1 side streams (the tuner changes nstreams).
+// Creates side streams up to nstreams - 1; streams beyond that (left by a
+// tuning run) stay idle until the batch is released.
 int ensure_side_streams(fgt_batch* b) {
-  while ((int)b->side.size() > b->nstreams - 1) {
-    (void)hipStreamSynchronize(b->side.back());
-    (void)hipStreamDestroy(b->side.back());
-    b->side.pop_back();
-  }
   while ((int)b->side.size() < b->nstreams - 1) {
     hipStream_t s = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
