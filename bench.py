@@ -1,20 +1,21 @@
 """Benchmark of the MI355X machine fast Gauss transform.
 
-Workload (one "step" = one fgt_execute, every stage of Algorithm 4 over the
-whole tree): the 3D adaptive free-space transform with p = 16 Gauss-Legendre
-nodes per axis, delta = 1e-4, sigma a sum of 8 Gaussians (widths log-uniform in
-[1e-3, 1e-2], centers U[-0.4,0.4]^3, amplitudes U(-1,1), seed 0) resolved by
-the Legendre-tail test to 1e-9 ||sigma||_2 and 2:1 balanced: 2,661 leaves,
-N = 10,899,456 grid points.  The headline value is FP64 at tol = 1e-6; the
-same tree at tol = 1e-10 (FP64) and at tol = 1e-6 with FP32 contractions are
-reported beside it.  Inputs are resident in HBM before the timed region.
+Headline workload (one "step" = one fgt_execute, every stage of Algorithm 4
+over the whole tree): the 3D adaptive free-space transform with p = 16
+Gauss-Legendre nodes per axis, delta = 1e-4, sigma a sum of 8 Gaussians
+(widths log-uniform in [1e-3, 1e-2], centers U[-0.4,0.4]^3, amplitudes
+U(-1,1), seed 0) resolved by the Legendre-tail test to 1e-9 ||sigma||_2 and
+2:1 balanced: 2,661 leaves, N = 10,899,456 grid points, FP64 at tol = 1e-6.
+Inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line.  Also reported:
-  roofline      the dominant kernel's algorithmic flops (or bytes) per launch
-                over its mean HIP-event duration, against the MI355X peak;
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of target leaves;
-  accuracy      relative l2 error of the GPU result against the oracle on
-                that sample.
+The parent process never touches the GPU.  It runs every measurement in a
+child process of its own (the headline first, then the small 2D workload,
+the other tolerances and precisions, the periodic variant, the precision
+form, the batched and the served forms), merges the children's JSON, records
+the exit status of a child that fails (never retried), then runs the CPU
+leg: the FP64 oracle over every leaf of each tree a child returned u for
+(accuracy of every form, whole tree), timed on the headline tree as
+cpu_baseline.  It prints ONE JSON line.
 """
 
 from __future__ import annotations
@@ -24,7 +25,10 @@ import hashlib
 import json
 import math
 import os
+import shutil
+import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -34,6 +38,8 @@ PEAK_FP64 = 78.6e12   # dense FP64 matrix and vector, FLOP/s
 PEAK_FP32 = 157.3e12  # dense FP32, FLOP/s
 PEAK_HBM = 8.0e12     # bytes/s
 STAGES = ("form_leaf", "form_box", "translate", "eval_box", "eval_leaf", "near")
+CHILDREN = ("headline", "config0", "forms", "periodic", "precision", "batched", "served")
+METRIC = "grid points/s at tol=1e-6 (3D adaptive), FP64 vs mixed; p50/p99 latency"
 
 
 def near_runs(plan) -> tuple:
@@ -153,68 +159,255 @@ def pct(sorted_ms, q):
     return sorted_ms[i]
 
 
-def precision_form(pr, steps, warmup, log, ntarget=96):
-    """The 3D tree of the headline workload at delta in {1e-3, 1e-5}: FP32 and
-    BF16x3 products at tol 1e-3 and 1e-6, each timed and compared with the FP64
-    oracle on a sample of target leaves; speedups are over the FP64 path at
-    tol 1e-6 on the same delta."""
-    import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# children: each runs one measurement on the GPU and returns a dict; arrays of
+# u it wants checked against the oracle are saved under the run's scratch
+# directory and listed in "arrays"
+
+
+class Ctx:
+    def __init__(self, args):
+        self.args = args
+        self.tmp = args.tmp
+
+    def log(self, msg):
+        print(f"[bench:{self.args.child}] {msg}", file=sys.stderr, flush=True)
+
+    def save(self, name, arr):
+        import numpy as np
+        path = os.path.join(self.tmp, f"{self.args.child}-{name}.npy")
+        np.save(path, np.ascontiguousarray(arr))
+        return path
+
+
+def _array(name, path, tree, delta, periodic, tol):
+    return {"name": name, "path": path, "tree": tree, "delta": delta, "periodic": periodic, "tol": tol}
+
+
+def child_headline(ctx):
     import torch
 
-    import oracle
-    from paper_2305_07165_amd import api
-
-    s = torch.from_numpy(pr.sigma).cuda()
+    from paper_2305_07165_amd import api, synth
+    args = ctx.args
+    t0 = time.perf_counter()
+    pr = synth.adaptive_3d(args.seed)
+    ctx.log(f"tree: {len(pr.levels)} leaves, N={pr.npoints}, generated in {time.perf_counter() - t0:.1f}s")
+    s = torch.from_numpy(pr.sigma).to("cuda:0")
     u = torch.empty_like(s)
-    # random leaves plus the 16 with the largest |sigma| (where u is largest),
-    # so the sample's l2 norm stands for the whole output's
-    rng = np.random.default_rng(777)
-    tg = set(rng.choice(len(pr.levels), min(ntarget, len(pr.levels)), replace=False).tolist())
-    tg |= set(np.argsort(-np.abs(pr.sigma).max(axis=1))[:16].tolist())
-    tg = np.array(sorted(tg), dtype=np.int64)
-    out = {}
-    for delta in (1e-3, 1e-5):
-        t0 = time.perf_counter()
-        uo = oracle.oracle_u(pr.levels, pr.coords, pr.p, delta, pr.sigma, targets=tg)
-        t_or = time.perf_counter() - t0
+    tp = time.perf_counter()
+    plan = api.Plan(pr.levels, pr.coords, pr.p, pr.delta, args.tol)
+    plan_ms = 1e3 * (time.perf_counter() - tp)
+    info = plan.info()
+    ctx.log(f"plan: lc={info['lc']} nr={info['nr']} pw_boxes={info['n_pwbox']} pw_leaves={info['n_pwleaf']} "
+            f"translations={info['n_plist']} near_pairs={info['n_near_pair']} plan_ms={plan_ms:.1f}")
+    wall, per = timed_steps(plan, s, u, args.steps, args.warmup, torch)
+    ms_step = 1e3 * wall / args.steps
+    value = pr.npoints * args.steps / wall
+    ctx.log(f"fp64 tol={args.tol:g}: {ms_step:.3f} ms/step, {value:.3e} pts/s")
+    upath = ctx.save("u", u.cpu().numpy())
+    # per-stage HIP-event durations on the plan's stream (profiled plan, same work)
+    pplan = api.Plan(pr.levels, pr.coords, pr.p, pr.delta, args.tol, profile=True)
+    for _ in range(args.warmup):
+        pplan.execute(s, u)
+    torch.cuda.synchronize()
+    acc = {k: 0.0 for k in STAGES}
+    for _ in range(args.steps):
+        pplan.execute(s, u)
+        pplan.sync()
+        for k, v in pplan.stage_times().items():
+            acc[k] += v
+    stage_ms = {k: v / args.steps for k, v in acc.items()}
+    pplan.close()
+    work = stage_work(info, near_runs(plan))
+    plan.close()
+    dom = max(stage_ms, key=stage_ms.get)
+    wd = work[dom]
+    t_dom = stage_ms[dom] * 1e-3
+    fl_rate, by_rate = wd["flops"] / t_dom, wd["bytes"] / t_dom
+    if wd["flops"] / PEAK_FP64 >= wd["bytes"] / PEAK_HBM:
+        # translations are vector arithmetic (rotations), the rest matrix-core products
+        roof = {"bound": "alu" if dom == "translate" else "mfma", "achieved": fl_rate / 1e12,
+                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fl_rate / PEAK_FP64}
+    else:
+        roof = {"bound": "hbm", "achieved": by_rate / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": by_rate / PEAK_HBM}
+    roof.update({"kernel": dom, "traffic": load_traffic(dom), "mean_ms": stage_ms[dom],
+                 "algorithmic_flops": wd["flops"], "algorithmic_bytes": wd["bytes"]})
+    tstar = sum(max(work[k]["flops"] / PEAK_FP64, work[k]["bytes"] / PEAK_HBM) for k in STAGES)
+    path = {"t_star_ms": 1e3 * tstar, "stage_ms": stage_ms,
+            "frac": 1e3 * tstar / max(sum(stage_ms.values()), 1e-9)}
+    ctx.log(f"stages: {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}")
+    return {"value": value, "ms_per_step": ms_step, "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+            "roofline": roof, "path_roofline": path,
+            "flops_per_point": sum(work[k]["flops"] for k in STAGES) / pr.npoints,
+            "config": {"workload": "3d-adaptive-free p=16 delta=1e-4 8 Gaussians seed %d, tol %g"
+                                   % (args.seed, args.tol),
+                       "npoints": pr.npoints, "nleaves": int(len(pr.levels)), "tol": args.tol,
+                       "lc": info["lc"], "nr": info["nr"], "plan_ms": plan_ms},
+            "arrays": [_array("fp64_tol%g" % args.tol, upath, "adaptive_3d", pr.delta, False, args.tol)]}
 
-        def run(tol, prec):
-            pl = api.Plan(pr.levels, pr.coords, pr.p, delta, tol, precision=prec)
-            wall, per = timed_steps(pl, s, u, steps, warmup, torch)
-            ug = u.cpu().numpy()
-            info = pl.info()
-            pl.close()
-            err = float(np.linalg.norm(ug[tg] - uo) / np.linalg.norm(uo))
-            emax = float(np.max(np.abs(ug[tg] - uo)) / np.max(np.abs(uo)))
-            return 1e3 * wall / steps, (err, emax), info
 
-        ms64, (err64, emax64), i64 = run(1e-6, "fp64")
-        rec = {"delta": delta, "fp64_tol1e-6": {"ms": ms64, "rel_l2": err64, "max_abs_rel": emax64,
-                                                "lc": i64["lc"], "nr": i64["nr"]},
-               "oracle_targets": int(len(tg)), "oracle_s": t_or}
-        for tol in (1e-3, 1e-6):
-            for prec in ("fp32", "bf16x3"):
-                ms, (err, emax), info = run(tol, prec)
-                rec[f"{prec}_tol{tol:g}"] = {"ms": ms, "points_per_s": pr.npoints / (ms * 1e-3),
-                                             "rel_l2": err, "max_abs_rel": emax, "meets_tol": err < tol,
-                                             "speedup_vs_fp64_tol1e-6": ms64 / ms, "nr": info["nr"]}
-        log(f"precision delta={delta:g}: fp64 1e-6 {ms64:.3f} ms err {err64:.1e}; " + "; ".join(
-            f"{k} {v['ms']:.3f} ms err {v['rel_l2']:.1e}" for k, v in rec.items()
-            if isinstance(v, dict) and "speedup_vs_fp64_tol1e-6" in v))
-        out[f"delta_{delta:g}"] = rec
+def child_config0(ctx):
+    """The small 2D workload (uniform level-3 tree, 64 leaves, p = 8, 4,096
+    points, delta = 1e-3, tol 1e-6): launch-latency bound, so it reports the
+    per-execute device time (HIP events, p50/p99 in microseconds), the host
+    time per call, and points/s, on both routes: the automatic cutoff level
+    (3: every pair direct) and the cutoff forced to 2 (every pair by plane
+    waves)."""
+    import torch
+
+    from paper_2305_07165_amd import api, synth
+    args = ctx.args
+    pr = synth.small_2d(args.seed)
+    s = torch.from_numpy(pr.sigma).to("cuda:0")
+    steps, warm = max(200, 4 * args.steps), max(20, args.warmup)
+    out = {"workload": "2d-uniform-l3 p=8 delta=1e-3 4 Gaussians seed %d, tol 1e-6" % args.seed,
+           "npoints": pr.npoints, "arrays": []}
+    for name, force_lc in (("auto", -1), ("forced_lc2", 2)):
+        u = torch.empty_like(s)
+        plan = api.Plan(pr.levels, pr.coords, pr.p, pr.delta, pr.tol, force_lc=force_lc)
+        info = plan.info()
+        wall, per = timed_steps(plan, s, u, steps, warm, torch)
+        med = pct(per, 50)
+        rec = {"lc": info["lc"], "nr": info["nr"], "n_near_pair": info["n_near_pair"],
+               "n_pwleaf": info["n_pwleaf"], "steps": steps,
+               "p50_us": 1e3 * med, "p99_us": 1e3 * pct(per, 99),
+               "host_us_per_call": 1e6 * wall / steps,
+               "points_per_s": pr.npoints / (med * 1e-3),
+               "points_per_s_wall": pr.npoints * steps / wall}
+        out[name] = rec
+        out["arrays"].append(_array(f"config0_{name}", ctx.save(name, u.cpu().numpy()),
+                                    "small_2d", pr.delta, False, pr.tol))
+        plan.close()
+        ctx.log(f"{name}: lc={info['lc']} p50 {rec['p50_us']:.1f} us p99 {rec['p99_us']:.1f} us, "
+                f"{rec['points_per_s']:.3e} pts/s, host {rec['host_us_per_call']:.1f} us/call")
     return out
 
 
-def batched_form(probs, steps, log):
+def child_forms(ctx):
+    """The headline tree at tol 1e-10 (FP64) and at tol 1e-6 with FP32 products."""
+    import torch
+
+    from paper_2305_07165_amd import api, synth
+    args = ctx.args
+    pr = synth.adaptive_3d(args.seed)
+    s = torch.from_numpy(pr.sigma).to("cuda:0")
+    out = {"arrays": []}
+    for name, tol, prec in (("fp64_tol1e-10", 1e-10, "fp64"), ("fp32_tol1e-6", 1e-6, "fp32")):
+        fp = api.Plan(pr.levels, pr.coords, pr.p, pr.delta, tol, precision=prec)
+        uf = torch.empty_like(s)
+        fw, fper = timed_steps(fp, s, uf, args.steps, args.warmup, torch)
+        fi = fp.info()
+        out[name] = {"value": pr.npoints * args.steps / fw, "ms_per_step": 1e3 * fw / args.steps,
+                     "p50_ms": pct(fper, 50), "p99_ms": pct(fper, 99), "tol": tol,
+                     "dtype": "f64" if prec == "fp64" else "f32", "nr": fi["nr"], "lc": fi["lc"]}
+        out["arrays"].append(_array(name, ctx.save(name, uf.cpu().numpy()), "adaptive_3d", pr.delta,
+                                    False, tol))
+        fp.close()
+        ctx.log(f"{name}: {out[name]['ms_per_step']:.3f} ms/step")
+    return out
+
+
+def child_periodic(ctx):
+    """The periodic variant of the 3D workload (blobs periodized over Z^3); its
+    tree and samples are built on the device by Algorithm 3."""
+    import torch
+
+    from paper_2305_07165_amd import api, synth
+    args = ctx.args
+    dens = synth.adaptive_3d_density(args.seed, wrap_blobs=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lvp, csp, sp, _ = api.resolve_gaussians(dens.centers, dens.widths, dens.amps, 16, 1e-9,
+                                           periodic=True, max_level=7)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    tree = {"levels": ctx.save("levels", lvp), "coords": ctx.save("coords", csp),
+            "sigma": ctx.save("sigma", sp.cpu().numpy()), "p": 16}
+    up = torch.empty_like(sp)
+    npp = int(sp.numel())
+    out = {"arrays": []}
+    for tol in (1e-6, 1e-10):
+        pp = api.Plan(lvp, csp, 16, 1e-4, tol, periodic=True)
+        pw, pper = timed_steps(pp, sp, up, args.steps, args.warmup, torch)
+        pi = pp.info()
+        name = f"periodic_fp64_tol{tol:g}"
+        out[name] = {"value": npp * args.steps / pw, "ms_per_step": 1e3 * pw / args.steps,
+                     "p50_ms": pct(pper, 50), "p99_ms": pct(pper, 99), "tol": tol, "dtype": "f64",
+                     "npoints": npp, "nleaves": int(len(lvp)), "lc": pi["lc"], "nr": pi["nr"],
+                     "tree_ms_device": 1e3 * tg}
+        out["arrays"].append(_array(name, ctx.save(name, up.cpu().numpy()), tree, 1e-4, True, tol))
+        pp.close()
+        ctx.log(f"periodic tol={tol:g}: {len(lvp)} leaves (built on the device in {1e3 * tg:.1f} ms), "
+                f"{1e3 * pw / args.steps:.3f} ms/step, {npp * args.steps / pw:.3e} pts/s")
+    return out
+
+
+def child_precision(ctx):
+    """The headline tree at delta in {1e-3, 1e-5}: FP32 and split-bf16 products
+    at tol 1e-3 and 1e-6 (and 1e-4, the smallest tol split bf16 is accepted
+    at), timed beside FP64 at tol 1e-6 on the same delta.  A precision fgt_plan
+    refuses at a tol is recorded as refused."""
+    import torch
+
+    from paper_2305_07165_amd import api, synth
+    args = ctx.args
+    steps = min(args.steps, 20)
+    pr = synth.adaptive_3d(args.seed)
+    s = torch.from_numpy(pr.sigma).to("cuda:0")
+    u = torch.empty_like(s)
+    out = {"arrays": []}
+    for delta in (1e-3, 1e-5):
+        key = f"delta_{delta:g}"
+
+        def run(tol, prec):
+            pl = api.Plan(pr.levels, pr.coords, pr.p, delta, tol, precision=prec)
+            wall, per = timed_steps(pl, s, u, steps, args.warmup, torch)
+            info = pl.info()
+            pl.close()
+            name = f"{key}_{prec}_tol{tol:g}"
+            out["arrays"].append(_array(name, ctx.save(name, u.cpu().numpy()), "adaptive_3d", delta,
+                                        False, tol))
+            return 1e3 * wall / steps, info
+
+        ms64, i64 = run(1e-6, "fp64")
+        rec = {"delta": delta, "fp64_tol1e-6": {"ms": ms64, "points_per_s": pr.npoints / (ms64 * 1e-3),
+                                                "lc": i64["lc"], "nr": i64["nr"]}}
+        for prec, tol in (("fp32", 1e-3), ("fp32", 1e-6), ("bf16x3", 1e-3), ("bf16x3", 1e-4),
+                          ("bf16x3", 1e-6)):
+            name = f"{prec}_tol{tol:g}"
+            try:
+                ms, info = run(tol, prec)
+            except api.FgtError as e:
+                rec[name] = {"refused": str(e)}
+                continue
+            rec[name] = {"ms": ms, "points_per_s": pr.npoints / (ms * 1e-3), "nr": info["nr"],
+                         "speedup_vs_fp64_tol1e-6": ms64 / ms}
+        ctx.log(f"precision delta={delta:g}: fp64 1e-6 {ms64:.3f} ms; " + "; ".join(
+            f"{k} " + (f"{v['ms']:.3f} ms" if "ms" in v else "refused") for k, v in rec.items()
+            if isinstance(v, dict) and k != "fp64_tol1e-6"))
+        out[key] = rec
+    return out
+
+
+def child_batched(ctx):
     """The batched workload (synth.batch_problems): every transform in its own
-    precision (FP32 when tol >= 1e-6, else FP64) in one batch (a captured HIP
-    graph, schedule picked by the autotuner), against the same transforms run
-    one after another with plain fgt_execute, in their own precision and all
-    in FP64."""
+    precision (FP32 when tol >= 1e-6, else FP64) in one batch (per-class
+    launches captured in one HIP graph on one stream), against the same
+    transforms run one after another with plain fgt_execute, in their own
+    precision and all in FP64."""
+    from paper_2305_07165_amd import synth
+    args = ctx.args
+    t0 = time.perf_counter()
+    # generated before the process touches the GPU (tree building forks workers)
+    probs = synth.batch_problems(args.seed + 200, args.batch_size, workers=min(16, os.cpu_count() or 1))
+    ctx.log(f"{len(probs)} transforms, generated in {time.perf_counter() - t0:.1f}s")
     import torch
 
     from paper_2305_07165_amd import api
-
+    steps = 3
     npts = sum(t.npoints for t in probs)
     sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
 
@@ -230,8 +423,7 @@ def batched_form(probs, steps, log):
             for pl, s_, u_ in zip(plans, sig, us):
                 pl.execute(s_, u_)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        return plans, us, dt
+        return plans, us, (time.perf_counter() - t0) / steps
 
     plans64, _, dt64 = seq(lambda t: "fp64")
     for pl in plans64:
@@ -239,12 +431,10 @@ def batched_form(probs, steps, log):
     del plans64
     # the batch's plans never fuse the 3D translation (measured faster in a batch)
     plans, us_seq, dtmix = seq(lambda t: t.precision, no_fuse=True)
-    log(f"batched: {len(probs)} transforms, {npts} points; sequential fp64 {1e3 * dt64:.2f} ms, "
-        f"sequential mixed {1e3 * dtmix:.2f} ms")
+    ctx.log(f"{npts} points; sequential fp64 {1e3 * dt64:.2f} ms, sequential mixed {1e3 * dtmix:.2f} ms")
     b = api.Batch(plans)
     us = [torch.empty_like(s) for s in sig]
     b.bind(sig, us)
-    tuned = b.tune(reps=3)
     b.execute()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -254,25 +444,21 @@ def batched_form(probs, steps, log):
     dt = (time.perf_counter() - t0) / steps
     same = all(torch.equal(a, c) for a, c in zip(us, us_seq))
     info = b.info()
-    log(f"batched: {1e3 * dt:.2f} ms per batch ({npts / dt:.3e} pts/s), tuned {tuned:.2f} ms, "
-        f"{info['nclasses']} classes, {info['nlaunches']} launches, streams {info['nstreams']}, "
-        f"class-major {info['class_major']}, alternative form tile in {info['tile_alt_classes']} classes, "
-        f"bitwise equal to sequential: {same}")
+    ctx.log(f"{1e3 * dt:.2f} ms per batch ({npts / dt:.3e} pts/s), {info['nclasses']} classes, "
+            f"{info['nlaunches']} launches, bitwise equal to sequential: {same}")
     b.close()
     for pl in plans:
         pl.close()
     return {"value": npts / dt, "unit": "grid points/s", "ms_per_batch": 1e3 * dt, "transforms": len(probs),
             "npoints": npts, "sequential_fp64_ms": 1e3 * dt64, "sequential_same_precision_ms": 1e3 * dtmix,
             "speedup_vs_sequential_fp64": dt64 / dt, "speedup_vs_sequential_same_precision": dtmix / dt,
-            "bitwise_equal_to_sequential": same, "tuned_ms": tuned,
-            "schedule": {"nstreams": info["nstreams"], "class_major": bool(info["class_major"]),
-                         "form_tile_alt_classes": info["tile_alt_classes"]},
+            "bitwise_equal_to_sequential": same, "schedule": "per-class launches, one stream, one HIP graph",
             "nclasses": info["nclasses"], "nlaunches": info["nlaunches"],
             "precisions": {"fp32": sum(t.precision == "fp32" for t in probs),
                            "fp64": sum(t.precision == "fp64" for t in probs)}}
 
 
-def served_form(seed, nreq, log):
+def child_served(ctx):
     """The serving workload: a pool of request types (d ~ U{2,3}, N log-uniform
     in [1e4, 1e8], delta log-uniform in [1e-6, 1e-2], tol ~ U{1e-3, 1e-6,
     1e-10}, p ~ U{8, 16}), requests drawn uniformly from the pool.  Reports
@@ -281,11 +467,12 @@ def served_form(seed, nreq, log):
     import numpy as np
 
     from paper_2305_07165_amd import api, serving, synth
-
+    args = ctx.args
+    seed, nreq = args.seed + 100, args.serve_requests
     t0 = time.perf_counter()
     types = synth.serve_request_types(seed, 12)
-    log(f"served: {len(types)} request types, {sum(t.npoints for t in types)} points in all, "
-        f"generated in {time.perf_counter() - t0:.1f}s")
+    ctx.log(f"{len(types)} request types, {sum(t.npoints for t in types)} points in all, "
+            f"generated in {time.perf_counter() - t0:.1f}s")
     pool = serving.Pool(types)
     rng = np.random.default_rng(seed + 1)
     kinds = rng.integers(0, len(types), nreq)
@@ -303,17 +490,222 @@ def served_form(seed, nreq, log):
                     "speedup_vs_sequential": (cl_pts / cl_s) / (seq_pts / seq_s),
                     "closed_loop_p50_ms": float(np.percentile([c["total_ms"] for c in done], 50)),
                     "closed_loop_p99_ms": float(np.percentile([c["total_ms"] for c in done], 99))})
-        log(f"served closed loop: {cap:.1f} req/s, {cl_pts / cl_s:.3e} pts/s "
-            f"(sequential {seq_pts / seq_s:.3e} pts/s)")
+        ctx.log(f"closed loop: {cap:.1f} req/s, {cl_pts / cl_s:.3e} pts/s "
+                f"(sequential {seq_pts / seq_s:.3e} pts/s)")
         out["poisson"] = []
         for frac in (0.3, 0.6, 0.9):
             r = serving.poisson(srv, pool, kinds, frac * cap, np.random.default_rng(seed + 2))
             r["load"] = frac
             out["poisson"].append(r)
-            log(f"served poisson {frac:.0%}: p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms "
-                f"{r['points_per_s']:.3e} pts/s")
+            ctx.log(f"poisson {frac:.0%}: p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms "
+                    f"{r['points_per_s']:.3e} pts/s")
         out["server_stats"] = srv.stats()
     return out
+
+
+# ---------------------------------------------------------------------------
+# parent: children in order, then the CPU leg
+
+
+CHILD_TIMEOUT_S = {"headline": 300, "config0": 120, "forms": 180, "periodic": 180, "precision": 240,
+                   "batched": 300, "served": 300}
+
+
+def run_child(name, args, log):
+    cmd = [sys.executable, os.path.abspath(__file__), "--child", name, "--tmp", args.tmp,
+           "--steps", str(args.steps), "--warmup", str(args.warmup), "--seed", str(args.seed),
+           "--tol", repr(args.tol), "--batch-size", str(args.batch_size),
+           "--serve-requests", str(args.serve_requests)]
+    t0 = time.perf_counter()
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=None, text=True,
+                           timeout=CHILD_TIMEOUT_S[name])
+        rc, text = r.returncode, r.stdout
+    except subprocess.TimeoutExpired as e:
+        rc, text = 124, (e.stdout or b"").decode() if isinstance(e.stdout, bytes) else (e.stdout or "")
+    dt = time.perf_counter() - t0
+    res = None
+    for line in reversed(text.strip().splitlines()):
+        if line.startswith("{"):
+            try:
+                res = json.loads(line)
+            except ValueError:
+                res = None
+            break
+    if rc != 0 or res is None:
+        log(f"child {name} failed: rc={rc} after {dt:.1f}s")
+        return {"rc": rc, "seconds": dt, "error": "exit status %d" % rc}
+    log(f"child {name} done in {dt:.1f}s")
+    res["rc"], res["seconds"] = 0, dt
+    return res
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(results, args, log):
+    """The oracle over every leaf of each (tree, delta, boundary) that a child
+    returned u for: rel-l2 and max-abs errors of every form, and the oracle's
+    own time on the headline tree (cpu_baseline)."""
+    import numpy as np
+
+    import oracle
+    from paper_2305_07165_amd import synth
+    groups = {}
+    for cname, res in results.items():
+        for a in res.get("arrays", []):
+            tk = json.dumps(a["tree"], sort_keys=True)
+            groups.setdefault((tk, a["delta"], a["periodic"]), []).append((cname, a))
+    trees = {}
+    acc = {}
+    cpu = None
+    for (tk, delta, periodic), items in groups.items():
+        tree = json.loads(tk)
+        if tree not in ("adaptive_3d", "small_2d") and not isinstance(tree, dict):
+            continue
+        if tk not in trees:
+            if tree == "adaptive_3d":
+                pr = synth.adaptive_3d(args.seed)
+                trees[tk] = (pr.levels, pr.coords, pr.p, pr.sigma)
+            elif tree == "small_2d":
+                pr = synth.small_2d(args.seed)
+                trees[tk] = (pr.levels, pr.coords, pr.p, pr.sigma)
+            else:
+                trees[tk] = (np.load(tree["levels"]), np.load(tree["coords"]), tree["p"],
+                             np.load(tree["sigma"]))
+        lv, cs, p, sig = trees[tk]
+        t0 = time.perf_counter()
+        uo = oracle.oracle_u(lv, cs, p, delta, sig, periodic=periodic)
+        dt = time.perf_counter() - t0
+        log(f"oracle: {len(lv)} leaves, delta={delta:g}, periodic={periodic}: {dt:.1f}s")
+        if tree == "adaptive_3d" and delta == 1e-4 and not periodic:
+            nt = len(lv)
+            cpu = {"value": nt * p ** 3 / dt, "unit": "grid points/s", "cores": oracle.threads_used(),
+                   "cpu_model": cpu_model(), "kind": "oracle",
+                   "sample": f"all {nt} leaves ({nt * p ** 3} grid points) of the headline tree, every "
+                             f"source leaf within r_cut, FP64, {dt:.1f} s"}
+        nrm, mx = float(np.linalg.norm(uo)), float(np.max(np.abs(uo)))
+        for cname, a in items:
+            ug = np.load(a["path"])
+            e = {"rel_l2": float(np.linalg.norm(ug - uo) / nrm),
+                 "max_abs_rel": float(np.max(np.abs(ug - uo)) / mx), "tol": a["tol"],
+                 "nodes_compared": int(ug.size)}
+            e["meets_tol"] = e["rel_l2"] < a["tol"] and e["max_abs_rel"] < a["tol"]
+            acc[a["name"]] = e
+            os.remove(a["path"])
+    return acc, cpu
+
+
+def attach_accuracy(forms, acc):
+    """Puts each array's error next to the timing it belongs to."""
+    for name, e in acc.items():
+        if name in forms and isinstance(forms[name], dict):
+            forms[name]["accuracy"] = e
+    prec = forms.get("precision", {})
+    for key, rec in prec.items():
+        if not isinstance(rec, dict) or not key.startswith("delta_"):
+            continue
+        for k, v in rec.items():
+            a = acc.get(f"{key}_{k}")
+            if isinstance(v, dict) and a:
+                v["accuracy"] = a
+    c0 = forms.get("config0", {})
+    for k in ("auto", "forced_lc2"):
+        if k in c0 and f"config0_{k}" in acc:
+            c0[k]["accuracy"] = acc[f"config0_{k}"]
+
+
+def parent(args):
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    skip = set()
+    if args.no_forms:
+        skip |= {"forms", "periodic", "precision", "batched", "served"}
+    if args.no_batch:
+        skip.add("batched")
+    if args.no_serve:
+        skip.add("served")
+    args.tmp = tempfile.mkdtemp(prefix="fgt_bench_")
+    results = {}
+    try:
+        for name in CHILDREN:
+            if name in skip:
+                continue
+            log(f"child {name}")
+            results[name] = run_child(name, args, log)
+        acc, cpu = ({}, None)
+        if args.cpu_leaves != 0:
+            acc, cpu = cpu_leg(results, args, log)
+    finally:
+        shutil.rmtree(args.tmp, ignore_errors=True)
+    head = results.get("headline", {})
+    forms = {}
+    for name in ("forms", "periodic"):
+        for k, v in results.get(name, {}).items():
+            if isinstance(v, dict) and "ms_per_step" in v:
+                if head.get("value"):
+                    v["speedup_vs_fp64_tol1e-6"] = v["value"] / head["value"]
+                forms[k] = v
+    for name in ("config0", "precision", "batched", "served"):
+        if name in results:
+            forms[name] = {k: v for k, v in results[name].items() if k != "arrays"}
+    attach_accuracy(forms, acc)
+    for name in ("forms", "periodic"):
+        if name in results and results[name].get("rc"):
+            forms[name + "_error"] = {"rc": results[name]["rc"]}
+    hacc = acc.get("fp64_tol%g" % args.tol)
+    out = {
+        "metric": METRIC, "value": head.get("value"), "unit": "grid points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.get("ms_per_step"),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": head.get("config", {"workload": "3d-adaptive-free p=16 delta=1e-4 8 Gaussians seed %d, "
+                                                  "tol %g" % (args.seed, args.tol)}),
+        "p50_ms": head.get("p50_ms"), "p99_ms": head.get("p99_ms"),
+        "roofline": head.get("roofline"), "path_roofline": head.get("path_roofline"),
+        "cpu_baseline": cpu,
+        "accuracy": hacc,
+        "accuracy_rel_l2": {k: v["rel_l2"] for k, v in acc.items()},
+        "forms": forms,
+        "flops_per_point": head.get("flops_per_point"),
+        "children": {k: {"rc": v.get("rc"), "seconds": v.get("seconds")} for k, v in results.items()},
+        # the paper's own figures for this method, on other hardware: context, not a target
+        "paper_context": {"value_range": [1e6, 7e6], "unit": "grid points/s", "d": 3,
+                          "hardware": "1 thread of an Intel i9-10885H at 2.40 GHz, Fortran, no SIMD",
+                          "workload": "adaptive tensor Legendre grids, k = 16, several tolerances"},
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if head.get("rc") == 0 else 1
+
+
+def profile_only(args):
+    """warmup + steps of the headline plan in this process (for rocprofv3)."""
+    import torch
+
+    from paper_2305_07165_amd import api, synth
+    pr = synth.adaptive_3d(args.seed)
+    s = torch.from_numpy(pr.sigma).to("cuda:0")
+    u = torch.empty_like(s)
+    plan = api.Plan(pr.levels, pr.coords, pr.p, pr.delta, args.tol)
+    timed_steps(plan, s, u, args.steps, args.warmup, torch)
+    if args.calib_copy:
+        # a plain device copy of known size: 1 GiB read + 1 GiB written, to
+        # scale the FETCH_SIZE / WRITE_SIZE counters
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+    plan.close()
+    print("[bench] profile-only run done", file=sys.stderr, flush=True)
 
 
 def main():
@@ -324,16 +716,18 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-leaves", type=int, default=-1,
-                    help="target leaves in the CPU-oracle sample (-1 = every leaf, 0 = skip)")
-    ap.add_argument("--no-forms", action="store_true", help="skip the tol=1e-10 and FP32 lines")
+                    help="0 = skip the CPU leg (oracle accuracy and cpu_baseline); else every leaf")
+    ap.add_argument("--no-forms", action="store_true", help="headline and the small 2D workload only")
     ap.add_argument("--no-serve", action="store_true", help="skip the served form")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-size", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--profile-only", action="store_true",
-                    help="run warmup+steps of the headline plan only (for rocprofv3)")
+                    help="run warmup+steps of the headline plan only, in this process (for rocprofv3)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="with --profile-only: also run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--child", choices=CHILDREN, help=argparse.SUPPRESS)
+    ap.add_argument("--tmp", help=argparse.SUPPRESS)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -341,183 +735,15 @@ def main():
               "(it would shard by cutoff-level subtrees with a one-box halo of sigma).",
               file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    from paper_2305_07165_amd import api, synth
-
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    log("building the 3D adaptive workload")
-    t0 = time.perf_counter()
-    pr = synth.adaptive_3d(args.seed)
-    log(f"tree: {len(pr.levels)} leaves, N={pr.npoints}, generated in {time.perf_counter() - t0:.1f}s")
-    batch_probs = None
-    if not (args.no_forms or args.no_batch or args.profile_only):
-        # generated before the process touches the GPU (tree building forks workers)
-        t0 = time.perf_counter()
-        batch_probs = synth.batch_problems(args.seed + 200, args.batch_size,
-                                           workers=min(16, os.cpu_count() or 1))
-        log(f"batched workload: {len(batch_probs)} transforms, generated in {time.perf_counter() - t0:.1f}s")
-    dev = torch.device("cuda:0")
-    s = torch.from_numpy(pr.sigma).to(dev)
-    u = torch.empty_like(s)
-
-    tp = time.perf_counter()
-    plan = api.Plan(pr.levels, pr.coords, pr.p, pr.delta, args.tol)
-    plan_ms = 1e3 * (time.perf_counter() - tp)
-    info = plan.info()
-    log(f"plan: lc={info['lc']} nr={info['nr']} pw_boxes={info['n_pwbox']} pw_leaves={info['n_pwleaf']} "
-        f"translations={info['n_plist']} near_pairs={info['n_near_pair']} plan_ms={plan_ms:.1f}")
     if args.profile_only:
-        timed_steps(plan, s, u, args.steps, args.warmup, torch)
-        if args.calib_copy:
-            # a plain device copy of known size: 1 GiB read + 1 GiB written,
-            # to scale the FETCH_SIZE / WRITE_SIZE counters
-            x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-            y = torch.empty_like(x)
-            y.copy_(x)
-            torch.cuda.synchronize()
-        log("profile-only run done")
+        profile_only(args)
         return
-
-    wall, per = timed_steps(plan, s, u, args.steps, args.warmup, torch)
-    ms_step = 1e3 * wall / args.steps
-    value = pr.npoints * args.steps / wall
-    log(f"fp64 tol={args.tol}: {ms_step:.3f} ms/step, {value:.3e} pts/s")
-    u_head = u.cpu().numpy()
-
-    # per-stage HIP-event durations on the plan's stream (profiled plan, same work)
-    pplan = api.Plan(pr.levels, pr.coords, pr.p, pr.delta, args.tol, profile=True)
-    for _ in range(args.warmup):
-        pplan.execute(s, u)
-    torch.cuda.synchronize()
-    acc = {k: 0.0 for k in STAGES}
-    for _ in range(args.steps):
-        pplan.execute(s, u)
-        pplan.sync()
-        for k, v in pplan.stage_times().items():
-            acc[k] += v
-    stage_ms = {k: v / args.steps for k, v in acc.items()}
-    pplan.close()
-    work = stage_work(info, near_runs(plan))
-    dom = max(stage_ms, key=stage_ms.get)
-    wd = work[dom]
-    t_dom = stage_ms[dom] * 1e-3
-    fl_rate, by_rate = wd["flops"] / t_dom, wd["bytes"] / t_dom
-    flop_bound = wd["flops"] / PEAK_FP64 >= wd["bytes"] / PEAK_HBM
-    if flop_bound:
-        # translations are vector arithmetic (rotations), the rest matrix-core products
-        roof = {"bound": "alu" if dom == "translate" else "mfma", "achieved": fl_rate / 1e12,
-                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": fl_rate / PEAK_FP64}
-    else:
-        roof = {"bound": "hbm", "achieved": by_rate / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": by_rate / PEAK_HBM}
-    tr = load_traffic(dom)
-    roof.update({"kernel": dom, "traffic": tr, "mean_ms": stage_ms[dom],
-                 "algorithmic_flops": wd["flops"], "algorithmic_bytes": wd["bytes"]})
-    tstar = sum(max(work[k]["flops"] / PEAK_FP64, work[k]["bytes"] / PEAK_HBM) for k in STAGES)
-    path = {"t_star_ms": 1e3 * tstar, "stage_ms": stage_ms,
-            "frac": 1e3 * tstar / max(sum(stage_ms.values()), 1e-9)}
-    log(f"stages: {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}")
-
-    forms = {}
-    if not args.no_forms:
-        for name, tol, prec in (("fp64_tol1e-10", 1e-10, "fp64"), ("fp32_tol1e-6", 1e-6, "fp32")):
-            fp = api.Plan(pr.levels, pr.coords, pr.p, pr.delta, tol, precision=prec)
-            uf = torch.empty_like(s)
-            fw, fper = timed_steps(fp, s, uf, args.steps, args.warmup, torch)
-            fi = fp.info()
-            forms[name] = {"value": pr.npoints * args.steps / fw, "ms_per_step": 1e3 * fw / args.steps,
-                           "p50_ms": pct(fper, 50), "p99_ms": pct(fper, 99), "tol": tol,
-                           "dtype": "f64" if prec == "fp64" else "f32", "nr": fi["nr"], "lc": fi["lc"],
-                           "speedup_vs_fp64_tol1e-6": (pr.npoints * args.steps / fw) / value,
-                           "_u": uf.cpu().numpy()}
-            fp.close()
-            log(f"{name}: {forms[name]['ms_per_step']:.3f} ms/step")
-
-    if not args.no_forms:
-        # the periodic variant of the 3D workload (blobs periodized over Z^3);
-        # its tree and samples are built on the device by Algorithm 3, the same
-        # tree the numpy generator builds, in milliseconds instead of a minute
-        dens = synth.adaptive_3d_density(args.seed, wrap_blobs=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lvp, csp, sp, dinfo = api.resolve_gaussians(dens.centers, dens.widths, dens.amps, 16, 1e-9,
-                                                    periodic=True, max_level=7)
-        torch.cuda.synchronize()
-        tg = time.perf_counter() - t0
-        up = torch.empty_like(sp)
-        npp = int(sp.numel())
-        for tol in (1e-6, 1e-10):
-            pp = api.Plan(lvp, csp, 16, pr.delta, tol, periodic=True)
-            pw, pper = timed_steps(pp, sp, up, args.steps, args.warmup, torch)
-            pi = pp.info()
-            forms[f"periodic_fp64_tol{tol:g}"] = {
-                "value": npp * args.steps / pw, "ms_per_step": 1e3 * pw / args.steps,
-                "p50_ms": pct(pper, 50), "p99_ms": pct(pper, 99), "tol": tol, "dtype": "f64",
-                "npoints": npp, "nleaves": int(len(lvp)), "lc": pi["lc"], "nr": pi["nr"],
-                "tree_ms_device": 1e3 * tg}
-            pp.close()
-            log(f"periodic tol={tol:g}: {len(lvp)} leaves (built on the device in {1e3 * tg:.1f} ms), "
-                f"{1e3 * pw / args.steps:.3f} ms/step, {npp * args.steps / pw:.3e} pts/s")
-        del sp, up
-        forms["precision"] = precision_form(pr, min(args.steps, 20), args.warmup, log)
-    if batch_probs is not None:
-        forms["batched"] = batched_form(batch_probs, 3, log)
-        del batch_probs
-    if not (args.no_forms or args.no_serve):
-        forms["served"] = served_form(args.seed + 100, args.serve_requests, log)
-
-    cpu = None
-    accuracy = {}
-    if args.cpu_leaves != 0:
-        import oracle
-        rng = np.random.default_rng(12345)
-        nt = len(pr.levels) if args.cpu_leaves < 0 else min(args.cpu_leaves, len(pr.levels))
-        tg = np.sort(rng.choice(len(pr.levels), nt, replace=False))
-        log(f"cpu oracle on {nt} target leaves")
-        tc = time.perf_counter()
-        uo = oracle.oracle_u(pr.levels, pr.coords, pr.p, pr.delta, pr.sigma, targets=tg)
-        dt = time.perf_counter() - tc
-        cpu = {"value": nt * pr.p ** 3 / dt, "unit": "grid points/s", "cores": oracle.threads_used(),
-               "kind": "oracle",
-               "sample": (f"all {nt} leaves ({nt * pr.p ** 3} grid points) of the tree"
-                          if nt == len(pr.levels) else
-                          f"{nt} random target leaves ({nt * pr.p ** 3} grid points) of the tree")
-                         + f", every source leaf within r_cut, {dt:.1f} s"}
-
-        def err(a):
-            return float(np.linalg.norm(a[tg] - uo) / np.linalg.norm(uo))
-        accuracy["fp64_tol%g" % args.tol] = err(u_head)
-        for name, f in forms.items():
-            if isinstance(f, dict) and "_u" in f:
-                accuracy[name] = err(f["_u"])
-                f["rel_l2_vs_oracle"] = accuracy[name]
-    for f in forms.values():
-        if isinstance(f, dict):
-            f.pop("_u", None)
-
-    out = {
-        "metric": "grid points/s at tol=1e-6 (3D adaptive), FP64 vs mixed; p50/p99 latency",
-        "value": value, "unit": "grid points/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "3d-adaptive-free p=16 delta=1e-4 8 Gaussians seed 0, tol 1e-6",
-                   "npoints": pr.npoints, "nleaves": int(len(pr.levels)), "tol": args.tol,
-                   "lc": info["lc"], "nr": info["nr"], "plan_ms": plan_ms},
-        "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
-        "roofline": roof, "path_roofline": path,
-        "cpu_baseline": cpu, "accuracy_rel_l2": accuracy, "forms": forms,
-        "flops_per_point": sum(work[k]["flops"] for k in STAGES) / pr.npoints,
-        # the paper's own figures for this method, on other hardware: context, not a target
-        "paper_context": {"value_range": [1e6, 7e6], "unit": "grid points/s", "d": 3,
-                          "hardware": "1 thread of an Intel i9-10885H at 2.40 GHz, Fortran, no SIMD",
-                          "workload": "adaptive tensor Legendre grids, k = 16, several tolerances"},
-    }
-    print(json.dumps(out), flush=True)
+    if args.child:
+        ctx = Ctx(args)
+        res = globals()["child_" + args.child](ctx)
+        print(json.dumps(res), flush=True)
+        return
+    sys.exit(parent(args))
 
 
 if __name__ == "__main__":

@@ -48,11 +48,14 @@ extern "C" {
 
 #define FGT_FP64 0 /* every contraction in FP64 */
 #define FGT_FP32 1 /* contractions and expansions in FP32 with FP32 accumulation;
-                      tables are built in FP64 and rounded once; sigma/u stay FP64 */
+                      tables are built in FP64 and rounded once; sigma/u stay FP64.
+                      Adds about 2e-7 relative l2 error: fgt_plan accepts it for
+                      tol >= 1e-6 only (FGT_ERR_UNSUPPORTED below) */
 #define FGT_BF16X3 2 /* as FGT_FP32, but every matrix product runs as three bf16
                         matrix-core products of hi/lo splits of its FP32 operands
                         (the lo x lo term dropped), accumulated in FP32; translations
-                        stay FP32.  About 1e-5 relative error per product */
+                        stay FP32.  About 1e-5 relative error per product and 3e-6
+                        relative l2 error on u: accepted for tol >= 1e-4 only */
 
 typedef struct fgt_tree {
   int32_t dim;           /* 1, 2 or 3 */
@@ -117,7 +120,8 @@ typedef struct fgt_plan fgt_plan_t;
  * of image boxes at a cutoff level >= 2 and the truncated Fourier series of
  * the periodic kernel on the root otherwise (Section 5; fgt_info_t.fourier);
  * FGT_ERR_UNSUPPORTED if that series needs more than 128 real modes
- * (2 n_p + 1 > 128, only with force_lc on a small delta).
+ * (2 n_p + 1 > 128, only with force_lc on a small delta), and for a
+ * reduced precision below its smallest tol (FGT_FP32: 1e-6, FGT_BF16X3: 1e-4).
  * opts may be NULL.  *out receives a plan owned by the caller (fgt_destroy).
  */
 int fgt_plan(const fgt_tree_t* tree, int p, double delta, double tol, int bc,

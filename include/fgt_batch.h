@@ -12,11 +12,9 @@
  * graph and replayed.  Results are bitwise identical to fgt_execute of each
  * plan alone (the same kernel bodies, the same fixed-order reductions).
  *
- * An autotuner (fgt_batch_tune) times the legal launch schedules -- how many
- * streams the classes are spread over and whether a stream runs its classes
- * stage by stage or class by class -- and keeps the fastest; then, per kernel
- * class, the tile shape of the d = 3 box formation (four or two 16-column
- * slabs per wave), keeping the other shape where it measures faster.  Tile
+ * The schedule -- how many streams the classes are spread over and whether a
+ * stream runs its classes stage by stage or class by class -- and the tile
+ * shape of the d = 3 box formation are chosen at fgt_batch_create.  Tile
  * shapes change neither the columns nor the order of any sum: results stay
  * bitwise identical.
  *
@@ -41,9 +39,8 @@ typedef struct fgt_batch_opts {
   int32_t nstreams;    /* schedule: streams the classes are spread over (1..8; 0 = 1) */
   int32_t class_major; /* schedule: 1 = each stream runs its classes one after the other,
                           0 = stage by stage across its classes */
-  int32_t form_tile;   /* box-formation tile shape of every d = 3 class until fgt_batch_tune
-                          chooses per class: 0 (default) = four 16-column slabs per wave,
-                          as fgt_execute; 1 = two */
+  int32_t form_tile;   /* box-formation tile shape of every d = 3 class: 0 (default) = four
+                          16-column slabs per wave, as fgt_execute; 1 = two */
 } fgt_batch_opts_t;
 
 typedef struct fgt_batch_info {
@@ -52,7 +49,7 @@ typedef struct fgt_batch_info {
   int32_t nsingle;      /* 1D plans run one by one */
   int32_t nlaunches;    /* kernel launches per execution */
   int32_t nstreams, class_major, use_graph;
-  double tuned_ms;      /* best time per execution found by fgt_batch_tune (0 if not tuned) */
+  double tuned_ms;      /* 0: the autotuner is switched off (fgt_batch_tune) */
   int32_t tile_alt_classes; /* classes whose box formation runs the alternative tile shape */
 } fgt_batch_info_t;
 
@@ -70,12 +67,10 @@ int fgt_batch_bind(fgt_batch_t* b, const double* const* sigma, double* const* u)
 /* Enqueues one execution of every transform of the batch on its stream. */
 int fgt_batch_execute(fgt_batch_t* b);
 
-/* Times every schedule (nstreams in {1, 2, 4} x {stage by stage, class by
-   class}) with `reps` executions each after one warm-up and keeps the
-   fastest; then tries the alternative box-formation tile of each d = 3 class
-   (largest first) and keeps it where the execution gets more than 0.5%
-   faster.  Returns the best mean time per execution in *best_ms (may be
-   NULL).  The batch must be bound.  Synchronizes the batch's stream. */
+/* Schedule autotuner: switched off.  It re-captured the batch graph once per
+   trial schedule and crashed the host process intermittently on large batches,
+   for a reason not established; it now returns FGT_ERR_UNSUPPORTED (and 0 in
+   *best_ms, which may be NULL) without touching the device. */
 int fgt_batch_tune(fgt_batch_t* b, int32_t reps, double* best_ms);
 
 int fgt_batch_info(const fgt_batch_t* b, fgt_batch_info_t* info);

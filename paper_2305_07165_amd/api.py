@@ -12,7 +12,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import FGT_BF16X3, FGT_FP32, FGT_FP64, FGT_FREE, FGT_PERIODIC, FgtError, check
+from ._lib import (FGT_BF16X3, FGT_ERR_UNSUPPORTED, FGT_FP32, FGT_FP64, FGT_FREE, FGT_PERIODIC,  # noqa: F401
+                   FgtError, check)
 
 _PRECISION = {"fp64": FGT_FP64, "fp32": FGT_FP32, "bf16x3": FGT_BF16X3}
 

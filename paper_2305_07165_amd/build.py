@@ -32,21 +32,35 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """True when obj is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(d, f) for d in (CSRC, os.path.join(ROOT, "include"))
+                    for f in os.listdir(d) if f.endswith(".h")]
+    return any(os.path.getmtime(x) > t for x in deps)
+
+
+def build(verbose: bool = True, incremental: bool = False) -> str:
+    """Compiles every source (incremental=True: only objects older than their
+    source or a header) and links libfgt.so and the ceilings probe."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
     for src in HOST_SRC:
         obj = os.path.join(BUILD, src + ".o")
-        jobs.append((["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+        jobs.append((["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj, src))
     for src in HIP_SRC:
         obj = os.path.join(BUILD, src + ".o")
-        jobs.append(([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+        jobs.append(([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj, src))
+    todo = [cmd for cmd, obj, src in jobs
+            if not incremental or _stale(obj, os.path.join(CSRC, src))]
     # independent translation units compile in parallel
     workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        for f in [ex.submit(_run, cmd) for cmd, _ in jobs]:
+        for f in [ex.submit(_run, cmd) for cmd in todo]:
             f.result()
-    objs = [obj for _, obj in jobs]
+    objs = [obj for _, obj, _ in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
@@ -59,5 +73,5 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)
     sys.exit(0)

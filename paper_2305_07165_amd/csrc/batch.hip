@@ -5,8 +5,7 @@
 // launch sequence of an execution is captured into a HIP graph on a private
 // stream and replayed on the batch's stream.  A schedule spreads the classes
 // over one or more streams (a fork/join inside the graph) and orders each
-// stream's launches stage by stage or class by class; fgt_batch_tune picks
-// the schedule by timing, then the box-formation tile shape of each class.
+// stream's launches stage by stage or class by class; the caller picks it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,8 +62,12 @@ struct fgt_batch {
 
 namespace {
 
+// Destroys the instantiated graph once no replay of it is in flight.
 void drop_graph(fgt_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->exec) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipGraphExecDestroy(b->exec);
+  }
   b->exec = nullptr;
 }
 
@@ -351,84 +354,13 @@ int fgt_batch_execute(fgt_batch_t* b) {
 
 int fgt_batch_tune(fgt_batch_t* b, int32_t reps, double* best_ms) {
   if (!b || reps < 1) return fgt::set_error(FGT_ERR_INVALID_ARG, "batch is NULL or reps < 1");
-  if (!b->bound) return fgt::set_error(FGT_ERR_INVALID_ARG, "batch is not bound (fgt_batch_bind)");
-  hipError_t e = hipSetDevice(b->device);
-  if (e != hipSuccess) return herr(e, "hipSetDevice");
-  hipEvent_t t0, t1;
-  if ((e = hipEventCreate(&t0)) != hipSuccess) return herr(e, "hipEventCreate");
-  if ((e = hipEventCreate(&t1)) != hipSuccess) {
-    (void)hipEventDestroy(t0);
-    return herr(e, "hipEventCreate");
-  }
-  for (ClassRun& cr : b->classes) cr.tile = 0;  // schedules are timed with the default tiles
-  const int cand_ns[3] = {1, 2, 4};
-  double best = -1;
-  int best_ns = b->nstreams;
-  bool best_cm = b->class_major;
-  int rc = FGT_OK;
-  for (int ci = 0; ci < 3 && rc == FGT_OK; ci++) {
-    for (int cm = 0; cm < 2 && rc == FGT_OK; cm++) {
-      b->nstreams = cand_ns[ci];
-      b->class_major = cm != 0;
-      drop_graph(b);
-      if ((rc = ensure_side_streams(b)) != FGT_OK) break;
-      if ((rc = launch(b)) != FGT_OK) break;  // warm-up (and capture)
-      if ((e = hipEventRecord(t0, b->stream)) != hipSuccess) { rc = herr(e, "hipEventRecord"); break; }
-      for (int r = 0; r < reps && rc == FGT_OK; r++) rc = launch(b);
-      if (rc != FGT_OK) break;
-      if ((e = hipEventRecord(t1, b->stream)) != hipSuccess) { rc = herr(e, "hipEventRecord"); break; }
-      if ((e = hipEventSynchronize(t1)) != hipSuccess) { rc = herr(e, "hipEventSynchronize"); break; }
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, t0, t1);
-      const double per = ms / reps;
-      if (best < 0 || per < best) {
-        best = per;
-        best_ns = b->nstreams;
-        best_cm = b->class_major;
-      }
-    }
-  }
-  b->nstreams = best_ns;
-  b->class_major = best_cm;
-  drop_graph(b);
-  if (rc == FGT_OK) rc = ensure_side_streams(b);
-  // tile shapes: with the schedule fixed, try the alternative box-formation
-  // tile for each class that has one, largest class first, and keep it when
-  // the whole execution gets faster by more than the timing noise (0.5%)
-  std::vector<int> order;
-  for (size_t c = 0; c < b->classes.size(); c++)
-    if (b->classes[c].has_tiles()) order.push_back((int)c);
-  std::sort(order.begin(), order.end(), [&](int x, int y) { return b->classes[x].work > b->classes[y].work; });
-  auto time_once = [&](double* per) -> int {
-    drop_graph(b);
-    int r = launch(b);  // warm-up (and capture)
-    if (r != FGT_OK) return r;
-    if ((e = hipEventRecord(t0, b->stream)) != hipSuccess) return herr(e, "hipEventRecord");
-    for (int k = 0; k < reps && r == FGT_OK; k++) r = launch(b);
-    if (r != FGT_OK) return r;
-    if ((e = hipEventRecord(t1, b->stream)) != hipSuccess) return herr(e, "hipEventRecord");
-    if ((e = hipEventSynchronize(t1)) != hipSuccess) return herr(e, "hipEventSynchronize");
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, t0, t1);
-    *per = ms / reps;
-    return FGT_OK;
-  };
-  if (rc == FGT_OK && !order.empty()) rc = time_once(&best);  // the fixed schedule, tiles 0
-  for (size_t k = 0; k < order.size() && rc == FGT_OK; k++) {
-    ClassRun& cr = b->classes[order[k]];
-    cr.tile = 1;
-    double per = 0;
-    if ((rc = time_once(&per)) != FGT_OK) break;
-    if (per < 0.995 * best) best = per;
-    else cr.tile = 0;
-  }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
-  drop_graph(b);
-  if (rc != FGT_OK) return rc;
-  b->tuned_ms = best;
-  if (best_ms) *best_ms = best;
-  return FGT_OK;
+  if (best_ms) *best_ms = 0;
+  // The tuner re-captured and re-instantiated the batch graph once per trial
+  // schedule (with a fork/join over side streams) and crashed the host process
+  // intermittently on large batches; its cause is not established, so the
+  // schedule stays the one given at fgt_batch_create.
+  return fgt::set_error(FGT_ERR_UNSUPPORTED,
+                        "fgt_batch_tune is switched off; pick the schedule in fgt_batch_opts_t");
 }
 
 int fgt_batch_info(const fgt_batch_t* b, fgt_batch_info_t* info) {

@@ -10,6 +10,9 @@ namespace fgt {
 
 constexpr int kMaxDim = 3;
 constexpr int kMaxP = 16;      // nodes per axis handled by the kernels
+// smallest tol a reduced-precision plan accepts (FGT_ERR_UNSUPPORTED below)
+constexpr double kMinTolFp32 = 1e-6 * (1 - 1e-9);
+constexpr double kMinTolBf16x3 = 1e-4 * (1 - 1e-9);
 constexpr int kMaxModes = 128; // real plane-wave modes per axis (2M-1)
 constexpr int kFormLeaves = 8; // leaves per formation work item
 constexpr double kFuseBytes = 128e6;  // psi bytes above which the 3D translation is fused

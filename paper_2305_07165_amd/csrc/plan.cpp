@@ -77,6 +77,18 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     return FGT_ERR_INVALID_ARG;
   }
   if (precision == FGT_BF16X3 && d == 1) { err = "FGT_BF16X3 needs d = 2 or 3"; return FGT_ERR_UNSUPPORTED; }
+  // reduced precision is offered only where its rounding stays below tol
+  // (measured against the FP64 oracle over whole trees): FP32 products and
+  // expansions add a relative l2 error of about 2e-7, split bf16 products
+  // about 3e-6
+  if (precision == FGT_FP32 && tol < kMinTolFp32) {
+    err = "FGT_FP32 needs tol >= 1e-6 (FP64 below)";
+    return FGT_ERR_UNSUPPORTED;
+  }
+  if (precision == FGT_BF16X3 && tol < kMinTolBf16x3) {
+    err = "FGT_BF16X3 needs tol >= 1e-4 (FGT_FP32 or FGT_FP64 below)";
+    return FGT_ERR_UNSUPPORTED;
+  }
   if (eps_internal < 0 || eps_internal >= 0.1) { err = "eps_internal must be 0 or in (0, 0.1)"; return FGT_ERR_INVALID_ARG; }
   const bool periodic = bc == FGT_PERIODIC;
 

@@ -83,3 +83,10 @@ def rel_l2(a, b) -> float:
     a = np.asarray(a).ravel()
     b = np.asarray(b).ravel()
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def max_rel(a, b) -> float:
+    """max |a - b| over max |b|: the pointwise companion of rel_l2."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))

@@ -84,7 +84,7 @@ def test_batch_equals_alone_graph_and_direct():
         b.close()
 
 
-def test_batch_rebind_and_tune():
+def test_batch_rebind_and_tuner_off():
     probs = _problems()
     plans = _plans(probs)
     sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
@@ -93,11 +93,13 @@ def test_batch_rebind_and_tune():
     us = [torch.empty_like(s) for s in sig]
     b.bind(sig, us)
     b.execute()
-    best = b.tune(reps=2)
-    info = b.info()
-    _say(f"tuned {best:.3f} ms/exec: {info}")
-    assert best > 0 and info["tuned_ms"] == best
-    # new outputs and doubled inputs after tuning: linear, and still exact per job
+    torch.cuda.synchronize()
+    # the schedule autotuner is switched off: it refuses without touching the device
+    with pytest.raises(api.FgtError) as ei:
+        b.tune(reps=2)
+    assert ei.value.code == api.FGT_ERR_UNSUPPORTED
+    assert b.info()["tuned_ms"] == 0
+    # new outputs and doubled inputs: linear, and still exact per job
     sig2 = [2.0 * s for s in sig]
     us2 = [torch.full_like(s, float("nan")) for s in sig]
     b.bind(sig2, us2)
@@ -109,10 +111,10 @@ def test_batch_rebind_and_tune():
     b.close()
 
 
-@pytest.mark.skip(reason="aborted once inside fgt_batch_tune (no GPU fault reported) while the tuner "
-                         "destroyed side streams between tunings and a plane-formation tiling was under "
-                         "trial; both are removed, and this case stays off the GPU until the abort is "
-                         "explained")
+@pytest.mark.skip(reason="the schedule autotuner aborted inside fgt_batch_tune (SIGABRT, no GPU fault "
+                         "reported) in this test, and a later version crashed a benchmark run (SIGSEGV) "
+                         "on 512 transforms; the cause is not established, so fgt_batch_tune is switched "
+                         "off and this case stays off the GPU")
 def test_batch_graph_replays_after_repeated_tuning():
     """Tuning leaves any of 1, 2 or 4 streams (a fork/join in the graph); the
     replays after each tuning, with eager work between them, stay exact."""

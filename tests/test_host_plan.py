@@ -335,6 +335,15 @@ def test_validation_errors():
     # small delta it would need more than 128 real modes
     assert mk(lv, cs, delta=0.05, periodic=True).info()["fourier"] == 1
     assert _code(lambda: mk(lv, cs, delta=1e-5, periodic=True, force_lc=0)) == _lib.FGT_ERR_UNSUPPORTED
+    # reduced precision only where its rounding stays below tol: FP32 from
+    # tol 1e-6, split bf16 products from tol 1e-4 (FP64 everywhere)
+    assert _code(lambda: mk(lv, cs, tol=1e-7, precision="fp32")) == _lib.FGT_ERR_UNSUPPORTED
+    assert _code(lambda: mk(lv, cs, tol=1e-10, precision="fp32")) == _lib.FGT_ERR_UNSUPPORTED
+    assert mk(lv, cs, tol=1e-6, precision="fp32").info()["precision"] == _lib.FGT_FP32
+    assert _code(lambda: mk(lv, cs, tol=1e-6, precision="bf16x3")) == _lib.FGT_ERR_UNSUPPORTED
+    assert _code(lambda: mk(lv, cs, tol=5e-5, precision="bf16x3")) == _lib.FGT_ERR_UNSUPPORTED
+    assert mk(lv, cs, tol=1e-4, precision="bf16x3").info()["precision"] == _lib.FGT_BF16X3
+    assert mk(lv, cs, tol=1e-10, precision="fp64").info()["precision"] == _lib.FGT_FP64
     # a valid plan works
     assert mk(lv, cs).info()["nleaves"] == 16
     assert ok
