@@ -136,6 +136,23 @@ int fgt_plan(const fgt_tree_t* tree, int p, double delta, double tol, int bc,
  */
 int fgt_execute(fgt_plan_t* plan, const double* sigma_dev, double* u_dev);
 
+/*
+ * For callers that cannot allocate device memory at execution time (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): fgt_execute with the workspace (plane intermediates, expansions,
+ * partial sums) taken from a static device array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends, instead of the plan's
+ * own workspace.  Allocates nothing and calls no allocating routine; results
+ * are bitwise those of fgt_execute.  Returns FGT_ERR_UNSUPPORTED, without
+ * enqueuing anything, when the plan's workspace exceeds 64 MiB (small and
+ * medium trees fit; the 3D p = 16 trees of millions of points do not).  All
+ * calls on one GPU share that array, and it keeps the last call's contents:
+ * calls that may overlap on one GPU (plans on different streams, or from
+ * different threads) race and must be ordered by the caller.  Asynchronous on
+ * the plan's stream, like fgt_execute.
+ */
+int fgt_execute_noalloc(fgt_plan_t* plan, const double* sigma_dev, double* u_dev);
+
 /* Waits for the plan's stream.  Returns FGT_ERR_HIP if queued work failed. */
 int fgt_sync(fgt_plan_t* plan);
 

@@ -25,7 +25,7 @@ FGT_FP64 = 0
 FGT_FP32 = 1
 FGT_BF16X3 = 2
 
-EXPORTED = ["fgt_plan", "fgt_execute", "fgt_sync", "fgt_plan_info", "fgt_stage_times",
+EXPORTED = ["fgt_plan", "fgt_execute", "fgt_execute_noalloc", "fgt_sync", "fgt_plan_info", "fgt_stage_times",
             "fgt_destroy", "fgt_strerror", "fgt_last_error", "fgt_pw_terms",
             "fgt_periodic_terms", "fgt_plan_array",
             "fgt_server_create", "fgt_server_submit", "fgt_server_poll", "fgt_server_wait",
@@ -184,6 +184,8 @@ def lib():
                                ctypes.POINTER(vp)]
         L.fgt_execute.restype = ctypes.c_int
         L.fgt_execute.argtypes = [vp, vp, vp]
+        L.fgt_execute_noalloc.restype = ctypes.c_int
+        L.fgt_execute_noalloc.argtypes = [vp, vp, vp]
         L.fgt_sync.restype = ctypes.c_int
         L.fgt_sync.argtypes = [vp]
         L.fgt_plan_info.restype = ctypes.c_int

@@ -64,6 +64,10 @@ def fgt_execute(plan: int, sigma, u) -> None:
     check(_lib.lib().fgt_execute(plan, _ptr(sigma), _ptr(u)), "fgt_execute")
 
 
+def fgt_execute_noalloc(plan: int, sigma, u) -> None:
+    check(_lib.lib().fgt_execute_noalloc(plan, _ptr(sigma), _ptr(u)), "fgt_execute_noalloc")
+
+
 def fgt_sync(plan: int) -> None:
     check(_lib.lib().fgt_sync(plan), "fgt_sync")
 
@@ -140,6 +144,11 @@ class Plan:
         if u is None:
             import torch
             u = torch.empty_like(sigma)
+        self._check_io(sigma, u)
+        fgt_execute(self.handle, sigma, u)
+        return u
+
+    def _check_io(self, sigma, u):
         expect = (self.nleaves, self.p ** self.dim)
         for name, t in (("sigma", sigma), ("u", u)):
             if hasattr(t, "shape"):
@@ -151,7 +160,12 @@ class Plan:
                     raise ValueError(f"{name} must be a device tensor")
                 if hasattr(t, "is_contiguous") and not t.is_contiguous():
                     raise ValueError(f"{name} must be contiguous")
-        fgt_execute(self.handle, sigma, u)
+
+    def execute_noalloc(self, sigma, u):
+        """fgt_execute_noalloc: the workspace comes from the library's static
+        device scratch; u must be given (nothing is allocated)."""
+        self._check_io(sigma, u)
+        fgt_execute_noalloc(self.handle, sigma, u)
         return u
 
     def sync(self):

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -241,20 +242,15 @@ int fgt::plan_unload(fgt_plan_t* pl) {
   return FGT_OK;
 }
 
-int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem) {
-  if (!pl || pl->host_only || !args || !mem) return fail(FGT_ERR_INVALID_ARG, "plan is not resident");
-  const fgt::HostPlan& hp = pl->hp;
+// Lays the workspace arrays (Y, phi, psi unless fused away, partial sums) out
+// from base, each on a 256-byte boundary, in plan_workspace_bytes(hp) bytes.
+static void carve_workspace(const fgt::HostPlan& hp, void* base, fgt::DeviceArgs* args) {
   const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
-  const int64_t bytes = plan_workspace_bytes(hp);
-  void* m = nullptr;
-  hipError_t e = hipMalloc(&m, (size_t)std::max<int64_t>(bytes, 256));
-  if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(FGT_ERR_OOM, "workspace") : hip_fail(e, "hipMalloc");
   int64_t n2 = 1;
   for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
   const int64_t ncoef = n2 * hp.nr, round = 256 / ts;
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
-  char* c = static_cast<char*>(m);
-  *args = pl->args;
+  char* c = static_cast<char*>(base);
   args->Y = c;
   c += ts * up((hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : hp.n_pwleaf())) * hp.p * n2);
   args->phi = c;
@@ -262,6 +258,16 @@ int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem
   args->psi = hp.fuse_te ? nullptr : c;
   if (!hp.fuse_te) c += ts * up(hp.n_pwbox() * ncoef);
   args->partial = c;
+}
+
+int fgt::plan_alloc_workspace(const fgt_plan_t* pl, DeviceArgs* args, void** mem) {
+  if (!pl || pl->host_only || !args || !mem) return fail(FGT_ERR_INVALID_ARG, "plan is not resident");
+  const int64_t bytes = plan_workspace_bytes(pl->hp);
+  void* m = nullptr;
+  hipError_t e = hipMalloc(&m, (size_t)std::max<int64_t>(bytes, 256));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(FGT_ERR_OOM, "workspace") : hip_fail(e, "hipMalloc");
+  *args = pl->args;
+  carve_workspace(pl->hp, m, args);
   *mem = m;
   return FGT_OK;
 }
@@ -272,6 +278,38 @@ int fgt::execute_args(const DeviceArgs& a, const double* sigma, double* u, hipSt
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return FGT_OK;
 }
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Static scratch of fgt_execute_noalloc: one file-scope device array per GPU
+// (each device holds its own copy at its own address until the process ends).
+// Host code never uses the array's name as an address: the device address is
+// looked up once per device with that device current, and kept.
+constexpr int64_t kScratchBytes = int64_t(64) << 20;
+constexpr int kScratchDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// The device address of `scratch` on `device`, which must be current.
+int scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kScratchDevices)
+    return fail(FGT_ERR_UNSUPPORTED, "device ordinal beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(FGT_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return FGT_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -321,6 +359,29 @@ int fgt_execute(fgt_plan_t* pl, const double* sigma, double* u) {
   hipError_t e = hipSetDevice(pl->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   e = fgt::launch_transform(pl->args, sigma, u, pl->stream, pl->profile ? pl->ev : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return FGT_OK;
+}
+
+int fgt_execute_noalloc(fgt_plan_t* pl, const double* sigma, double* u) {
+  if (!pl) return fail(FGT_ERR_INVALID_ARG, "plan is NULL");
+  if (pl->host_only) return fail(FGT_ERR_INVALID_ARG, "host-only plan cannot execute");
+  if (!sigma || !u) return fail(FGT_ERR_INVALID_ARG, "sigma/u is NULL");
+  const int64_t need = fgt::plan_workspace_bytes(pl->hp);
+  if (need > kScratchBytes)
+    return fail(FGT_ERR_UNSUPPORTED, "plan workspace of " + std::to_string(need) +
+                                         " bytes exceeds the static scratch of " + std::to_string(kScratchBytes) +
+                                         " bytes (fgt_execute uses the plan's own workspace)");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  void* base = nullptr;
+  const int rc = scratch_address(pl->device, &base);
+  if (rc != FGT_OK) return rc;
+  // every word the kernels read from the workspace is written earlier in the
+  // same execution, so the scratch needs no clearing
+  fgt::DeviceArgs a = pl->args;
+  carve_workspace(pl->hp, base, &a);
+  e = fgt::launch_transform(a, sigma, u, pl->stream, pl->profile ? pl->ev : nullptr);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return FGT_OK;
 }
