@@ -106,6 +106,9 @@ typedef struct fgt_info {
                             periodic kernel's truncated Fourier series on the root
                             (Sections 2.2 and 5): lc = 0, nr = 2 n_p + 1, R = 0,
                             h = 2 pi sqrt(delta), no near field */
+  int32_t nr_stored;     /* modes stored per axis, 2M = nr + 1: mode m's (cos, sin) pair at
+                            2m, 2m+1, the constant at 0 and an exact zero at 1; the stride
+                            of the "F" and "E" arrays and of every expansion */
 } fgt_info_t;
 
 typedef struct fgt_plan fgt_plan_t;
@@ -188,7 +191,8 @@ int fgt_periodic_terms(double eps, double delta);
 
 /*
  * Copies a host-side array of a plan (host-only or full) for inspection:
- * name is one of "F", "E", "V", "rot" (double) or "pwbox_isleaf", "pw_start",
+ * name is one of "F" ([table][nr_stored][p]), "E" ([table][p][nr_stored]),
+ * "V", "rot" (double) or "pwbox_isleaf", "pw_start",
  * "pwleaf_id", "pwleaf_tab", "pwleaf_box", "box_order", "plist_start",
  * "plist_src", "plist_dir", "echunk", "fitem", "fred", "near_tgt",
  * "near_haspw", "near_start", "near_src", "near_tab", "ftab_meta", "vtab_meta",

@@ -67,7 +67,8 @@ class fgt_info_t(ctypes.Structure):
                 ("bytes_min", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("n_plane", ctypes.c_int64), ("n_row", ctypes.c_int64),
                 ("n_near_source", ctypes.c_int64), ("n_near_haspw", ctypes.c_int64),
-                ("fused_translate", ctypes.c_int32), ("fourier", ctypes.c_int32)]
+                ("fused_translate", ctypes.c_int32), ("fourier", ctypes.c_int32),
+                ("nr_stored", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -85,9 +85,6 @@ double ipowd(double b, int e) {
 
 int64_t fgt::plan_device_bytes(const HostPlan& hp) {
   const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
-  int64_t n2 = 1;
-  for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
-  const int64_t ncoef = n2 * hp.nr;
   int64_t b = ts * (int64_t)(hp.F.size() + hp.E.size() + hp.V.size() + hp.rot.size());
   for (const std::vector<int32_t>* v : {&hp.pw_start, &hp.pwleaf_id, &hp.pwleaf_tab, &hp.pwleaf_box,
                                         &hp.box_order, &hp.plist_start, &hp.plist_src, &hp.plist_dir,
@@ -101,8 +98,8 @@ int64_t fgt::plan_device_bytes(const HostPlan& hp) {
 int64_t fgt::plan_workspace_bytes(const HostPlan& hp) {
   const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
   int64_t n2 = 1;
-  for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
-  const int64_t ncoef = n2 * hp.nr;
+  for (int a = 1; a < hp.d; a++) n2 *= hp.nrs;
+  const int64_t ncoef = n2 * hp.nrs;
   const int64_t round = 256 / ts;  // each array starts on a 256-byte boundary
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
   const int64_t nU = hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : hp.n_pwleaf());
@@ -121,15 +118,15 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   int lds_max = 0;
   e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-  size_t need = std::max(fgt::lds_form_leaf(hp.d, hp.p, hp.nr, ts),
-                         std::max(fgt::lds_eval_leaf(hp.d, hp.p, hp.nr, ts), fgt::lds_near(hp.d, hp.p, ts)));
+  size_t need = std::max(fgt::lds_form_leaf(hp.d, hp.p, hp.nrs, ts),
+                         std::max(fgt::lds_eval_leaf(hp.d, hp.p, hp.nrs, ts), fgt::lds_near(hp.d, hp.p, ts)));
   if (need > (size_t)lds_max)
     return fail(FGT_ERR_UNSUPPORTED, "stage needs " + std::to_string(need) + " bytes of LDS, device allows " +
                                          std::to_string(lds_max));
   fgt::DeviceArgs& a = pl->args;
   a.d = hp.d;
   a.p = hp.p;
-  a.nr = hp.nr;
+  a.nr = hp.nrs;  // the kernels see the stored modes
   a.M = hp.pw.M;
   a.fp32 = fp32;
   a.bf3 = hp.precision == FGT_BF16X3;
@@ -159,8 +156,8 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
       (rc = upload_i32(pl, hp.row_start, &a.row_start)) || (rc = upload_i32(pl, hp.row_tab, &a.row_tab)))
     return rc;
   a.nPl = hp.n_plane();
-  const size_t n2 = (size_t)ipowd(hp.nr, hp.d - 1);
-  const size_t ncoef = n2 * hp.nr;
+  const size_t n2 = (size_t)ipowd(hp.nrs, hp.d - 1);
+  const size_t ncoef = n2 * hp.nrs;
   // the intermediate: per plane for d = 3, none for d = 2 (both axes fused), per leaf for d = 1
   const int64_t nU = hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : a.nL);
   // no psi when the translation is fused with the first evaluation step
@@ -247,8 +244,8 @@ int fgt::plan_unload(fgt_plan_t* pl) {
 static void carve_workspace(const fgt::HostPlan& hp, void* base, fgt::DeviceArgs* args) {
   const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
   int64_t n2 = 1;
-  for (int a = 1; a < hp.d; a++) n2 *= hp.nr;
-  const int64_t ncoef = n2 * hp.nr, round = 256 / ts;
+  for (int a = 1; a < hp.d; a++) n2 *= hp.nrs;
+  const int64_t ncoef = n2 * hp.nrs, round = 256 / ts;
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
   char* c = static_cast<char*>(base);
   args->Y = c;
@@ -421,6 +418,7 @@ int fgt_plan_info(const fgt_plan_t* pl, fgt_info_t* info) {
   info->lmax = hp.lmax;
   info->nf = 2 * hp.pw.M;
   info->nr = hp.nr;
+  info->nr_stored = hp.nrs;
   info->delta = hp.delta;
   info->tol = hp.tol;
   info->eps = hp.pw.eps;

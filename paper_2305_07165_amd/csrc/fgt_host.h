@@ -13,7 +13,7 @@ constexpr int kMaxP = 16;      // nodes per axis handled by the kernels
 // smallest tol a reduced-precision plan accepts (FGT_ERR_UNSUPPORTED below)
 constexpr double kMinTolFp32 = 1e-6 * (1 - 1e-9);
 constexpr double kMinTolBf16x3 = 1e-4 * (1 - 1e-9);
-constexpr int kMaxModes = 128; // real plane-wave modes per axis (2M-1)
+constexpr int kMaxModes = 128; // stored plane-wave modes per axis (2M)
 constexpr int kFormLeaves = 8; // leaves per formation work item
 constexpr double kFuseBytes = 128e6;  // psi bytes above which the 3D translation is fused
 
@@ -42,6 +42,9 @@ struct HostPlan {
   double Llc = 1;      // side of a cutoff-level box
   PwParams pw;         // eps, D0, R, h, M
   int nr = 0;          // real modes per axis, 2M-1
+  int nrs = 0;         // stored modes per axis, 2M: every expansion, table and
+                       // intermediate stores mode m's (cos, sin) pair at 2m, 2m+1,
+                       // the constant mode at 0 and a zero at 1 (the sin of m = 0)
   double sqrt_delta = 0;
   // periodic with l_c <= 1: the root's Fourier series (lc = 0, h = 2 pi
   // sqrt(delta), M = n_p + 1, identity translation, no near field)
@@ -92,8 +95,8 @@ struct HostPlan {
   int nftab = 0, nvtab = 0;
   std::vector<int32_t> ftab_meta;     // [2*nftab] level of each form/eval table, then its position
   std::vector<int32_t> vtab_meta;     // [2*nvtab] source level of each near table, then its type (0..10)
-  std::vector<double> F;              // [nftab][nr][p]  leaf values -> cutoff-box pw moments
-  std::vector<double> E;              // [nftab][p][nr]  cutoff-box pw moments -> leaf values
+  std::vector<double> F;              // [nftab][nrs][p]  leaf values -> cutoff-box pw moments
+  std::vector<double> E;              // [nftab][p][nrs]  cutoff-box pw moments -> leaf values
   std::vector<double> V;              // [nvtab][p][p]   source values -> target values
   std::vector<double> rot;            // [M][2]  cos, sin of k_m * Llc
 

@@ -191,9 +191,12 @@ __global__ __launch_bounds__(256) void k_form_box(const T* __restrict__ Y,
 
 // ---------------------------------------------------------------------------
 // translate: psi_A = sum_{(B,dir) in P(A)} Rot(dir * L_c) phi_B.  One thread per
-// mode multi-index (m_1..m_d); it owns the 2^#(m_a>0) (cos/sin) coefficients.
+// mode multi-index (m_1..m_d); it owns the 2^d coefficients 2 m_a + v_a
+// (v_a = 0: cos, 1: sin; for m_a = 0 the constant and the stored zero, which a
+// shift leaves alone since rot of mode 0 is the identity).
 // R2F: the tensors are stored [r3][r1][r2] (r2 fastest, the d = 3 layout of
-// kernels_fast.hip) instead of [r3][r2][r1]; threads then run along m_2.
+// kernels_fast.hip) instead of [r3][r2][r1]; threads then run along m_2.  The
+// pair along the fastest-stored axis is one aligned two-element vector.
 
 template <typename T, int D, bool R2F>
 __device__ __forceinline__ void translate_body(const T* __restrict__ phi,
@@ -202,6 +205,7 @@ __device__ __forceinline__ void translate_body(const T* __restrict__ phi,
                                                const int32_t* __restrict__ plist_dir,
                                                const T* __restrict__ rot, int M, int nr, int nA,
                                                T* __restrict__ psi, int bid) {
+  typedef typename Pair2<T>::type T2;
   // Chunks of modes are dealt to the XCDs: XCD x sweeps every target box (in
   // Morton order) for chunks x, x + 8, ..., so each source slice of those
   // chunks is fetched into one L2 and reused by all its targets there; the
@@ -236,24 +240,33 @@ __device__ __forceinline__ void translate_body(const T* __restrict__ phi,
       for (int a = 0; a < D; a++) { m[a] = q % M; q /= M; }
     }
   }
-  // coefficient indices of this block: idx[a][0] = cos (or the single m = 0 mode), idx[a][1] = sin
-  int ix[3][2], cnt[3];
-  for (int a = 0; a < 3; a++) {
-    if (a < D && m[a] > 0) { ix[a][0] = 2 * m[a] - 1; ix[a][1] = 2 * m[a]; cnt[a] = 2; }
-    else { ix[a][0] = 0; ix[a][1] = 0; cnt[a] = 1; }
-  }
+  constexpr int FA = R2F ? 1 : 0;  // the axis stored fastest
+  constexpr int NV = 1 << D, NW = NV / 2;
   const int64_t stride[3] = {R2F ? nr : 1, R2F ? 1 : nr, (int64_t)nr * nr};
-  int64_t off[8];
-  int nv = 0;
-  constexpr int NV = 1 << D;
-  for (int v = 0; v < NV; v++) {
-    int c0 = v & 1, c1 = (v >> 1) & 1, c2 = (v >> 2) & 1;
-    int64_t o = stride[0] * ix[0][c0];
-    if (D > 1) o += stride[1] * ix[1][c1];
-    if (D > 2) o += stride[2] * ix[2][c2];
-    off[v] = o;
-    nv++;
+  // off[w]: the pair (v_FA = 0, 1) of coefficient v = spread(w), where w runs
+  // over the cos/sin choices of the other axes
+  int64_t off[NW];
+#pragma unroll
+  for (int w = 0; w < NW; w++) {
+    int64_t o = stride[FA] * (2 * m[FA]);
+    int bit = 0;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+      if (a == FA) continue;
+      o += stride[a] * (2 * m[a] + ((w >> bit) & 1));
+      bit++;
+    }
+    off[w] = o;
   }
+  auto vidx = [](int w, int vf) {  // coefficient v (bit a = sin member of axis a)
+    int v = vf << FA, bit = 0;
+    for (int a = 0; a < D; a++) {
+      if (a == FA) continue;
+      v |= ((w >> bit) & 1) << a;
+      bit++;
+    }
+    return v;
+  };
   T cs[3], sn[3];
   for (int a = 0; a < D; a++) { cs[a] = rot[2 * m[a]]; sn[a] = rot[2 * m[a] + 1]; }
   int64_t ncoef = nr;
@@ -262,58 +275,78 @@ __device__ __forceinline__ void translate_body(const T* __restrict__ phi,
 #pragma unroll
   for (int v = 0; v < NV; v++) acc[v] = 0;
   const int q0 = plist_start[A], q1 = plist_start[A + 1];
-  bool present[NV];
-#pragma unroll
-  for (int v = 0; v < NV; v++) {
-    present[v] = !((cnt[0] == 1 && (v & 1)) || (D > 1 && cnt[1] == 1 && ((v >> 1) & 1)) ||
-                   (D > 2 && cnt[2] == 1 && ((v >> 2) & 1)));
-  }
   // two sources in flight: the loads of source q+1 are issued before the
-  // rotations of source q
+  // rotations of source q (a q past the list reloads the last source)
   auto fetch = [&](int q, T (&x)[NV]) {
-    const bool okq = q < q1;
-    const T* src = phi + (int64_t)(okq ? plist_src[q] : 0) * ncoef;
+    const T* src = phi + (int64_t)plist_src[min(q, q1 - 1)] * ncoef;
 #pragma unroll
-    for (int v = 0; v < NV; v++) x[v] = ld0<T>(src, off[v], okq && present[v]);
+    for (int w = 0; w < NW; w++) {
+      const T2 v2 = *reinterpret_cast<const T2*>(src + off[w]);
+      x[vidx(w, 0)] = v2.x;
+      x[vidx(w, 1)] = v2.y;
+    }
   };
+  // rotations along every axis the source is displaced on; the last one adds
+  // straight into the accumulators
   auto apply = [&](int q, T (&x)[NV]) {
     int code = plist_dir[q];
+    int dir[3] = {0, 0, 0};
+    int last = -1;
 #pragma unroll
     for (int a = 0; a < D; a++) {
-      const int dir = code % 3 - 1;
+      dir[a] = code % 3 - 1;
       code /= 3;
-      if (dir == 0 || m[a] == 0) continue;
-      const T c = cs[a], s = dir > 0 ? sn[a] : -sn[a];
-      const int bit = 1 << a;
-#pragma unroll
-      for (int v = 0; v < NV; v++) {
-        if (v & bit) continue;
-        const T xc = x[v], xs = x[v | bit];
-        x[v] = c * xc - s * xs;
-        x[v | bit] = s * xc + c * xs;
-      }
+      if (dir[a] != 0) last = a;
     }
 #pragma unroll
-    for (int v = 0; v < NV; v++) acc[v] += x[v];
+    for (int a = 0; a < D; a++) {
+      if (dir[a] == 0) continue;
+      const T c = cs[a], s = dir[a] > 0 ? sn[a] : -sn[a];
+      const int bit = 1 << a;
+      if (a == last) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          if (v & bit) continue;
+          const T xc = x[v], xs = x[v | bit];
+          acc[v] = fma(c, xc, acc[v]);
+          acc[v] = fma(-s, xs, acc[v]);
+          acc[v | bit] = fma(s, xc, acc[v | bit]);
+          acc[v | bit] = fma(c, xs, acc[v | bit]);
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          if (v & bit) continue;
+          const T xc = x[v], xs = x[v | bit];
+          x[v] = c * xc - s * xs;
+          x[v | bit] = s * xc + c * xs;
+        }
+      }
+    }
+    if (last < 0) {
+#pragma unroll
+      for (int v = 0; v < NV; v++) acc[v] += x[v];
+    }
   };
   T xa[NV], xb[NV];
-  fetch(q0, xa);
-  for (int q = q0; q < q1; q += 2) {
-    fetch(q + 1, xb);
-    apply(q, xa);
-    if (q + 1 < q1) {
-      fetch(q + 2, xa);
-      apply(q + 1, xb);
+  if (q0 < q1) {
+    fetch(q0, xa);
+    for (int q = q0; q < q1; q += 2) {
+      fetch(q + 1, xb);
+      apply(q, xa);
+      if (q + 1 < q1) {
+        fetch(q + 2, xa);
+        apply(q + 1, xb);
+      }
     }
   }
   T* dst = psi + (int64_t)A * ncoef;
 #pragma unroll
-  for (int v = 0; v < NV; v++) {
-    bool ok = true;
-    if (cnt[0] == 1 && (v & 1)) ok = false;
-    if (D > 1 && cnt[1] == 1 && ((v >> 1) & 1)) ok = false;
-    if (D > 2 && cnt[2] == 1 && ((v >> 2) & 1)) ok = false;
-    if (ok) dst[off[v]] = acc[v];
+  for (int w = 0; w < NW; w++) {
+    T2 v2;
+    v2.x = acc[vidx(w, 0)];
+    v2.y = acc[vidx(w, 1)];
+    *reinterpret_cast<T2*>(dst + off[w]) = v2;
   }
 }
 

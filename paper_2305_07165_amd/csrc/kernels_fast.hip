@@ -281,23 +281,24 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 // ---------------------------------------------------------------------------
 // d = 3 out->in translation fused with the first evaluation contraction.
 // A workgroup owns one cutoff box A and one tile of mode columns (r1, r2):
-// the r1 pair of one axis-1 mode m1 times the r2 pairs of a run of axis-2
-// modes -- all of them, whole contiguous rows, up to 96 columns -- so every
-// (cos, sin) partner is inside the tile.  Phase 1 gathers psi_A[r3][tile] = sum_{B in P(A)} Rot(c_B - c_A)
-// phi_B[r3][tile] into LDS (a thread owns the 2 x 2 x 2 coefficients of one
-// (m3, m2) unit, as in the plain translation); phase 2 contracts it with the
-// axis-3 evaluation table of every plane of A, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
+// the stored pair r1 = 2 m1, 2 m1 + 1 of one axis-1 mode m1 times the pairs of
+// a run of axis-2 modes -- all of them, whole rows, while they fit in 64
+// columns -- so every (cos, sin) partner is inside the tile.  Phase 1 gathers
+// psi_A[r3][tile] = sum_{B in P(A)} Rot(c_B - c_A) phi_B[r3][tile] into LDS (a
+// thread owns the 2 x 2 x 2 coefficients of one (m3, m2) unit: four aligned
+// pairs along r2, loaded as vectors); phase 2 contracts it with the axis-3
+// evaluation table of every plane of A, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
 // psi_A[r3][c], 16-column groups spread over the waves.  psi never goes to HBM.
 
-// axis-2 modes per tile: all of them (whole contiguous r2 rows) while the tile
-// stays within 96 columns; else at most 16 with M * modes <= 256
+// axis-2 modes per tile: all of them (whole r2 rows) while 2M <= 64; else at
+// most 16 with M * modes <= 256
 __host__ __device__ inline int transeval_modes(int M) {
   if (M <= 32) return M;
   return M <= 16 ? 16 : (256 / M > 0 ? 256 / M : 1);
 }
 
 // LDS of the psi tile: nr rows of LDW = 2 nr + 1 columns (odd, to spread the
-// banks; a tile holds at most 2 nr columns since fused plans have M <= 32)
+// banks; a tile holds at most 2 nr columns since fused plans have 2M <= 64)
 __host__ __device__ inline int transeval_ldw(int nr) { return 2 * nr + 1; }
 inline size_t transeval_lds(int nr, size_t ts) { return (size_t)nr * transeval_ldw(nr) * ts; }
 
@@ -313,6 +314,7 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
                                                 int nr, int nA, elem_t<C>* __restrict__ Z,
                                                 elem_t<C>* __restrict__ ps, int bid) {
   typedef elem_t<C> T;
+  typedef typename Pair2<T>::type T2;
   typedef Mfma<C> M_;
   typedef typename M_::acc acc_t;
   constexpr int Q = 4 * NT;
@@ -340,10 +342,9 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
   if (A >= nA || tile >= ntile) return;  // whole workgroup
   const int m1 = tile / nb2, b2 = tile - m1 * nb2;
   const int mlo = b2 * TM, mhi = min(M, mlo + TM), nm2 = mhi - mlo;
-  const int n1 = m1 > 0 ? 2 : 1;
-  const int r2first = mlo > 0 ? 2 * mlo - 1 : 0;
-  const int n2 = 2 * nm2 - (mlo == 0 ? 1 : 0);  // r2 columns of the tile
-  const int ncol = n1 * n2;
+  const int r2first = 2 * mlo;
+  const int n2 = 2 * nm2;  // r2 columns of the tile
+  const int ncol = 2 * n2;
   const int64_t nr2 = (int64_t)nr * nr, ncoef = nr2 * nr;
   const int tid = threadIdx.x;
   // ---- phase 1: translations into LDS
@@ -353,71 +354,80 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
     const int m3 = unit / nm2, m2 = mlo + (unit - (unit / nm2) * nm2);
     const T cs2 = rot[2 * m2], sn2 = rot[2 * m2 + 1];
     const T cs3 = rot[2 * m3], sn3 = rot[2 * m3 + 1];
-    // coefficient v = v1 + 2 v2 + 4 v3 (bit a: sin member of the axis pair)
-    int64_t off[8];
-    bool present[8];
+    // coefficient v = v1 + 2 v2 + 4 v3 (bit a: sin member of the axis pair);
+    // pair w = v1 + 2 v3 holds v2 = 0, 1 at off[w], off[w] + 1
+    int off[4];
 #pragma unroll
-    for (int v = 0; v < 8; v++) {
-      const int v1 = v & 1, v2 = (v >> 1) & 1, v3 = v >> 2;
-      present[v] = (v1 == 0 || m1 > 0) && (v2 == 0 || m2 > 0) && (v3 == 0 || m3 > 0);
-      const int c1 = m1 > 0 ? 2 * m1 - 1 + v1 : 0;
-      const int c2 = m2 > 0 ? 2 * m2 - 1 + v2 : 0;
-      const int c3 = m3 > 0 ? 2 * m3 - 1 + v3 : 0;
-      off[v] = c3 * nr2 + (int64_t)c1 * nr + c2;
+    for (int w = 0; w < 4; w++) {
+      const int v1 = w & 1, v3 = w >> 1;
+      off[w] = (2 * m3 + v3) * (int)nr2 + (2 * m1 + v1) * nr + 2 * m2;
     }
     T acc[8];
 #pragma unroll
     for (int v = 0; v < 8; v++) acc[v] = 0;
     auto fetch = [&](int q, T (&x)[8]) {
-      const bool okq = q < q1;
-      const T* src = phi + (int64_t)(okq ? plist_src[q] : 0) * ncoef;
+      const T* src = phi + (int64_t)plist_src[min(q, q1 - 1)] * ncoef;
 #pragma unroll
-      for (int v = 0; v < 8; v++) x[v] = ld0<T>(src, off[v], okq && present[v]);
+      for (int w = 0; w < 4; w++) {
+        const T2 v2 = *reinterpret_cast<const T2*>(src + off[w]);
+        const int v = (w & 1) | ((w >> 1) << 2);
+        x[v] = v2.x;
+        x[v | 2] = v2.y;
+      }
     };
-    auto rotate = [](T c, T s, T& xc, T& xs) {
-      const T a = xc, b = xs;
-      xc = c * a - s * b;
-      xs = s * a + c * b;
-    };
+    // rotations along every displaced axis; the last one adds straight into acc
     auto apply = [&](int q, T (&x)[8]) {
       const int code = plist_dir[q];
       const int d1 = code % 3 - 1, d2 = (code / 3) % 3 - 1, d3 = code / 9 - 1;
-      if (d1 != 0 && m1 > 0) {
-        const T s = d1 > 0 ? sn1 : -sn1;
+      const int last = d3 != 0 ? 2 : (d2 != 0 ? 1 : (d1 != 0 ? 0 : -1));
+      const T c[3] = {cs1, cs2, cs3};
+      const T s[3] = {d1 > 0 ? sn1 : -sn1, d2 > 0 ? sn2 : -sn2, d3 > 0 ? sn3 : -sn3};
+      const int dd[3] = {d1, d2, d3};
 #pragma unroll
-        for (int v = 0; v < 8; v += 2) rotate(cs1, s, x[v], x[v + 1]);
+      for (int a = 0; a < 3; a++) {
+        if (dd[a] == 0) continue;
+        const int bit = 1 << a;
+        if (a == last) {
+#pragma unroll
+          for (int v = 0; v < 8; v++) {
+            if (v & bit) continue;
+            const T xc = x[v], xs = x[v | bit];
+            acc[v] = fma(c[a], xc, acc[v]);
+            acc[v] = fma(-s[a], xs, acc[v]);
+            acc[v | bit] = fma(s[a], xc, acc[v | bit]);
+            acc[v | bit] = fma(c[a], xs, acc[v | bit]);
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 8; v++) {
+            if (v & bit) continue;
+            const T xc = x[v], xs = x[v | bit];
+            x[v] = c[a] * xc - s[a] * xs;
+            x[v | bit] = s[a] * xc + c[a] * xs;
+          }
+        }
       }
-      if (d2 != 0 && m2 > 0) {
-        const T s = d2 > 0 ? sn2 : -sn2;
+      if (last < 0) {
 #pragma unroll
-        for (int v = 0; v < 8; v++)
-          if (!(v & 2)) rotate(cs2, s, x[v], x[v + 2]);
+        for (int v = 0; v < 8; v++) acc[v] += x[v];
       }
-      if (d3 != 0 && m3 > 0) {
-        const T s = d3 > 0 ? sn3 : -sn3;
-#pragma unroll
-        for (int v = 0; v < 4; v++) rotate(cs3, s, x[v], x[v + 4]);
-      }
-#pragma unroll
-      for (int v = 0; v < 8; v++) acc[v] += x[v];
     };
     T xa[8], xb[8];
-    fetch(q0, xa);
-    for (int q = q0; q < q1; q += 2) {
-      fetch(q + 1, xb);
-      apply(q, xa);
-      if (q + 1 < q1) {
-        fetch(q + 2, xa);
-        apply(q + 1, xb);
+    if (q0 < q1) {
+      fetch(q0, xa);
+      for (int q = q0; q < q1; q += 2) {
+        fetch(q + 1, xb);
+        apply(q, xa);
+        if (q + 1 < q1) {
+          fetch(q + 2, xa);
+          apply(q + 1, xb);
+        }
       }
     }
 #pragma unroll
     for (int v = 0; v < 8; v++) {
-      if (!present[v]) continue;
       const int v1 = v & 1, v2 = (v >> 1) & 1, v3 = v >> 2;
-      const int r3 = m3 > 0 ? 2 * m3 - 1 + v3 : 0;
-      const int r2 = m2 > 0 ? 2 * m2 - 1 + v2 : 0;
-      ps[r3 * LDW + v1 * n2 + (r2 - r2first)] = acc[v];
+      ps[(2 * m3 + v3) * LDW + v1 * n2 + (2 * (m2 - mlo) + v2)] = acc[v];
     }
   }
   __syncthreads();
@@ -435,7 +445,7 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
     b[q] = k < nr && colok ? v : (T)0;
   }
   const int i1 = col < n2 ? 0 : 1;
-  const int r1 = m1 > 0 ? 2 * m1 - 1 + i1 : 0;
+  const int r1 = 2 * m1 + i1;
   const int r2 = r2first + col - i1 * n2;
   const int64_t cglob = (int64_t)r1 * nr + r2;
   const int P0 = plane_start[A], P1 = plane_start[A + 1];

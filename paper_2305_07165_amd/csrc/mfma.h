@@ -116,6 +116,12 @@ __device__ __forceinline__ T ld0(const S* __restrict__ base, int64_t idx, bool o
   return ok ? (T)v : (T)0;
 }
 
+// The two-element vector of a storage type: a stored (cos, sin) mode pair,
+// which starts at an even index, is one aligned vector load or store.
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { typedef double2 type; };
+template <> struct Pair2<float> { typedef float2 type; };
+
 template <typename A> __device__ __forceinline__ void zero4(A& a) {
   a[0] = 0;
   a[1] = 0;

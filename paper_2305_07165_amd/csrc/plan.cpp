@@ -214,7 +214,8 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     hp.pw = pw_params(eps, R);
   }
   hp.nr = 2 * hp.pw.M - 1;
-  if (hp.nr > kMaxModes) { err = "too many plane-wave modes for this build (nr > 128)"; return FGT_ERR_UNSUPPORTED; }
+  hp.nrs = 2 * hp.pw.M;
+  if (hp.nrs > kMaxModes) { err = "too many plane-wave modes for this build (2M > 128)"; return FGT_ERR_UNSUPPORTED; }
 
   // ---- cutoff-level boxes and f-flags (Definition fflagdef)
   struct LcBox { int32_t c[3]; int isleaf; int f; int32_t idx; };
@@ -346,7 +347,7 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     // four mode tiles); with wider tiles its tile shape reads phi less
     // contiguously than the plain translation and the pair of kernels is faster
     const double ts = precision == FGT_FP64 ? 8.0 : 4.0;
-    hp.fuse_te = allow_fuse && hp.nr <= 64 && ts * nA * (double)hp.nr * hp.nr * hp.nr > kFuseBytes;
+    hp.fuse_te = allow_fuse && hp.nrs <= 64 && ts * nA * (double)hp.nrs * hp.nrs * hp.nrs > kFuseBytes;
   }
   // the units the box-level stages run over: planes for d = 3, leaves otherwise
   const std::vector<int32_t>& unit_start = d == 3 ? hp.plane_start : hp.pw_start;

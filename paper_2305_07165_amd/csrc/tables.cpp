@@ -14,6 +14,11 @@
 // expansion center is a 2x2 rotation of each (cos, sin) pair, the real form of
 // the diagonal translations T_{c->p}, T_{out->in}, T_{p->c}.
 //
+// Storage order of the modes (nrs = 2M per axis): b_0 at 0, a zero at 1, and
+// the pair (cos, sin) of mode m at (2m, 2m+1).  The zero row of F and column
+// of E make the stored slot 1 an exact zero mode, so every mode index m owns
+// an aligned pair and a shift rotates every pair alike (m = 0 by the identity).
+//
 // Tables (per axis, all FP64):
 //  F[l,pos][r][j]  leaf values (level l, position pos inside its cutoff box
 //                  along the axis) -> moments about the cutoff-box center:
@@ -162,7 +167,7 @@ void gauss_legendre_moments(int p, double t, double lam, const double* xq, const
 }  // namespace
 
 void build_tables(HostPlan& hp) {
-  const int p = hp.p, nr = hp.nr, M = hp.pw.M;
+  const int p = hp.p, nr = hp.nrs, M = hp.pw.M;
   const double h = hp.pw.h, sd = hp.sqrt_delta;
   std::vector<double> eta(p), wgl(p), V2P(p * p), P(p);
   gauss_legendre(p, eta.data(), wgl.data());
@@ -190,11 +195,14 @@ void build_tables(HostPlan& hp) {
       const double cs = std::cos(km[m] * shift), sn = std::sin(km[m] * shift);
       const double sc = wm[m] * 0.5 * L;
       if (m == 0) {
-        for (int n = 0; n < p; n++) Tpw[n] = sc * C[n];
+        for (int n = 0; n < p; n++) {
+          Tpw[n] = sc * C[n];
+          Tpw[p + n] = 0.0;  // the zero slot
+        }
       } else {
         for (int n = 0; n < p; n++) {
-          Tpw[(2 * m - 1) * p + n] = sc * (cs * C[n] - sn * S[n]);
-          Tpw[(2 * m) * p + n] = sc * (sn * C[n] + cs * S[n]);
+          Tpw[(2 * m) * p + n] = sc * (cs * C[n] - sn * S[n]);
+          Tpw[(2 * m + 1) * p + n] = sc * (sn * C[n] + cs * S[n]);
         }
       }
     }
@@ -209,9 +217,10 @@ void build_tables(HostPlan& hp) {
     for (int i = 0; i < p; i++) {
       const double x = shift + 0.5 * L * eta[i];  // x_i - c_A
       Eo[i * nr + 0] = 1.0;
+      Eo[i * nr + 1] = 0.0;  // the zero slot
       for (int m = 1; m < M; m++) {
-        Eo[i * nr + 2 * m - 1] = std::cos(km[m] * x);
-        Eo[i * nr + 2 * m] = std::sin(km[m] * x);
+        Eo[i * nr + 2 * m] = std::cos(km[m] * x);
+        Eo[i * nr + 2 * m + 1] = std::sin(km[m] * x);
       }
     }
   }

@@ -32,16 +32,17 @@ def _along(m, t, a, d):
     return np.moveaxis(np.tensordot(m, t, axes=([1], [ax])), 0, ax)
 
 
-def _rot_matrix(nr, rot, dir_):
-    R = np.zeros((nr, nr))
-    R[0, 0] = 1.0
-    M = (nr + 1) // 2
-    for m in range(1, M):
+def _rot_matrix(nrs, rot, dir_):
+    """Rotation of every stored (cos, sin) pair (2m, 2m+1) by dir * k_m L_c;
+    mode 0 (the constant and its zero slot) is left alone."""
+    R = np.zeros((nrs, nrs))
+    R[0, 0] = R[1, 1] = 1.0
+    for m in range(1, nrs // 2):
         c, s = rot[m]
         s = s * dir_
         if dir_ == 0:
             c, s = 1.0, 0.0
-        i, j = 2 * m - 1, 2 * m
+        i, j = 2 * m, 2 * m + 1
         R[i, i], R[i, j], R[j, i], R[j, j] = c, -s, s, c
     return R
 
@@ -53,8 +54,8 @@ def run(plan: api.Plan, sigma: np.ndarray, grouped: bool = False) -> np.ndarray:
     plane the axis-3 table (and the reverse for evaluation) -- instead of
     applying all tables per leaf."""
     info = plan.info()
-    d, p, nr = info["dim"], info["p"], info["nr"]
-    M = (nr + 1) // 2
+    d, p, nr = info["dim"], info["p"], info["nr_stored"]  # stored modes: (2m, 2m+1) = mode m
+    M = nr // 2
     F = plan.array("F").reshape(-1, nr, p)
     E = plan.array("E").reshape(-1, p, nr)
     V = plan.array("V").reshape(-1, p, p)

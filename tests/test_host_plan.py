@@ -255,9 +255,12 @@ def test_form_eval_tables_reproduce_the_1d_kernel():
     lv, cs = synth.uniform_tree(1, 4)  # 1D, level-4 leaves
     pl = _plan(lv, cs, p, delta, tol, force_lc=2)
     info = pl.info()
-    nr, M = info["nr"], (info["nr"] + 1) // 2
+    nr, M = info["nr_stored"], (info["nr"] + 1) // 2
+    assert nr == 2 * M
     F = pl.array("F").reshape(-1, nr, p)
     E = pl.array("E").reshape(-1, p, nr)
+    # the stored zero slot of mode 0
+    assert np.all(F[:, 1, :] == 0.0) and np.all(E[:, :, 1] == 0.0)
     rot = pl.array("rot").reshape(M, 2)
     meta = pl.array("ftab_meta").reshape(2, -1)
     tid = {(int(meta[0, k]), int(meta[1, k])): k for k in range(meta.shape[1])}
@@ -283,7 +286,7 @@ def test_form_eval_tables_reproduce_the_1d_kernel():
         for m in range(1, M):
             c, s = rot[m]
             s *= dir_
-            Rm[2 * m - 1:2 * m + 1, 2 * m - 1:2 * m + 1] = [[c, -s], [s, c]]
+            Rm[2 * m:2 * m + 2, 2 * m:2 * m + 2] = [[c, -s], [s, c]]
         return Rm
 
     for pos_s, pos_t in ((0, 1), (3, 0), (2, 2)):
