@@ -2,12 +2,14 @@
 
 The device resolves a Gaussian-sum density level by level (samples at the
 box nodes, Legendre-tail estimate, split above eps*||sigma||_2) and balances
-the tree.  The host input generator implements the same algorithm in numpy
-(its own sampling, coefficients and balance), so the two trees must be the
-same set of leaves, and sigma on them must agree to rounding.  A split
+the tree.  The oracle's Algorithm 3 (oracle/alg3.py: box by box in numpy,
+pinned on the CPU by Legendre-product densities with known tails, the
+hand-counted tail sets, a quadrature of the norm and balance properties)
+must produce the same set of leaves, and sigma on them must agree to
+rounding with the density evaluated at the oracle's own nodes.  A split
 decision is a floating-point comparison taken on both sides in FP64 (with
-different summation orders); the cases below have no box within rounding of
-the threshold, so the trees must be identical.
+different summation orders); every case asserts that no examined box lies
+within 1e-9 of the threshold, so the trees must be identical.
 """
 
 import time
@@ -16,6 +18,7 @@ import numpy as np
 import pytest
 
 import closed_forms as cf
+from oracle import alg3
 from paper_2305_07165_amd import api, synth
 
 torch = pytest.importorskip("torch")
@@ -45,23 +48,30 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,d,p,eps,periodic,maxl,minl,make", CASES, ids=[c[0] for c in CASES])
-def test_resolve_matches_the_input_generator(name, d, p, eps, periodic, maxl, minl, make):
+def test_resolve_matches_the_oracle_algorithm_3(name, d, p, eps, periodic, maxl, minl, make):
     dens = make()
+    norm = alg3.gaussian_sum_norm(dens.centers, dens.widths, dens.amps)
     t0 = time.time()
-    lv_h, cs_h = synth.resolve_tree(dens, d, p, eps, max_level=maxl, min_level=minl, periodic=periodic)
-    t_host = time.time() - t0
+    lv_o, cs_o, examined = alg3.resolve(alg3.gaussian_sum(dens.centers, dens.widths, dens.amps, periodic),
+                                        d, p, eps, norm, min_level=minl, max_level=maxl, periodic=periodic)
+    t_oracle = time.time() - t0
+    margin = min(abs(e - eps * norm) / (eps * norm) for _, _, e in examined)
     torch.cuda.synchronize()
     t0 = time.time()
     lv, cs, sig, info = api.resolve_gaussians(dens.centers, dens.widths, dens.amps, p, eps,
                                               periodic=dens.periodic, min_level=minl, max_level=maxl)
     torch.cuda.synchronize()
     t_dev = time.time() - t0
-    _say(f"{name}: {info['nleaves']} leaves (host {len(lv_h)}), boxes sampled {info['boxes_sampled']}, "
-         f"device {1e3 * t_dev:.1f} ms, host generator {1e3 * t_host:.1f} ms")
-    assert abs(info["norm"] - dens.l2norm()) <= 1e-13 * dens.l2norm()
-    assert _leafset(lv, cs) == _leafset(lv_h, cs_h)
-    assert synth.is_balanced_fast(lv, cs, periodic)
-    ref = synth.sample(lv, cs, p, dens)
+    _say(f"{name}: {info['nleaves']} leaves (oracle {len(lv_o)}), boxes sampled {info['boxes_sampled']} "
+         f"(oracle {len(examined)}), device {1e3 * t_dev:.1f} ms, oracle {1e3 * t_oracle:.1f} ms, "
+         f"closest box to the threshold {margin:.2e} of it")
+    assert margin > 1e-9
+    # the device's closed-form norm, then the same threshold on both sides
+    assert abs(info["norm"] - norm) <= 1e-13 * norm
+    assert _leafset(lv, cs) == _leafset(lv_o, cs_o)
+    assert alg3.is_balanced(lv, cs, periodic)
+    f = alg3.gaussian_sum(dens.centers, dens.widths, dens.amps, periodic)
+    ref = np.stack([f(alg3.box_nodes(int(l), tuple(int(v) for v in c), p)) for l, c in zip(lv, cs)])
     got = sig.cpu().numpy()
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     _say(f"{name}: sigma max rel diff {err:.2e}")
@@ -72,7 +82,8 @@ def test_sample_gaussians_on_a_given_tree():
     dens = synth.GaussianSum(np.array([[0.1, -0.2, 0.05]]), np.array([0.05]), np.array([0.8]), periodic=True)
     lv, cs = synth.point_refined_tree(3, [0.49, -0.2, 0.1], 4, periodic=True)
     got = api.sample_gaussians(dens.centers, dens.widths, dens.amps, lv, cs, 6, periodic=True).cpu().numpy()
-    ref = synth.sample(lv, cs, 6, dens)
+    f = alg3.gaussian_sum(dens.centers, dens.widths, dens.amps, periodic=True)
+    ref = np.stack([f(alg3.box_nodes(int(l), tuple(int(v) for v in c), 6)) for l, c in zip(lv, cs)])
     assert np.max(np.abs(got - ref)) < 1e-14 * np.max(np.abs(ref))
 
 
