@@ -14,12 +14,14 @@ with the leaf model of Eq. (papprox)), computed by the plain definition in
 ``oracle_u_boxes`` returns the same u at the nodes of arbitrary target boxes
 (the boxes of an output tree, Section 4.2).  ``oracle_interp`` evaluates a
 function given by values on a tree's leaves (the leaf model of Eq. (papprox))
-at arbitrary points, in numpy.
+at arbitrary points, in numpy.  ``oracle_point`` is the discrete transform of
+Eq. (pgt) summed directly over source points.
 """
 
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -60,6 +62,9 @@ def _load():
                                              ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                              ctypes.c_double, f64p, ctypes.c_int64, i32p, i32p,
                                              f64p, ctypes.c_int]
+        lib.oracle_point_fgt.restype = ctypes.c_int64
+        lib.oracle_point_fgt.argtypes = [ctypes.c_int, ctypes.c_int64, f64p, f64p, ctypes.c_int64,
+                                         f64p, ctypes.c_double, ctypes.c_double, f64p, ctypes.c_int]
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_gauss_legendre.restype = None
         lib.oracle_gauss_legendre.argtypes = [ctypes.c_int, f64p, f64p]
@@ -174,6 +179,30 @@ def oracle_interp(levels, coords, p: int, values, x, chunk: int = 65536):
             c = np.einsum("mn,mn...->m...", P, c)
         out[s:s + chunk] = c
     return out
+
+
+def oracle_point(sources, charges, targets, delta: float, cut: float | None = None,
+                 nthreads: int = 0, return_pairs: bool = False):
+    """The discrete Gauss transform (Eq. (pgt)) summed directly:
+    u_i = sum_j exp(-|x_i - y_j|^2/delta) q_j for sources ``[n, d]`` and
+    targets ``[m, d]`` in [-1/2, 1/2]^d.  cut: sources farther than it along
+    some axis are skipped (each skipped term is below exp(-cut^2/delta)|q_j|);
+    default sqrt(delta ln 1e18); 0 sums every pair."""
+    lib = _load()
+    y = np.ascontiguousarray(sources, dtype=np.float64)
+    q = np.ascontiguousarray(charges, dtype=np.float64).reshape(-1)
+    x = np.ascontiguousarray(targets, dtype=np.float64)
+    if y.ndim != 2 or x.ndim != 2 or y.shape[1] != x.shape[1] or len(q) != len(y):
+        raise ValueError("sources [n, d], charges [n], targets [m, d]")
+    if cut is None:
+        cut = math.sqrt(delta * math.log(1e18))
+    u = np.zeros(len(x))
+    n = lib.oracle_point_fgt(y.shape[1], len(y), _ptr(y, ctypes.c_double), _ptr(q, ctypes.c_double),
+                             len(x), _ptr(x, ctypes.c_double), float(delta), float(cut),
+                             _ptr(u, ctypes.c_double), int(nthreads))
+    if n < 0:
+        raise RuntimeError(f"oracle_point_fgt failed ({n})")
+    return (u, int(n)) if return_pairs else u
 
 
 def threads_used() -> int:

@@ -500,3 +500,126 @@ int64_t oracle_box_fgt(int d, int64_t nleaves, const int32_t *level, const int32
 
 /* The Gauss-Legendre rule used above, exported so tests can pin it. */
 void oracle_gauss_legendre(int n, double *x, double *w) { or_gauss_legendre(n, x, w); }
+
+/* ---------------------------------------------------------------------- */
+/* The discrete (point) Gauss transform, Section 1, Eq. (pgt):             */
+/*                                                                        */
+/*   u_i = sum_j exp(-|x_i - y_j|^2 / delta) q_j,                         */
+/*                                                                        */
+/* summed directly over the sources y_j of [-1/2,1/2]^d for every target  */
+/* x_i.  With cut > 0 the sources are binned into cells of side >= cut and */
+/* a target visits only the 3^d cells around its own: every source it     */
+/* skips is farther than cut along some axis, so its term is below        */
+/* exp(-cut^2/delta) |q_j|.  With cut = 0 every pair is summed.  Returns  */
+/* the number of pairs summed.                                            */
+
+int64_t oracle_point_fgt(int d, int64_t ns, const double *y, const double *q, int64_t nt,
+                         const double *x, double delta, double cut, double *u, int nthreads)
+{
+    if (d < 1 || d > 3 || ns < 0 || nt < 0 || !(delta > 0)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+    {
+#pragma omp single
+        or_threads_used = omp_get_num_threads();
+    }
+#else
+    or_threads_used = 1;
+#endif
+    int64_t npairs = 0;
+    if (cut <= 0.0) {
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : npairs)
+        for (int64_t i = 0; i < nt; i++) {
+            double s = 0.0;
+            for (int64_t j = 0; j < ns; j++) {
+                double r2 = 0.0;
+                for (int a = 0; a < d; a++) {
+                    const double t = x[i * d + a] - y[j * d + a];
+                    r2 += t * t;
+                }
+                s += exp(-r2 / delta) * q[j];
+            }
+            u[i] = s;
+            npairs += ns;
+        }
+        return npairs;
+    }
+    /* cells of side 1/nc >= cut over [-1/2, 1/2]^d */
+    int nc = (int)floor(1.0 / cut);
+    if (nc < 1) nc = 1;
+    if (nc > 512) nc = 512;
+    int64_t ncell = 1;
+    for (int a = 0; a < d; a++) ncell *= nc;
+    int64_t *start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+    int64_t *cellof = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+    if (!start || !order || !cellof) {
+        free(start);
+        free(order);
+        free(cellof);
+        return -2;
+    }
+    for (int64_t j = 0; j < ns; j++) {
+        int64_t c = 0;
+        for (int a = 0; a < d; a++) {
+            int k = (int)floor((y[j * d + a] + 0.5) * nc);
+            if (k < 0) k = 0;
+            if (k >= nc) k = nc - 1;
+            c = c * nc + k;
+        }
+        cellof[j] = c;
+        start[c + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; c++) start[c + 1] += start[c];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+        if (!fill) {
+            free(start);
+            free(order);
+            free(cellof);
+            return -2;
+        }
+        memcpy(fill, start, sizeof(int64_t) * (size_t)ncell);
+        for (int64_t j = 0; j < ns; j++) order[fill[cellof[j]]++] = j;
+        free(fill);
+    }
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : npairs)
+    for (int64_t i = 0; i < nt; i++) {
+        int k[3] = {0, 0, 0};
+        for (int a = 0; a < d; a++) {
+            k[a] = (int)floor((x[i * d + a] + 0.5) * nc);
+            if (k[a] < 0) k[a] = 0;
+            if (k[a] >= nc) k[a] = nc - 1;
+        }
+        double s = 0.0;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int a = 0; a < d; a++) {
+            lo[a] = k[a] > 0 ? k[a] - 1 : 0;
+            hi[a] = k[a] < nc - 1 ? k[a] + 1 : nc - 1;
+        }
+        for (int c3 = (d > 2 ? lo[2] : 0); c3 <= (d > 2 ? hi[2] : 0); c3++)
+            for (int c2 = (d > 1 ? lo[1] : 0); c2 <= (d > 1 ? hi[1] : 0); c2++)
+                for (int c1 = lo[0]; c1 <= hi[0]; c1++) {
+                    /* cell index with axis 1 most significant, as binned above */
+                    int64_t c = c1;
+                    if (d > 1) c = c * nc + c2;
+                    if (d > 2) c = c * nc + c3;
+                    for (int64_t t = start[c]; t < start[c + 1]; t++) {
+                        const int64_t j = order[t];
+                        double r2 = 0.0;
+                        for (int a = 0; a < d; a++) {
+                            const double e = x[i * d + a] - y[j * d + a];
+                            r2 += e * e;
+                        }
+                        s += exp(-r2 / delta) * q[j];
+                        npairs++;
+                    }
+                }
+        u[i] = s;
+    }
+    free(start);
+    free(order);
+    free(cellof);
+    return npairs;
+}
