@@ -431,46 +431,55 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
     }
   }
   __syncthreads();
-  // ---- phase 2: Z_P[i3][c] = sum_r3 E3_P[i3][r3] psi[r3][c], 16 columns per wave
+  // ---- phase 2: Z_P[i3][c] = sum_r3 E3_P[i3][r3] psi[r3][c], 16 columns per wave.
+  // Planes outer: a wave loads the plane's axis-3 table once and applies it to
+  // each of its column groups.  Both operands come from memory or LDS, so the
+  // K index of (group g, step kk) is 16 g + 4 lk + kk: a lane's four table
+  // entries are two aligned pairs of its row, loaded as vectors.
   const int lane = lane_of(), w = wave_of();
   const int lr = lane & 15, lk = lane >> 4;
-  for (int cg = w; 16 * cg < ncol; cg += 4) {  // column groups of 16, no barrier follows
-  const int col = 16 * cg + lr;
-  const bool colok = col < ncol;
-  T b[Q];
-#pragma unroll
-  for (int q = 0; q < Q; q++) {
-    const int k = 16 * (q >> 2) + M_::kidx(q & 3, lk);
-    const T v = ps[(k < nr && colok ? k * LDW + col : 0)];  // LDS: select, no branch
-    b[q] = k < nr && colok ? v : (T)0;
-  }
-  const int i1 = col < n2 ? 0 : 1;
-  const int r1 = 2 * m1 + i1;
-  const int r2 = r2first + col - i1 * n2;
-  const int64_t cglob = (int64_t)r1 * nr + r2;
   const int P0 = plane_start[A], P1 = plane_start[A + 1];
   for (int P = P0; P < P1; P++) {
     const T* E3 = E + (int64_t)plane_tab[P * 3 + 2] * p * nr;
-    acc_t acc;
-    zero4(acc);
+    T aq[Q];
 #pragma unroll
-    for (int g = 0; g < NT; g++) {
-      T aq[4], bq[4];
+    for (int g = 0; g < NT; g++)
 #pragma unroll
-      for (int kk = 0; kk < 4; kk++) {
-        const int k = 16 * g + M_::kidx(kk, lk);
-        aq[kk] = ld0<T>(E3, lr * nr + k, lr < p && k < nr);  // A[i3][r3]
-        bq[kk] = b[4 * g + kk];
+      for (int h = 0; h < 2; h++) {
+        const int k = 16 * g + 4 * lk + 2 * h;  // even: the pair (k, k+1) is inside the row or past it
+        const bool ok = lr < p && k < nr;
+        const T2 v2 = *reinterpret_cast<const T2*>(E3 + (ok ? lr * nr + k : 0));
+        aq[4 * g + 2 * h] = ok ? v2.x : (T)0;
+        aq[4 * g + 2 * h + 1] = ok ? v2.y : (T)0;
       }
-      acc = M_::template steps<4>(aq, bq, acc);
-    }
     T* Zp = Z + (int64_t)P * p * nr2;
+    for (int cg = w; 16 * cg < ncol; cg += 4) {  // column groups of 16, no barrier follows
+      const int col = 16 * cg + lr;
+      const bool colok = col < ncol;
+      acc_t acc;
+      zero4(acc);
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-      const int i3 = M_::row(lk, t);
-      if (i3 < p && colok) Zp[(int64_t)i3 * nr2 + cglob] = acc[t];
+      for (int g = 0; g < NT; g++) {
+        T aqg[4], bq[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
+          const int k = 16 * g + 4 * lk + kk;
+          const T v = ps[(k < nr && colok ? k * LDW + col : 0)];  // LDS: select, no branch
+          bq[kk] = k < nr && colok ? v : (T)0;
+          aqg[kk] = aq[4 * g + kk];
+        }
+        acc = M_::template steps<4>(aqg, bq, acc);
+      }
+      const int i1 = col < n2 ? 0 : 1;
+      const int r1 = 2 * m1 + i1;
+      const int r2 = r2first + col - i1 * n2;
+      const int64_t cglob = (int64_t)r1 * nr + r2;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int i3 = M_::row(lk, t);
+        if (i3 < p && colok) Zp[(int64_t)i3 * nr2 + cglob] = acc[t];
+      }
     }
-  }
   }
 }
 
