@@ -35,7 +35,9 @@ EXPORTED = ["fgt_plan", "fgt_execute", "fgt_execute_noalloc", "fgt_sync", "fgt_p
             "fgt_output_resolve", "fgt_output_info", "fgt_output_tree", "fgt_output_values",
             "fgt_output_destroy", "fgt_interp", "fgt_tree_balance",
             "fgt_resolve_gaussians", "fgt_density_info", "fgt_density_tree", "fgt_density_values",
-            "fgt_density_destroy", "fgt_sample_gaussians"]
+            "fgt_density_destroy", "fgt_sample_gaussians",
+            "fgt_point_plan", "fgt_point_execute", "fgt_point_info", "fgt_point_array",
+            "fgt_point_destroy"]
 
 
 class fgt_tree_t(ctypes.Structure):
@@ -151,6 +153,24 @@ class fgt_gaussians_t(ctypes.Structure):
                 ("amps", ctypes.POINTER(ctypes.c_double)), ("periodic", ctypes.c_int32)]
 
 
+class fgt_point_opts_t(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("ns", ctypes.c_int32), ("host_only", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class fgt_point_info_t(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("p", ctypes.c_int32), ("ns", ctypes.c_int32),
+                ("lc", ctypes.c_int32), ("lp", ctypes.c_int32), ("nr", ctypes.c_int32),
+                ("nsrc", ctypes.c_int64), ("ntgt", ctypes.c_int64), ("nleaves", ctypes.c_int64),
+                ("ndense", ctypes.c_int64), ("npwbox", ctypes.c_int64), ("nproxy", ctypes.c_int64),
+                ("nplist", ctypes.c_int64), ("ndirect_terms", ctypes.c_int64),
+                ("delta", ctypes.c_double), ("tol", ctypes.c_double), ("proxy_err", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class fgt_resolve_opts_t(ctypes.Structure):
     _fields_ = [("min_level", ctypes.c_int32), ("max_level", ctypes.c_int32),
                 ("max_leaves", ctypes.c_int64), ("norm", ctypes.c_double),
@@ -248,6 +268,17 @@ def lib():
         L.fgt_output_destroy.argtypes = [vp]
         L.fgt_interp.restype = ctypes.c_int
         L.fgt_interp.argtypes = [ctypes.POINTER(fgt_tree_t), ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp]
+        L.fgt_point_plan.restype = ctypes.c_int
+        L.fgt_point_plan.argtypes = [ctypes.c_int, ctypes.c_int64, vp, ctypes.c_int64, vp, ctypes.c_double,
+                                     ctypes.c_double, ctypes.POINTER(fgt_point_opts_t), ctypes.POINTER(vp)]
+        L.fgt_point_execute.restype = ctypes.c_int
+        L.fgt_point_execute.argtypes = [vp, vp, vp]
+        L.fgt_point_info.restype = ctypes.c_int
+        L.fgt_point_info.argtypes = [vp, ctypes.POINTER(fgt_point_info_t)]
+        L.fgt_point_array.restype = ctypes.c_int64
+        L.fgt_point_array.argtypes = [vp, ctypes.c_char_p, vp, ctypes.c_int64]
+        L.fgt_point_destroy.restype = None
+        L.fgt_point_destroy.argtypes = [vp]
         L.fgt_tree_balance.restype = ctypes.c_int64
         L.fgt_tree_balance.argtypes = [ctypes.POINTER(fgt_tree_t), ctypes.c_int, vp, vp, ctypes.c_int64]
         L.fgt_resolve_gaussians.restype = ctypes.c_int

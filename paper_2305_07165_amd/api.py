@@ -488,6 +488,70 @@ def fgt_tree_balance(levels, coords, periodic: bool = False):
     return lv, cs
 
 
+class PointPlan:
+    """The point Gauss transform with proxy grids (include/fgt_point.h):
+    sources [n, d] and targets [m, d] on the host at planning time; execute
+    takes the charges [n] and returns u [m] as float64 device tensors."""
+
+    def __init__(self, sources, targets, delta: float, tol: float, p: int = 16, ns: int = 64,
+                 host_only: bool = False, stream=None):
+        self.handle = 0
+        src = np.ascontiguousarray(sources, dtype=np.float64)
+        tgt = np.ascontiguousarray(targets, dtype=np.float64)
+        if src.ndim != 2 or tgt.ndim != 2 or src.shape[1] != tgt.shape[1]:
+            raise ValueError("sources [n, d] and targets [m, d]")
+        self.dim, self.nsrc, self.ntgt = src.shape[1], src.shape[0], tgt.shape[0]
+        if stream is None and not host_only:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        o = _lib.fgt_point_opts_t(int(p), int(ns), int(bool(host_only)), ctypes.c_void_p(int(stream or 0) or None))
+        h = ctypes.c_void_p()
+        check(_lib.lib().fgt_point_plan(self.dim, self.nsrc, src.ctypes.data, self.ntgt, tgt.ctypes.data,
+                                        float(delta), float(tol), ctypes.byref(o), ctypes.byref(h)),
+              "fgt_point_plan")
+        self.handle = h.value
+
+    def execute(self, q, u=None):
+        if u is None:
+            import torch
+            u = torch.empty(self.ntgt, dtype=torch.float64, device=q.device)
+        for name, t, n in (("q", q, self.nsrc), ("u", u, self.ntgt)):
+            if tuple(t.shape) != (n,) or str(t.dtype) != "torch.float64" or not t.is_cuda:
+                raise ValueError(f"{name} must be a float64 device tensor of shape ({n},)")
+        check(_lib.lib().fgt_point_execute(self.handle, _ptr(q), _ptr(u)), "fgt_point_execute")
+        return u
+
+    def info(self) -> dict:
+        info = _lib.fgt_point_info_t()
+        check(_lib.lib().fgt_point_info(self.handle, ctypes.byref(info)), "fgt_point_info")
+        return info.as_dict()
+
+    def array(self, name: str) -> np.ndarray:
+        L = _lib.lib()
+        n = check(L.fgt_point_array(self.handle, name.encode(), None, 0), "fgt_point_array")
+        out = np.zeros(n, dtype=np.int32)
+        if n:
+            L.fgt_point_array(self.handle, name.encode(), out.ctypes.data, n)
+        return out
+
+    def close(self):
+        if self.handle:
+            _lib.lib().fgt_point_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 class OutputTree:
     """u resolved on its own adaptive tree (Section 4.2).  ``levels``,
     ``coords`` and ``u`` (a tensor on sigma's device) are filled on

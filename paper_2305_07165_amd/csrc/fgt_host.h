@@ -50,6 +50,10 @@ struct HostPlan {
   // sqrt(delta), M = n_p + 1, identity translation, no near field)
   bool fourier = false;
 
+  // formation tables evaluated at the leaf nodes instead of integrated over the
+  // leaf: the leaves are proxy grids of a point transform (point_host.h)
+  bool point_tables = false;
+
   // d = 3: fuse the translations with the first evaluation step when the
   // incoming expansions would not stay in the caches (more than kFuseBytes)
   bool fuse_te = false;
@@ -109,6 +113,16 @@ struct HostPlan {
   int64_t n_plane() const { return row_start.empty() ? 0 : (int64_t)plane_row.size() - 1; }
   int64_t n_row() const { return row_start.empty() ? 0 : (int64_t)row_start.size() - 1; }
 };
+
+// A plane-wave leaf of cutoff box `box`: `id` its row in sigma / u, `lv` its
+// level, `m` its order key inside the box.
+struct PwLeafRef { int32_t box; uint64_t m; int32_t id; int32_t lv; };
+// Sorts the plane-wave leaves by (box, level, key) and fills pw_start,
+// pwleaf_id/tab/box, the form/eval table ids (nftab, ftab_meta), for d = 3 the
+// planes and rows, fuse_te, box_order, the formation items (fitem, fred,
+// nslots) and the evaluation chunks.  level/coord are indexed by id.
+void finish_pw_lists(HostPlan& hp, std::vector<PwLeafRef>& pl, int32_t nA, const int32_t* level,
+                     const int32_t* coord, bool allow_fuse);
 
 // Validates the tree and fills every field above.  Returns an FGT_* code.
 int build_host_plan(int dim, int64_t nleaves, const int32_t* level, const int32_t* coord,

@@ -63,6 +63,128 @@ void dir_of(int code, int d, int* dir) {
 
 }  // namespace
 
+// Orders the plane-wave leaves by (box, level, key) and fills the lists the
+// box-level stages run over: pw_start, pwleaf_id/tab/box, the form/eval table
+// ids (one table per level and position along an axis inside the cutoff box),
+// for d = 3 the planes and rows, the fused-translation choice, the dispatch
+// order of boxes, the formation items and the evaluation chunks.
+void finish_pw_lists(HostPlan& hp, std::vector<PwLeafRef>& pl, int32_t nA, const int32_t* level,
+                     const int32_t* coord, bool allow_fuse) {
+  const int d = hp.d, p = hp.p, lc = hp.lc;
+  std::sort(pl.begin(), pl.end(), [](const PwLeafRef& x, const PwLeafRef& y) {
+    if (x.box != y.box) return x.box < y.box;
+    if (x.lv != y.lv) return x.lv < y.lv;
+    return x.m < y.m;
+  });
+  std::unordered_map<uint64_t, int32_t> ftab;  // (level, pos) -> id
+  std::vector<int32_t> ftab_lv, ftab_pos;
+  hp.pw_start.assign(nA + 1, 0);
+  hp.pwleaf_id.resize(pl.size());
+  hp.pwleaf_tab.resize(pl.size() * d);
+  hp.pwleaf_box.resize(pl.size());
+  for (size_t s = 0; s < pl.size(); s++) {
+    int32_t i = pl[s].id;
+    int l = level[i];
+    hp.pwleaf_id[s] = i;
+    hp.pwleaf_box[s] = pl[s].box;
+    hp.pw_start[pl[s].box + 1]++;
+    for (int a = 0; a < d; a++) {
+      int32_t pos = coord[i * d + a] - ((coord[i * d + a] >> (l - lc)) << (l - lc));
+      uint64_t k = ((uint64_t)l << 32) | (uint32_t)pos;
+      auto it = ftab.find(k);
+      int32_t id;
+      if (it == ftab.end()) {
+        id = (int32_t)ftab_lv.size();
+        ftab.emplace(k, id);
+        ftab_lv.push_back(l);
+        ftab_pos.push_back(pos);
+      } else {
+        id = it->second;
+      }
+      hp.pwleaf_tab[s * d + a] = id;
+    }
+  }
+  for (int32_t a = 0; a < nA; a++) hp.pw_start[a + 1] += hp.pw_start[a];
+  hp.nftab = (int)ftab_lv.size();
+  hp.ftab_meta = ftab_lv;
+  hp.ftab_meta.insert(hp.ftab_meta.end(), ftab_pos.begin(), ftab_pos.end());
+
+  // d = 3 planes and rows (see the leaf order above)
+  if (d == 3) {
+    hp.plane_start.assign(nA + 1, 0);
+    for (int32_t a = 0; a < nA; a++) {
+      for (int32_t s = hp.pw_start[a]; s < hp.pw_start[a + 1]; s++) {
+        const int32_t t3 = hp.pwleaf_tab[s * 3 + 2], t1 = hp.pwleaf_tab[s * 3 + 0];
+        const bool new_plane = s == hp.pw_start[a] || hp.pwleaf_tab[(s - 1) * 3 + 2] != t3;
+        const bool new_row = new_plane || hp.pwleaf_tab[(s - 1) * 3 + 0] != t1;
+        if (new_plane) {
+          hp.plane_row.push_back((int32_t)hp.row_tab.size());
+          hp.plane_tab.insert(hp.plane_tab.end(), {0, 0, t3});
+        }
+        if (new_row) {
+          hp.row_start.push_back(s);
+          hp.row_tab.push_back(t1);
+        }
+      }
+      hp.plane_start[a + 1] = (int32_t)hp.plane_row.size();
+    }
+    hp.plane_row.push_back((int32_t)hp.row_tab.size());
+    hp.row_start.push_back((int32_t)pl.size());
+  }
+  if (d == 3) {
+    // measured: the fused kernel wins while psi is large and n_r <= 64 (up to
+    // four mode tiles); with wider tiles its tile shape reads phi less
+    // contiguously than the plain translation and the pair of kernels is faster
+    const double ts = hp.precision == FGT_FP64 ? 8.0 : 4.0;
+    hp.fuse_te = allow_fuse && hp.nrs <= 64 && ts * nA * (double)hp.nrs * hp.nrs * hp.nrs > kFuseBytes;
+  }
+  // the units the box-level stages run over: planes for d = 3, leaves otherwise
+  const std::vector<int32_t>& unit_start = d == 3 ? hp.plane_start : hp.pw_start;
+
+  // dispatch order of per-box work: most units first (longest work first)
+  hp.box_order.resize(nA);
+  for (int32_t a = 0; a < nA; a++) hp.box_order[a] = a;
+  std::stable_sort(hp.box_order.begin(), hp.box_order.end(), [&](int32_t x, int32_t y) {
+    return unit_start[x + 1] - unit_start[x] > unit_start[y + 1] - unit_start[y];
+  });
+
+  // formation work items: at most kFormLeaves units each
+  for (int32_t a = 0; a < nA; a++) {
+    const int32_t s0 = unit_start[a], s1 = unit_start[a + 1];
+    if (s1 - s0 <= kFormLeaves) {
+      hp.fitem.insert(hp.fitem.end(), {a, s0, s1, -1});
+      continue;
+    }
+    const int32_t first = hp.nslots;
+    for (int32_t s = s0; s < s1; s += kFormLeaves)
+      hp.fitem.insert(hp.fitem.end(), {a, s, std::min(s + kFormLeaves, s1), hp.nslots++});
+    hp.fred.insert(hp.fred.end(), {a, first, hp.nslots - first});
+  }
+
+  {
+    const size_t ni = hp.fitem.size() / 4;
+    std::vector<int32_t> ord(ni);
+    for (size_t i = 0; i < ni; i++) ord[i] = (int32_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+      return hp.fitem[4 * x + 2] - hp.fitem[4 * x + 1] > hp.fitem[4 * y + 2] - hp.fitem[4 * y + 1];
+    });
+    std::vector<int32_t> f2;
+    f2.reserve(hp.fitem.size());
+    for (int32_t i : ord) f2.insert(f2.end(), hp.fitem.begin() + 4 * i, hp.fitem.begin() + 4 * i + 4);
+    hp.fitem.swap(f2);
+  }
+
+  // evaluation chunks: up to 64 stacked rows (count*p) of one box
+  const int per = std::max(1, 64 / p);
+  for (int32_t a = 0; a < nA; a++)
+    for (int32_t s = hp.pw_start[a]; s < hp.pw_start[a + 1]; s += per) {
+      hp.echunk.push_back(a);
+      hp.echunk.push_back(s);
+      hp.echunk.push_back(std::min(per, hp.pw_start[a + 1] - s));
+    }
+
+}
+
 int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord, int p,
                     double delta, double tol, int bc, int precision, double eps_internal,
                     int force_lc, bool allow_fuse, HostPlan& hp, std::string& err) {
@@ -263,8 +385,7 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
   // position on axis 1, position on axis 2), so that a plane (leaves of one
   // level sharing the axis-3 position, hence the axis-3 table) and a row of a
   // plane (also sharing the axis-1 position and table) are contiguous ranges.
-  struct PwLeaf { int32_t box; uint64_t m; int32_t id; int32_t lv; };
-  std::vector<PwLeaf> pl;
+  std::vector<PwLeafRef> pl;
   for (int64_t i = 0; i < n; i++) {
     int l = level[i];
     if (l < lc) continue;
@@ -282,117 +403,7 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     }
     pl.push_back({b.idx, m, (int32_t)i, lv});
   }
-  std::sort(pl.begin(), pl.end(), [](const PwLeaf& x, const PwLeaf& y) {
-    if (x.box != y.box) return x.box < y.box;
-    if (x.lv != y.lv) return x.lv < y.lv;
-    return x.m < y.m;
-  });
-  std::unordered_map<uint64_t, int32_t> ftab;  // (level, pos) -> id
-  std::vector<int32_t> ftab_lv, ftab_pos;
-  hp.pw_start.assign(nA + 1, 0);
-  hp.pwleaf_id.resize(pl.size());
-  hp.pwleaf_tab.resize(pl.size() * d);
-  hp.pwleaf_box.resize(pl.size());
-  for (size_t s = 0; s < pl.size(); s++) {
-    int32_t i = pl[s].id;
-    int l = level[i];
-    hp.pwleaf_id[s] = i;
-    hp.pwleaf_box[s] = pl[s].box;
-    hp.pw_start[pl[s].box + 1]++;
-    for (int a = 0; a < d; a++) {
-      int32_t pos = coord[i * d + a] - ((coord[i * d + a] >> (l - lc)) << (l - lc));
-      uint64_t k = ((uint64_t)l << 32) | (uint32_t)pos;
-      auto it = ftab.find(k);
-      int32_t id;
-      if (it == ftab.end()) {
-        id = (int32_t)ftab_lv.size();
-        ftab.emplace(k, id);
-        ftab_lv.push_back(l);
-        ftab_pos.push_back(pos);
-      } else {
-        id = it->second;
-      }
-      hp.pwleaf_tab[s * d + a] = id;
-    }
-  }
-  for (int32_t a = 0; a < nA; a++) hp.pw_start[a + 1] += hp.pw_start[a];
-  hp.nftab = (int)ftab_lv.size();
-  hp.ftab_meta = ftab_lv;
-  hp.ftab_meta.insert(hp.ftab_meta.end(), ftab_pos.begin(), ftab_pos.end());
-
-  // d = 3 planes and rows (see the leaf order above)
-  if (d == 3) {
-    hp.plane_start.assign(nA + 1, 0);
-    for (int32_t a = 0; a < nA; a++) {
-      for (int32_t s = hp.pw_start[a]; s < hp.pw_start[a + 1]; s++) {
-        const int32_t t3 = hp.pwleaf_tab[s * 3 + 2], t1 = hp.pwleaf_tab[s * 3 + 0];
-        const bool new_plane = s == hp.pw_start[a] || hp.pwleaf_tab[(s - 1) * 3 + 2] != t3;
-        const bool new_row = new_plane || hp.pwleaf_tab[(s - 1) * 3 + 0] != t1;
-        if (new_plane) {
-          hp.plane_row.push_back((int32_t)hp.row_tab.size());
-          hp.plane_tab.insert(hp.plane_tab.end(), {0, 0, t3});
-        }
-        if (new_row) {
-          hp.row_start.push_back(s);
-          hp.row_tab.push_back(t1);
-        }
-      }
-      hp.plane_start[a + 1] = (int32_t)hp.plane_row.size();
-    }
-    hp.plane_row.push_back((int32_t)hp.row_tab.size());
-    hp.row_start.push_back((int32_t)pl.size());
-  }
-  if (d == 3) {
-    // measured: the fused kernel wins while psi is large and n_r <= 64 (up to
-    // four mode tiles); with wider tiles its tile shape reads phi less
-    // contiguously than the plain translation and the pair of kernels is faster
-    const double ts = precision == FGT_FP64 ? 8.0 : 4.0;
-    hp.fuse_te = allow_fuse && hp.nrs <= 64 && ts * nA * (double)hp.nrs * hp.nrs * hp.nrs > kFuseBytes;
-  }
-  // the units the box-level stages run over: planes for d = 3, leaves otherwise
-  const std::vector<int32_t>& unit_start = d == 3 ? hp.plane_start : hp.pw_start;
-
-  // dispatch order of per-box work: most units first (longest work first)
-  hp.box_order.resize(nA);
-  for (int32_t a = 0; a < nA; a++) hp.box_order[a] = a;
-  std::stable_sort(hp.box_order.begin(), hp.box_order.end(), [&](int32_t x, int32_t y) {
-    return unit_start[x + 1] - unit_start[x] > unit_start[y + 1] - unit_start[y];
-  });
-
-  // formation work items: at most kFormLeaves units each
-  for (int32_t a = 0; a < nA; a++) {
-    const int32_t s0 = unit_start[a], s1 = unit_start[a + 1];
-    if (s1 - s0 <= kFormLeaves) {
-      hp.fitem.insert(hp.fitem.end(), {a, s0, s1, -1});
-      continue;
-    }
-    const int32_t first = hp.nslots;
-    for (int32_t s = s0; s < s1; s += kFormLeaves)
-      hp.fitem.insert(hp.fitem.end(), {a, s, std::min(s + kFormLeaves, s1), hp.nslots++});
-    hp.fred.insert(hp.fred.end(), {a, first, hp.nslots - first});
-  }
-
-  {
-    const size_t ni = hp.fitem.size() / 4;
-    std::vector<int32_t> ord(ni);
-    for (size_t i = 0; i < ni; i++) ord[i] = (int32_t)i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
-      return hp.fitem[4 * x + 2] - hp.fitem[4 * x + 1] > hp.fitem[4 * y + 2] - hp.fitem[4 * y + 1];
-    });
-    std::vector<int32_t> f2;
-    f2.reserve(hp.fitem.size());
-    for (int32_t i : ord) f2.insert(f2.end(), hp.fitem.begin() + 4 * i, hp.fitem.begin() + 4 * i + 4);
-    hp.fitem.swap(f2);
-  }
-
-  // evaluation chunks: up to 64 stacked rows (count*p) of one box
-  const int per = std::max(1, 64 / p);
-  for (int32_t a = 0; a < nA; a++)
-    for (int32_t s = hp.pw_start[a]; s < hp.pw_start[a + 1]; s += per) {
-      hp.echunk.push_back(a);
-      hp.echunk.push_back(s);
-      hp.echunk.push_back(std::min(per, hp.pw_start[a + 1] - s));
-    }
+  finish_pw_lists(hp, pl, nA, level, coord, allow_fuse);
 
   // ---- P-lists (Definition before Algorithm 4, read for every box with f = 1):
   // colleagues with f = 1 (images included when periodic), excluding pairs of

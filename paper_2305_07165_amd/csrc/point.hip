@@ -1,0 +1,449 @@
+// The point Gauss transform with proxy grids (declared in fgt_point.h): the
+// device side.  Per execution:
+//   1. k_anterp   charges -> proxy charges on the grids of the dense boxes
+//   2. the box transform's plane-wave stages over the proxy grids (formation
+//      with point-evaluation tables, translation, evaluation on the grids)
+//   3. k_interp   grid potentials -> the targets of every plane-wave box
+//   4. k_direct   the D-lists summed directly, plus the plane-wave part, into u
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fgt.h"
+#include "../../include/fgt_point.h"
+#include "plan_internal.h"
+#include "point_host.h"
+
+namespace fgt {
+namespace {
+
+constexpr int kPT = 256;  // threads per workgroup
+constexpr int kPMax = 16;
+
+// Lagrange weights of the p Gauss-Legendre nodes at t in [-1, 1], by the
+// barycentric formula; a node hit exactly gets the unit weight.
+__device__ __forceinline__ void lagrange(int p, double t, const double* __restrict__ eta,
+                                         const double* __restrict__ lam, double (&w)[kPMax]) {
+  double den = 0.0;
+  int hit = -1;
+#pragma unroll
+  for (int k = 0; k < kPMax; k++) {
+    const double dt = k < p ? t - eta[k] : 1.0;
+    if (k < p && dt == 0.0) hit = k;
+    w[k] = (k < p && dt != 0.0) ? lam[k] / dt : 0.0;
+    den += w[k];
+  }
+  const double inv = hit >= 0 ? 0.0 : 1.0 / den;
+#pragma unroll
+  for (int k = 0; k < kPMax; k++) w[k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : w[k] * inv;
+}
+
+// Local coordinate in [-1, 1] of x on axis a of the box (level l, coord c).
+__device__ __forceinline__ double local_coord(double x, int l, int32_t c) {
+  const double L = ldexp(1.0, -l);
+  const double lo = -0.5 + (double)c * L;
+  double t = 2.0 * (x - lo) / L - 1.0;
+  return t < -1.0 ? -1.0 : (t > 1.0 ? 1.0 : t);
+}
+
+// 1. Proxy charges of one grid: Q[k] = sum over its sources of
+// prod_a l_{k_a}(t_a) q, node k = k_1 + p k_2 (+ p^2 k_3).  Sources come in
+// chunks whose weights are computed once into LDS.
+template <int D>
+__global__ __launch_bounds__(kPT) void k_anterp(const double* __restrict__ q, const int32_t* __restrict__ src_perm,
+                                                const double* __restrict__ src_xyz,
+                                                const int32_t* __restrict__ px_src,
+                                                const int32_t* __restrict__ px_coord, int lp, int p,
+                                                const double* __restrict__ eta, const double* __restrict__ lam,
+                                                double* __restrict__ Q) {
+  constexpr int CH = 32;
+  constexpr int NE = D == 3 ? (kPMax * kPMax * kPMax + kPT - 1) / kPT : 1;
+  __shared__ double W[CH][D][kPMax];
+  __shared__ double qs[CH];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int s0 = px_src[2 * b], s1 = px_src[2 * b + 1];
+  int pd = p * p;
+  if (D == 3) pd *= p;
+  double acc[NE];
+#pragma unroll
+  for (int j = 0; j < NE; j++) acc[j] = 0.0;
+  for (int c0 = s0; c0 < s1; c0 += CH) {
+    const int nc = min(CH, s1 - c0);
+    if (tid < nc * D) {
+      const int s = tid / D, a = tid - (tid / D) * D;
+      const double t = local_coord(src_xyz[(int64_t)(c0 + s) * D + a], lp, px_coord[(int64_t)b * D + a]);
+      double w[kPMax];
+      lagrange(p, t, eta, lam, w);
+#pragma unroll
+      for (int k = 0; k < kPMax; k++) W[s][a][k] = w[k];
+    }
+    if (tid < nc) qs[tid] = q[src_perm[c0 + tid]];
+    __syncthreads();
+    for (int s = 0; s < nc; s++) {
+#pragma unroll
+      for (int j = 0; j < NE; j++) {
+        const int e = tid + kPT * j;
+        if (e < pd) {
+          const int k1 = e % p, k2 = (e / p) % p;
+          double v = W[s][0][k1] * W[s][1][k2] * qs[s];
+          if (D == 3) v *= W[s][2][e / (p * p)];
+          acc[j] += v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < NE; j++) {
+    const int e = tid + kPT * j;
+    if (e < pd) Q[(int64_t)b * pd + e] = acc[j];
+  }
+}
+
+// 3. The grid potential of one plane-wave box's grid at its targets (written
+// at their sorted positions).
+template <int D>
+__global__ __launch_bounds__(kPT) void k_interp(const double* __restrict__ U, const int32_t* __restrict__ px_list,
+                                                const int32_t* __restrict__ px_tgt,
+                                                const int32_t* __restrict__ px_coord, int lp, int p,
+                                                const double* __restrict__ eta, const double* __restrict__ lam,
+                                                const double* __restrict__ tgt_xyz, double* __restrict__ uw) {
+  __shared__ double Us[kPMax * kPMax * (D == 3 ? kPMax : 1)];
+  const int b = px_list[blockIdx.x], tid = threadIdx.x;
+  int pd = p * p;
+  if (D == 3) pd *= p;
+  for (int e = tid; e < pd; e += kPT) Us[e] = U[(int64_t)b * pd + e];
+  __syncthreads();
+  const int t0 = px_tgt[2 * b], t1 = px_tgt[2 * b + 1];
+  for (int pos = t0 + tid; pos < t1; pos += kPT) {
+    double w1[kPMax], w2[kPMax], w3[kPMax];
+    lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 0], lp, px_coord[(int64_t)b * D + 0]), eta, lam, w1);
+    lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 1], lp, px_coord[(int64_t)b * D + 1]), eta, lam, w2);
+    if (D == 3)
+      lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 2], lp, px_coord[(int64_t)b * D + 2]), eta, lam, w3);
+    double u = 0.0;
+#pragma unroll
+    for (int k3 = 0; k3 < (D == 3 ? kPMax : 1); k3++) {
+      if (k3 >= p) break;
+      double s3 = 0.0;
+#pragma unroll
+      for (int k2 = 0; k2 < kPMax; k2++) {
+        if (k2 >= p) break;
+        const double* row = Us + (k3 * p + k2) * p;
+        double s2 = 0.0;
+#pragma unroll
+        for (int k1 = 0; k1 < kPMax; k1++)
+          if (k1 < p) s2 += w1[k1] * row[k1];
+        s3 += w2[k2] * s2;
+      }
+      u += (D == 3 ? w3[k3] : 1.0) * s3;
+    }
+    uw[pos] = u;
+  }
+}
+
+// 4. One leaf's targets: the sum over the sources of its D-list, in a fixed
+// order, plus the plane-wave part when the leaf has one; u in the caller's order.
+template <int D>
+__global__ __launch_bounds__(kPT) void k_direct(const double* __restrict__ q, const int32_t* __restrict__ src_perm,
+                                                const double* __restrict__ src_xyz,
+                                                const double* __restrict__ tgt_xyz,
+                                                const int32_t* __restrict__ tgt_perm,
+                                                const int32_t* __restrict__ leaf_src_start,
+                                                const int32_t* __restrict__ leaf_tgt_start,
+                                                const int32_t* __restrict__ dl_tgt,
+                                                const int32_t* __restrict__ dl_haspw,
+                                                const int32_t* __restrict__ dl_start,
+                                                const int32_t* __restrict__ dl_src, double inv_delta,
+                                                const double* __restrict__ uw, double* __restrict__ u) {
+  __shared__ double ys[kPT][D + 1];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int T = dl_tgt[k];
+  const bool haspw = dl_haspw[k] != 0;
+  const int t0 = leaf_tgt_start[T], t1 = leaf_tgt_start[T + 1];
+  const int e0 = dl_start[k], e1 = dl_start[k + 1];
+  for (int tb = t0; tb < t1; tb += kPT) {
+    const int pos = tb + tid;
+    const bool mine = pos < t1;
+    double x[3] = {0.0, 0.0, 0.0};
+    if (mine)
+      for (int a = 0; a < D; a++) x[a] = tgt_xyz[(int64_t)pos * D + a];
+    double acc = 0.0;
+    for (int e = e0; e < e1; e++) {
+      const int S = dl_src[e];
+      const int s0 = leaf_src_start[S], s1 = leaf_src_start[S + 1];
+      for (int sb = s0; sb < s1; sb += kPT) {
+        const int n = min(kPT, s1 - sb);
+        if (tid < n) {
+          for (int a = 0; a < D; a++) ys[tid][a] = src_xyz[(int64_t)(sb + tid) * D + a];
+          ys[tid][D] = q[src_perm[sb + tid]];
+        }
+        __syncthreads();
+        if (mine) {
+          for (int j = 0; j < n; j++) {
+            double r2 = 0.0;
+            for (int a = 0; a < D; a++) {
+              const double dx = x[a] - ys[j][a];
+              r2 += dx * dx;
+            }
+            acc += exp(-r2 * inv_delta) * ys[j][D];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (mine) u[tgt_perm[pos]] = acc + (haspw ? uw[pos] : 0.0);
+  }
+}
+
+}  // namespace
+}  // namespace fgt
+
+struct fgt_point_plan {
+  fgt::PointHost ph;
+  fgt_plan_t* pw = nullptr;  // the plane-wave stages over the proxy grids
+  bool host_only = true;
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  int64_t device_bytes = 0;
+  // device arrays
+  int32_t *src_perm = nullptr, *tgt_perm = nullptr, *leaf_src_start = nullptr, *leaf_tgt_start = nullptr;
+  int32_t *dl_tgt = nullptr, *dl_haspw = nullptr, *dl_start = nullptr, *dl_src = nullptr;
+  int32_t *px_src = nullptr, *px_tgt = nullptr, *px_coord = nullptr, *px_list = nullptr;
+  double *src_xyz = nullptr, *tgt_xyz = nullptr, *eta = nullptr, *lam = nullptr;
+  double *Q = nullptr, *U = nullptr, *uw = nullptr;
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char* what) {
+  return fgt::set_error(FGT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename X>
+int upload(fgt_point_plan_t* pp, const std::vector<X>& v, X** out) {
+  *out = nullptr;
+  if (v.empty()) return FGT_OK;
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, v.size() * sizeof(X));
+  if (e != hipSuccess) return fgt::set_error(FGT_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  pp->allocs.push_back(d);
+  pp->device_bytes += (int64_t)(v.size() * sizeof(X));
+  if ((e = hipMemcpy(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy");
+  *out = static_cast<X*>(d);
+  return FGT_OK;
+}
+
+int alloc_doubles(fgt_point_plan_t* pp, size_t n, double** out) {
+  *out = nullptr;
+  if (n == 0) return FGT_OK;
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, n * sizeof(double));
+  if (e != hipSuccess) return fgt::set_error(FGT_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  pp->allocs.push_back(d);
+  pp->device_bytes += (int64_t)(n * sizeof(double));
+  *out = static_cast<double*>(d);
+  return FGT_OK;
+}
+
+void release(fgt_point_plan_t* pp) {
+  if (!pp) return;
+  if (!pp->host_only) {
+    (void)hipSetDevice(pp->device);
+    (void)hipStreamSynchronize(pp->stream);
+  }
+  for (void* x : pp->allocs) (void)hipFree(x);
+  if (pp->pw) fgt_destroy(pp->pw);
+  delete pp;
+}
+
+int setup(fgt_point_plan_t* pp, hipStream_t stream) {
+  fgt::PointHost& ph = pp->ph;
+  hipError_t e = hipGetDevice(&pp->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  pp->stream = stream;
+  int rc;
+  std::vector<double> eta, lam;
+  fgt::gl_barycentric(ph.p, eta, lam);
+  if ((rc = upload(pp, ph.src_perm, &pp->src_perm)) || (rc = upload(pp, ph.tgt_perm, &pp->tgt_perm)) ||
+      (rc = upload(pp, ph.leaf_src_start, &pp->leaf_src_start)) ||
+      (rc = upload(pp, ph.leaf_tgt_start, &pp->leaf_tgt_start)) || (rc = upload(pp, ph.dl_tgt, &pp->dl_tgt)) ||
+      (rc = upload(pp, ph.dl_haspw, &pp->dl_haspw)) || (rc = upload(pp, ph.dl_start, &pp->dl_start)) ||
+      (rc = upload(pp, ph.dl_src, &pp->dl_src)) || (rc = upload(pp, ph.px_src_start, &pp->px_src)) ||
+      (rc = upload(pp, ph.px_tgt_start, &pp->px_tgt)) || (rc = upload(pp, ph.px_coord, &pp->px_coord)) ||
+      (rc = upload(pp, ph.px_tgt_list, &pp->px_list)) || (rc = upload(pp, ph.src_xyz, &pp->src_xyz)) ||
+      (rc = upload(pp, ph.tgt_xyz, &pp->tgt_xyz)) || (rc = upload(pp, eta, &pp->eta)) ||
+      (rc = upload(pp, lam, &pp->lam)))
+    return rc;
+  const int64_t npx = (int64_t)ph.px_level.size();
+  int64_t pd = (int64_t)ph.p * ph.p;
+  if (ph.d == 3) pd *= ph.p;
+  if ((rc = alloc_doubles(pp, (size_t)(npx * pd), &pp->Q)) || (rc = alloc_doubles(pp, (size_t)(npx * pd), &pp->U)) ||
+      (rc = alloc_doubles(pp, (size_t)ph.ntgt, &pp->uw)))
+    return rc;
+  if (ph.n_pwbox > 0) {
+    fgt_plan_t* pw = new (std::nothrow) fgt_plan_t();
+    if (!pw) return fgt::set_error(FGT_ERR_OOM, "host allocation");
+    pw->hp = ph.hp;
+    pw->host_only = true;
+    if ((rc = fgt::plan_upload(pw, stream)) != FGT_OK) {
+      fgt_destroy(pw);
+      return rc;
+    }
+    pp->pw = pw;
+    pp->device_bytes += pw->device_bytes;
+  }
+  pp->host_only = false;
+  return FGT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fgt_point_plan(int dim, int64_t nsrc, const double* src, int64_t ntgt, const double* tgt, double delta,
+                   double tol, const fgt_point_opts_t* opts, fgt_point_plan_t** out) {
+  if (!out) return fgt::set_error(FGT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  fgt_point_opts_t o{};
+  if (opts) o = *opts;
+  const int p = o.p == 0 ? 16 : o.p, ns = o.ns == 0 ? 64 : o.ns;
+  fgt_point_plan_t* pp = new (std::nothrow) fgt_point_plan_t();
+  if (!pp) return fgt::set_error(FGT_ERR_OOM, "host allocation");
+  std::string err;
+  int rc;
+  try {
+    rc = fgt::build_point_plan(dim, nsrc, src, ntgt, tgt, delta, tol, p, ns, pp->ph, err);
+  } catch (const std::bad_alloc&) {
+    rc = FGT_ERR_OOM;
+    err = "host allocation";
+  } catch (...) {
+    rc = FGT_ERR_INVALID_ARG;
+    err = "unexpected exception while planning";
+  }
+  if (rc != FGT_OK) {
+    delete pp;
+    return fgt::set_error(rc, err);
+  }
+  if (!o.host_only) {
+    rc = setup(pp, static_cast<hipStream_t>(o.stream));
+    if (rc != FGT_OK) {
+      const std::string keep = fgt_last_error();
+      release(pp);
+      return fgt::set_error(rc, keep);
+    }
+  }
+  *out = pp;
+  return FGT_OK;
+}
+
+int fgt_point_execute(fgt_point_plan_t* pp, const double* q, double* u) {
+  if (!pp) return fgt::set_error(FGT_ERR_INVALID_ARG, "plan is NULL");
+  if (pp->host_only) return fgt::set_error(FGT_ERR_INVALID_ARG, "host-only plan cannot execute");
+  const fgt::PointHost& ph = pp->ph;
+  if ((ph.nsrc > 0 && !q) || (ph.ntgt > 0 && !u)) return fgt::set_error(FGT_ERR_INVALID_ARG, "q/u is NULL");
+  hipError_t e = hipSetDevice(pp->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (ph.ntgt == 0) return FGT_OK;
+  hipStream_t st = pp->stream;
+  const int d = ph.d;
+  const int64_t npx = (int64_t)ph.px_level.size();
+  if (pp->pw && npx > 0) {
+    if (d == 3)
+      hipLaunchKernelGGL(fgt::k_anterp<3>, dim3((unsigned)npx), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
+                         pp->px_src, pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->Q);
+    else
+      hipLaunchKernelGGL(fgt::k_anterp<2>, dim3((unsigned)npx), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
+                         pp->px_src, pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->Q);
+    int rc = fgt::execute_args(pp->pw->args, pp->Q, pp->U, st);
+    if (rc != FGT_OK) return rc;
+    const unsigned nb = (unsigned)ph.px_tgt_list.size();
+    if (nb > 0) {
+      if (d == 3)
+        hipLaunchKernelGGL(fgt::k_interp<3>, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->px_list, pp->px_tgt,
+                           pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->tgt_xyz, pp->uw);
+      else
+        hipLaunchKernelGGL(fgt::k_interp<2>, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->px_list, pp->px_tgt,
+                           pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->tgt_xyz, pp->uw);
+    }
+  }
+  const unsigned ndl = (unsigned)ph.dl_tgt.size();
+  if (ndl > 0) {
+    const double inv_delta = 1.0 / ph.delta;
+    if (d == 3)
+      hipLaunchKernelGGL(fgt::k_direct<3>, dim3(ndl), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
+                         pp->tgt_xyz, pp->tgt_perm, pp->leaf_src_start, pp->leaf_tgt_start, pp->dl_tgt, pp->dl_haspw,
+                         pp->dl_start, pp->dl_src, inv_delta, pp->uw, u);
+    else
+      hipLaunchKernelGGL(fgt::k_direct<2>, dim3(ndl), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
+                         pp->tgt_xyz, pp->tgt_perm, pp->leaf_src_start, pp->leaf_tgt_start, pp->dl_tgt, pp->dl_haspw,
+                         pp->dl_start, pp->dl_src, inv_delta, pp->uw, u);
+  }
+  e = hipGetLastError();
+  return e == hipSuccess ? FGT_OK : hip_fail(e, "kernel launch");
+}
+
+int fgt_point_info(const fgt_point_plan_t* pp, fgt_point_info_t* info) {
+  if (!pp || !info) return fgt::set_error(FGT_ERR_INVALID_ARG, "plan or info is NULL");
+  const fgt::PointHost& ph = pp->ph;
+  *info = fgt_point_info_t{};
+  info->dim = ph.d;
+  info->p = ph.p;
+  info->ns = ph.ns;
+  info->lc = ph.lc;
+  info->lp = ph.lp;
+  info->nr = ph.hp.nr;
+  info->nsrc = ph.nsrc;
+  info->ntgt = ph.ntgt;
+  info->nleaves = (int64_t)ph.leaf_level.size();
+  info->ndense = ph.n_dense;
+  info->npwbox = ph.n_pwbox;
+  info->nproxy = (int64_t)ph.px_level.size();
+  info->nplist = (int64_t)ph.hp.plist_src.size();
+  info->ndirect_terms = ph.n_direct_terms;
+  info->delta = ph.delta;
+  info->tol = ph.tol;
+  info->proxy_err = ph.proxy_err;
+  info->device_bytes = pp->device_bytes;
+  return FGT_OK;
+}
+
+int64_t fgt_point_array(const fgt_point_plan_t* pp, const char* name, void* dst, int64_t cap) {
+  if (!pp || !name) return fgt::set_error(FGT_ERR_INVALID_ARG, "plan or name is NULL");
+  const fgt::PointHost& ph = pp->ph;
+  const std::vector<int32_t>* v = nullptr;
+  const std::string n(name);
+  if (n == "leaf_level") v = &ph.leaf_level;
+  else if (n == "leaf_coord") v = &ph.leaf_coord;
+  else if (n == "leaf_dense") v = &ph.leaf_dense;
+  else if (n == "src_perm") v = &ph.src_perm;
+  else if (n == "tgt_perm") v = &ph.tgt_perm;
+  else if (n == "leaf_src_start") v = &ph.leaf_src_start;
+  else if (n == "leaf_tgt_start") v = &ph.leaf_tgt_start;
+  else if (n == "dl_tgt") v = &ph.dl_tgt;
+  else if (n == "dl_haspw") v = &ph.dl_haspw;
+  else if (n == "dl_start") v = &ph.dl_start;
+  else if (n == "dl_src") v = &ph.dl_src;
+  else if (n == "px_coord") v = &ph.px_coord;
+  else if (n == "px_src_start") v = &ph.px_src_start;
+  else if (n == "px_tgt_start") v = &ph.px_tgt_start;
+  else if (n == "plist_start") v = &ph.hp.plist_start;
+  else if (n == "plist_src") v = &ph.hp.plist_src;
+  else if (n == "plist_dir") v = &ph.hp.plist_dir;
+  else if (n == "pw_start") v = &ph.hp.pw_start;
+  else if (n == "pwleaf_id") v = &ph.hp.pwleaf_id;
+  else return fgt::set_error(FGT_ERR_INVALID_ARG, "unknown array " + n);
+  const int64_t len = (int64_t)v->size();
+  if (dst && cap > 0) std::memcpy(dst, v->data(), sizeof(int32_t) * (size_t)std::min<int64_t>(cap, len));
+  return len;
+}
+
+void fgt_point_destroy(fgt_point_plan_t* pp) { release(pp); }
+
+}  // extern "C"

@@ -190,7 +190,22 @@ void build_tables(HostPlan& hp) {
     const int l = hp.ftab_meta[id], pos = hp.ftab_meta[hp.nftab + id];
     const double L = std::ldexp(1.0, -l);
     const double shift = L * (pos + 0.5) - 0.5 * hp.Llc;  // c_S - c_A
-    for (int m = 0; m < M; m++) {
+    if (hp.point_tables) {
+      // point transform: the leaf's p^d values are charges at its nodes (a proxy
+      // grid), so F holds wh_r b_r(z_j - c_A) at the nodes z_j (Eq.
+      // (multipoleexpansion) for one charge) instead of integrals
+      double* Fo = &hp.F[(size_t)id * nr * p];
+      for (int j = 0; j < p; j++) {
+        const double z = shift + 0.5 * L * eta[j];
+        Fo[0 * p + j] = wm[0];
+        Fo[1 * p + j] = 0.0;  // the zero slot
+        for (int m = 1; m < M; m++) {
+          Fo[(2 * m) * p + j] = wm[m] * std::cos(km[m] * z);
+          Fo[(2 * m + 1) * p + j] = wm[m] * std::sin(km[m] * z);
+        }
+      }
+    }
+    for (int m = 0; m < M && !hp.point_tables; m++) {
       cos_sin_moments(p, km[m] * 0.5 * L, C.data(), S.data());
       const double cs = std::cos(km[m] * shift), sn = std::sin(km[m] * shift);
       const double sc = wm[m] * 0.5 * L;
@@ -207,7 +222,7 @@ void build_tables(HostPlan& hp) {
       }
     }
     double* Fo = &hp.F[(size_t)id * nr * p];
-    for (int r = 0; r < nr; r++)
+    for (int r = 0; r < nr && !hp.point_tables; r++)
       for (int j = 0; j < p; j++) {
         double s = 0.0;
         for (int n = 0; n < p; n++) s += Tpw[r * p + n] * V2P[n * p + j];
