@@ -38,7 +38,7 @@ PEAK_FP64 = 78.6e12   # dense FP64 matrix and vector, FLOP/s
 PEAK_FP32 = 157.3e12  # dense FP32, FLOP/s
 PEAK_HBM = 8.0e12     # bytes/s
 STAGES = ("form_leaf", "form_box", "translate", "eval_box", "eval_leaf", "near")
-CHILDREN = ("headline", "config0", "forms", "periodic", "precision", "batched", "served")
+CHILDREN = ("headline", "config0", "forms", "periodic", "precision", "batched", "served", "point")
 METRIC = "grid points/s at tol=1e-6 (3D adaptive), FP64 vs mixed; p50/p99 latency"
 
 
@@ -503,11 +503,63 @@ def child_served(ctx):
     return out
 
 
+def child_point(ctx):
+    """The point transform with proxy grids (fgt_point.h) on the paper's 3D
+    point workload shape (points on a surface, delta = 0.007 with N = 3.4e6):
+    3,400,000 points uniform on the sphere of radius 0.35 (synth.point_sphere,
+    seed + 300), each a source and a target, tol 1e-6, p = 16, n_s = 64.
+    Reports sources + targets per second of execute (plan time apart) and
+    saves 1,000 sampled targets for the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2305_07165_amd import api, synth
+    args = ctx.args
+    x, q = synth.point_sphere(args.seed + 300)
+    delta, tol = 0.007, 1e-6
+    tp = time.perf_counter()
+    pl = api.PointPlan(x, x, delta, tol, p=16, ns=64)
+    plan_ms = 1e3 * (time.perf_counter() - tp)
+    info = pl.info()
+    qd = torch.from_numpy(q).cuda()
+    u = torch.empty(len(x), dtype=torch.float64, device="cuda")
+    steps = max(5, args.steps // 2)
+    for _ in range(args.warmup):
+        pl.execute(qd, u)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        pl.execute(qd, u)
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = sorted(a.elapsed_time(b) for a, b in zip(starts, ends))
+    pl.close()
+    pick = np.random.default_rng(args.seed + 301).choice(len(x), 1000, replace=False)
+    ms = 1e3 * wall / steps
+    npts = 2 * len(x)
+    ctx.log(f"{len(x)} points on a sphere: lc={info['lc']} lp={info['lp']} dense={info['ndense']} "
+            f"proxies={info['nproxy']} direct terms={info['ndirect_terms']}; {ms:.3f} ms/execute, "
+            f"{npts / (ms * 1e-3):.3e} points/s, plan {plan_ms:.0f} ms")
+    arrays = {"src": ctx.save("src", x), "q": ctx.save("q", q), "tgt": ctx.save("tgt", x[pick]),
+              "u": ctx.save("u", u.cpu().numpy()[pick])}
+    return {"value": npts / (ms * 1e-3), "unit": "source+target points/s", "ms_per_execute": ms,
+            "p50_ms": pct(per, 50), "p99_ms": pct(per, 99), "plan_ms": plan_ms, "delta": delta, "tol": tol,
+            "workload": "3d points on a sphere (r = 0.35), 3.4e6 sources = targets, delta=0.007, tol 1e-6, "
+                        "p=16, n_s=64, seed %d" % (args.seed + 300),
+            "info": {k: info[k] for k in ("lc", "lp", "ndense", "npwbox", "nproxy", "nplist",
+                                          "ndirect_terms", "proxy_err")},
+            "point_arrays": arrays}
+
+
 # ---------------------------------------------------------------------------
 # parent: children in order, then the CPU leg
 
 
-CHILD_TIMEOUT_S = {"headline": 300, "config0": 120, "forms": 180, "periodic": 180, "precision": 240,
+CHILD_TIMEOUT_S = {"headline": 300, "config0": 120, "forms": 180, "periodic": 180, "precision": 240, "point": 180,
                    "batched": 300, "served": 300}
 
 
@@ -601,6 +653,18 @@ def cpu_leg(results, args, log):
             e["meets_tol"] = e["rel_l2"] < a["tol"] and e["max_abs_rel"] < a["tol"]
             acc[a["name"]] = e
             os.remove(a["path"])
+    pa = results.get("point", {}).get("point_arrays")
+    if pa:
+        src, q, tgt, ug = (np.load(pa[k]) for k in ("src", "q", "tgt", "u"))
+        t0 = time.perf_counter()
+        uo = oracle.oracle_point(src, q, tgt, results["point"]["delta"])
+        log(f"oracle: point transform at {len(tgt)} sampled targets: {time.perf_counter() - t0:.1f}s")
+        acc["point"] = {"rel_l2": float(np.linalg.norm(ug - uo) / np.linalg.norm(uo)),
+                        "max_abs_rel": float(np.max(np.abs(ug - uo)) / np.max(np.abs(uo))), "tol": 1e-6,
+                        "nodes_compared": int(len(tgt)), "sampled": True}
+        acc["point"]["meets_tol"] = acc["point"]["rel_l2"] < 1e-6 and acc["point"]["max_abs_rel"] < 1e-6
+        for k in pa.values():
+            os.remove(k)
     return acc, cpu
 
 
@@ -617,6 +681,8 @@ def attach_accuracy(forms, acc):
             a = acc.get(f"{key}_{k}")
             if isinstance(v, dict) and a:
                 v["accuracy"] = a
+    if "point" in forms and "point" in acc:
+        forms["point"]["accuracy"] = acc["point"]
     c0 = forms.get("config0", {})
     for k in ("auto", "forced_lc2"):
         if k in c0 and f"config0_{k}" in acc:
@@ -629,7 +695,7 @@ def parent(args):
 
     skip = set()
     if args.no_forms:
-        skip |= {"forms", "periodic", "precision", "batched", "served"}
+        skip |= {"forms", "periodic", "precision", "batched", "served", "point"}
     if args.no_batch:
         skip.add("batched")
     if args.no_serve:
@@ -655,9 +721,9 @@ def parent(args):
                 if head.get("value"):
                     v["speedup_vs_fp64_tol1e-6"] = v["value"] / head["value"]
                 forms[k] = v
-    for name in ("config0", "precision", "batched", "served"):
+    for name in ("config0", "precision", "batched", "served", "point"):
         if name in results:
-            forms[name] = {k: v for k, v in results[name].items() if k != "arrays"}
+            forms[name] = {k: v for k, v in results[name].items() if k not in ("arrays", "point_arrays")}
     attach_accuracy(forms, acc)
     for name in ("forms", "periodic"):
         if name in results and results[name].get("rc"):

@@ -293,6 +293,17 @@ def _blobs(rng, n, d, lo, hi, wlo, whi, log_widths):
     return centers, widths, amps
 
 
+def point_sphere(seed: int = 0, n: int = 3_400_000, radius: float = 0.35):
+    """Point workload after the paper's 3D point-transform experiment (points
+    on a surface, so that the tree must refine): n points uniform on the
+    sphere of the given radius about the box center, charges U(-1,1); the
+    points are both the sources and the targets.  Returns (points, charges)."""
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0.0, 1.0, (n, 3))
+    x = radius * x / np.linalg.norm(x, axis=1)[:, None]
+    return x, rng.uniform(-1.0, 1.0, n)
+
+
 def small_2d(seed: int = 0) -> Problem:
     """2D free space, uniform level-3 tree (64 leaves) on [-1/2,1/2]^2, p=8
     (4096 points), delta=1e-3, four Gaussians with centers U[-0.3,0.3]^2,

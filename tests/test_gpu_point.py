@@ -14,7 +14,7 @@ import pytest
 
 import closed_forms as cf
 import oracle
-from paper_2305_07165_amd import api
+from paper_2305_07165_amd import api, synth
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -81,24 +81,22 @@ def test_point_parity(name, d, nsrc, ntgt, delta, tol, p, ns, seed):
 
 
 def test_point_large_sampled():
-    """3D, 400,000 sources and targets in clusters and a uniform background,
-    delta = 1e-4, tol 1e-6: 4,000 targets checked one by one against the
-    oracle's direct sum over every source."""
-    d, n = 3, 400_000
-    src, tgt, q = _points(d, n, n, 11)
-    pl = api.PointPlan(src, tgt, 1e-4, 1e-6, p=16, ns=64)
+    """The paper's first 3D point workload shape: 1,000,000 points on a sphere
+    (each a source and a target), delta = 0.01, tol 1e-6; 2,000 targets
+    checked one by one against the oracle's direct sum over every source."""
+    x, q = synth.point_sphere(5, 1_000_000)
+    pl = api.PointPlan(x, x, 0.01, 1e-6, p=16, ns=64)
     info = pl.info()
-    _say(f"large: lc={info['lc']} lp={info['lp']} dense={info['ndense']} proxies={info['nproxy']} "
+    _say(f"sphere: lc={info['lc']} lp={info['lp']} dense={info['ndense']} proxies={info['nproxy']} "
          f"direct terms={info['ndirect_terms']}")
     u = pl.execute(torch.from_numpy(q).cuda())
     torch.cuda.synchronize()
     ug = u.cpu().numpy()
-    rng = np.random.default_rng(12)
-    pick = rng.choice(n, 4000, replace=False)
-    uo = oracle.oracle_point(src, q, tgt[pick], 1e-4)
+    pick = np.random.default_rng(12).choice(len(x), 2000, replace=False)
+    uo = oracle.oracle_point(x, q, x[pick], 0.01)
     err = float(np.linalg.norm(ug[pick] - uo) / np.linalg.norm(uo))
     emax = float(np.max(np.abs(ug[pick] - uo)) / np.max(np.abs(uo)))
-    _say(f"large: sampled rel_l2={err:.3e} max_rel={emax:.3e}")
+    _say(f"sphere: sampled rel_l2={err:.3e} max_rel={emax:.3e}")
     assert err < 1e-6 and emax < 1e-6
     pl.close()
 
