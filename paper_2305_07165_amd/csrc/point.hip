@@ -34,7 +34,12 @@ __device__ __forceinline__ void lagrange(int p, double t, const double* __restri
   for (int k = 0; k < kPMax; k++) {
     const double dt = k < p ? t - eta[k] : 1.0;
     if (k < p && dt == 0.0) hit = k;
-    w[k] = (k < p && dt != 0.0) ? lam[k] / dt : 0.0;
+    // 1/dt: the hardware estimate refined by two Newton steps (each doubles the
+    // correct bits), instead of a full division per node
+    double r = __builtin_amdgcn_rcp(dt);
+    r = fma(r, fma(-dt, r, 1.0), r);
+    r = fma(r, fma(-dt, r, 1.0), r);
+    w[k] = (k < p && dt != 0.0) ? lam[k] * r : 0.0;
     den += w[k];
   }
   const double inv = hit >= 0 ? 0.0 : 1.0 / den;
@@ -51,23 +56,29 @@ __device__ __forceinline__ double local_coord(double x, int l, int32_t c) {
 }
 
 // 1. Proxy charges of one grid: Q[k] = sum over its sources of
-// prod_a l_{k_a}(t_a) q, node k = k_1 + p k_2 (+ p^2 k_3).  Sources come in
-// chunks whose weights are computed once into LDS.
+// prod_a l_{k_a}(t_a) q, node k = k_1 + p k_2 (+ p^2 k_3).  Thread (k_1, k_2) =
+// (tid % 16, tid / 16) owns the nodes k_3 = 0..15 of its column; sources come
+// in chunks whose per-axis weights are computed once into LDS, and per source
+// a thread forms l_{k_1} l_{k_2} q once and scales the broadcast axis-3
+// weights by it.
+// Work item (grid, first source, end source, partial slot): a grid's sources
+// are split into parts of at most kAnterpPart, each summed by one workgroup
+// into its slot of `partial` (or straight into Q when the grid has one part);
+// k_anterp_reduce then adds a grid's parts in order.
 template <int D>
 __global__ __launch_bounds__(kPT) void k_anterp(const double* __restrict__ q, const int32_t* __restrict__ src_perm,
                                                 const double* __restrict__ src_xyz,
-                                                const int32_t* __restrict__ px_src,
+                                                const int32_t* __restrict__ items,
                                                 const int32_t* __restrict__ px_coord, int lp, int p,
                                                 const double* __restrict__ eta, const double* __restrict__ lam,
-                                                double* __restrict__ Q) {
-  constexpr int CH = 32;
-  constexpr int NE = D == 3 ? (kPMax * kPMax * kPMax + kPT - 1) / kPT : 1;
-  __shared__ double W[CH][D][kPMax];
+                                                double* __restrict__ Q, double* __restrict__ partial) {
+  constexpr int CH = 64;
+  constexpr int NE = D == 3 ? kPMax : 1;
+  __shared__ __align__(16) double W[CH][D][kPMax];
   __shared__ double qs[CH];
-  const int b = blockIdx.x, tid = threadIdx.x;
-  const int s0 = px_src[2 * b], s1 = px_src[2 * b + 1];
-  int pd = p * p;
-  if (D == 3) pd *= p;
+  const int b = items[4 * blockIdx.x], slot = items[4 * blockIdx.x + 3], tid = threadIdx.x;
+  const int k1 = tid & 15, k2 = tid >> 4;
+  const int s0 = items[4 * blockIdx.x + 1], s1 = items[4 * blockIdx.x + 2];
   double acc[NE];
 #pragma unroll
   for (int j = 0; j < NE; j++) acc[j] = 0.0;
@@ -84,70 +95,103 @@ __global__ __launch_bounds__(kPT) void k_anterp(const double* __restrict__ q, co
     if (tid < nc) qs[tid] = q[src_perm[c0 + tid]];
     __syncthreads();
     for (int s = 0; s < nc; s++) {
+      const double w12 = W[s][0][k1] * W[s][1][k2] * qs[s];
+      if (D == 3) {
+        const double2* w3 = reinterpret_cast<const double2*>(&W[s][D - 1][0]);
 #pragma unroll
-      for (int j = 0; j < NE; j++) {
-        const int e = tid + kPT * j;
-        if (e < pd) {
-          const int k1 = e % p, k2 = (e / p) % p;
-          double v = W[s][0][k1] * W[s][1][k2] * qs[s];
-          if (D == 3) v *= W[s][2][e / (p * p)];
-          acc[j] += v;
+        for (int j = 0; j < kPMax / 2; j++) {
+          const double2 v = w3[j];  // the same words in every lane: a broadcast
+          acc[2 * j] += w12 * v.x;
+          acc[2 * j + 1] += w12 * v.y;
         }
+      } else {
+        acc[0] += w12;
       }
     }
     __syncthreads();
   }
+  if (k1 < p && k2 < p) {
+    int64_t pd = (int64_t)p * p;
+    if (D == 3) pd *= p;
+    double* out = slot >= 0 ? partial + (int64_t)slot * pd : Q + (int64_t)b * pd;
 #pragma unroll
-  for (int j = 0; j < NE; j++) {
-    const int e = tid + kPT * j;
-    if (e < pd) Q[(int64_t)b * pd + e] = acc[j];
+    for (int j = 0; j < NE; j++)
+      if (j < (D == 3 ? p : 1)) out[k1 + p * k2 + (int64_t)p * p * j] = acc[j];
   }
 }
 
-// 3. The grid potential of one plane-wave box's grid at its targets (written
-// at their sorted positions).
+// Q of a grid split into parts: the parts' sums added in part order.  Item =
+// (grid, first slot, parts).
+__global__ __launch_bounds__(kPT) void k_anterp_reduce(const int32_t* __restrict__ items,
+                                                       const double* __restrict__ partial, int pd,
+                                                       double* __restrict__ Q) {
+  const int b = items[3 * blockIdx.x], slot0 = items[3 * blockIdx.x + 1], n = items[3 * blockIdx.x + 2];
+  for (int e = threadIdx.x; e < pd; e += kPT) {
+    double sum = 0.0;
+    for (int i = 0; i < n; i++) sum += partial[(int64_t)(slot0 + i) * pd + e];
+    Q[(int64_t)b * pd + e] = sum;
+  }
+}
+
+// 3. The grid potential of one plane-wave box's grid at one chunk of its
+// targets (written at their sorted positions): work item = (grid, chunk of
+// kPT targets).  The grid sits in LDS; every lane reads the same node at the
+// same time.
 template <int D>
-__global__ __launch_bounds__(kPT) void k_interp(const double* __restrict__ U, const int32_t* __restrict__ px_list,
+__global__ __launch_bounds__(kPT) void k_interp(const double* __restrict__ U, const int32_t* __restrict__ items,
                                                 const int32_t* __restrict__ px_tgt,
                                                 const int32_t* __restrict__ px_coord, int lp, int p,
                                                 const double* __restrict__ eta, const double* __restrict__ lam,
                                                 const double* __restrict__ tgt_xyz, double* __restrict__ uw) {
-  __shared__ double Us[kPMax * kPMax * (D == 3 ? kPMax : 1)];
-  const int b = px_list[blockIdx.x], tid = threadIdx.x;
+  __shared__ __align__(16) double Us[kPMax * kPMax * (D == 3 ? kPMax : 1)];
+  const int b = items[2 * blockIdx.x], tb = items[2 * blockIdx.x + 1], tid = threadIdx.x;
   int pd = p * p;
   if (D == 3) pd *= p;
-  for (int e = tid; e < pd; e += kPT) Us[e] = U[(int64_t)b * pd + e];
-  __syncthreads();
-  const int t0 = px_tgt[2 * b], t1 = px_tgt[2 * b + 1];
-  for (int pos = t0 + tid; pos < t1; pos += kPT) {
-    double w1[kPMax], w2[kPMax], w3[kPMax];
-    lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 0], lp, px_coord[(int64_t)b * D + 0]), eta, lam, w1);
-    lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 1], lp, px_coord[(int64_t)b * D + 1]), eta, lam, w2);
-    if (D == 3)
-      lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 2], lp, px_coord[(int64_t)b * D + 2]), eta, lam, w3);
-    double u = 0.0;
-#pragma unroll
-    for (int k3 = 0; k3 < (D == 3 ? kPMax : 1); k3++) {
-      if (k3 >= p) break;
-      double s3 = 0.0;
-#pragma unroll
-      for (int k2 = 0; k2 < kPMax; k2++) {
-        if (k2 >= p) break;
-        const double* row = Us + (k3 * p + k2) * p;
-        double s2 = 0.0;
-#pragma unroll
-        for (int k1 = 0; k1 < kPMax; k1++)
-          if (k1 < p) s2 += w1[k1] * row[k1];
-        s3 += w2[k2] * s2;
-      }
-      u += (D == 3 ? w3[k3] : 1.0) * s3;
-    }
-    uw[pos] = u;
+  // node (k1, k2, k3) at k1 + 16 k2 + 256 k3 in LDS (rows 16-aligned), zero
+  // past p
+  for (int e = tid; e < kPMax * kPMax * (D == 3 ? kPMax : 1); e += kPT) {
+    const int k1 = e % kPMax, k2 = (e / kPMax) % kPMax, k3 = e / (kPMax * kPMax);
+    const bool in = k1 < p && k2 < p && k3 < (D == 3 ? p : 1);
+    Us[e] = in ? U[(int64_t)b * pd + k1 + p * k2 + p * p * k3] : 0.0;
   }
+  __syncthreads();
+  const int t1 = px_tgt[2 * b + 1];
+  const int pos = tb + tid;
+  if (pos >= t1) return;
+  double w1[kPMax], w2[kPMax], w3[kPMax];
+  lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 0], lp, px_coord[(int64_t)b * D + 0]), eta, lam, w1);
+  lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 1], lp, px_coord[(int64_t)b * D + 1]), eta, lam, w2);
+  if (D == 3)
+    lagrange(p, local_coord(tgt_xyz[(int64_t)pos * D + 2], lp, px_coord[(int64_t)b * D + 2]), eta, lam, w3);
+  double u = 0.0;
+  for (int k3 = 0; k3 < (D == 3 ? p : 1); k3++) {
+    double s3 = 0.0;
+    for (int k2 = 0; k2 < p; k2++) {
+      const double2* row = reinterpret_cast<const double2*>(Us + kPMax * k2 + kPMax * kPMax * k3);
+      double s2 = 0.0;
+#pragma unroll
+      for (int h = 0; h < kPMax / 2; h++) {
+        const double2 v = row[h];  // weights past p are zero
+        s2 += w1[2 * h] * v.x + w1[2 * h + 1] * v.y;
+      }
+      double wk2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kPMax; k++) wk2 = k == k2 ? w2[k] : wk2;
+      s3 += wk2 * s2;
+    }
+    double wk3 = 1.0;
+    if (D == 3) {
+#pragma unroll
+      for (int k = 0; k < kPMax; k++) wk3 = k == k3 ? w3[k] : wk3;
+    }
+    u += wk3 * s3;
+  }
+  uw[pos] = u;
 }
 
-// 4. One leaf's targets: the sum over the sources of its D-list, in a fixed
-// order, plus the plane-wave part when the leaf has one; u in the caller's order.
+// 4. One chunk of kPT targets of a leaf (work item = (leaf, first target)):
+// the sum over the sources of its D-list, in a fixed order, plus the
+// plane-wave part when the leaf has one; u in the caller's order.
 template <int D>
 __global__ __launch_bounds__(kPT) void k_direct(const double* __restrict__ q, const int32_t* __restrict__ src_perm,
                                                 const double* __restrict__ src_xyz,
@@ -158,15 +202,17 @@ __global__ __launch_bounds__(kPT) void k_direct(const double* __restrict__ q, co
                                                 const int32_t* __restrict__ dl_tgt,
                                                 const int32_t* __restrict__ dl_haspw,
                                                 const int32_t* __restrict__ dl_start,
-                                                const int32_t* __restrict__ dl_src, double inv_delta,
+                                                const int32_t* __restrict__ dl_src,
+                                                const int32_t* __restrict__ items, double inv_delta,
                                                 const double* __restrict__ uw, double* __restrict__ u) {
   __shared__ double ys[kPT][D + 1];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = items[2 * blockIdx.x], tid = threadIdx.x;
   const int T = dl_tgt[k];
   const bool haspw = dl_haspw[k] != 0;
-  const int t0 = leaf_tgt_start[T], t1 = leaf_tgt_start[T + 1];
+  const int t1 = leaf_tgt_start[T + 1];
   const int e0 = dl_start[k], e1 = dl_start[k + 1];
-  for (int tb = t0; tb < t1; tb += kPT) {
+  {
+    const int tb = items[2 * blockIdx.x + 1];
     const int pos = tb + tid;
     const bool mine = pos < t1;
     double x[3] = {0.0, 0.0, 0.0};
@@ -214,7 +260,9 @@ struct fgt_point_plan {
   // device arrays
   int32_t *src_perm = nullptr, *tgt_perm = nullptr, *leaf_src_start = nullptr, *leaf_tgt_start = nullptr;
   int32_t *dl_tgt = nullptr, *dl_haspw = nullptr, *dl_start = nullptr, *dl_src = nullptr;
-  int32_t *px_src = nullptr, *px_tgt = nullptr, *px_coord = nullptr, *px_list = nullptr;
+  int32_t *px_src = nullptr, *px_tgt = nullptr, *px_coord = nullptr;
+  int32_t *interp_items = nullptr, *direct_items = nullptr, *anterp_items = nullptr, *reduce_items = nullptr;
+  double* partial = nullptr;
   double *src_xyz = nullptr, *tgt_xyz = nullptr, *eta = nullptr, *lam = nullptr;
   double *Q = nullptr, *U = nullptr, *uw = nullptr;
 };
@@ -277,7 +325,9 @@ int setup(fgt_point_plan_t* pp, hipStream_t stream) {
       (rc = upload(pp, ph.dl_haspw, &pp->dl_haspw)) || (rc = upload(pp, ph.dl_start, &pp->dl_start)) ||
       (rc = upload(pp, ph.dl_src, &pp->dl_src)) || (rc = upload(pp, ph.px_src_start, &pp->px_src)) ||
       (rc = upload(pp, ph.px_tgt_start, &pp->px_tgt)) || (rc = upload(pp, ph.px_coord, &pp->px_coord)) ||
-      (rc = upload(pp, ph.px_tgt_list, &pp->px_list)) || (rc = upload(pp, ph.src_xyz, &pp->src_xyz)) ||
+      (rc = upload(pp, ph.interp_items, &pp->interp_items)) ||
+      (rc = upload(pp, ph.anterp_items, &pp->anterp_items)) || (rc = upload(pp, ph.reduce_items, &pp->reduce_items)) ||
+      (rc = upload(pp, ph.direct_items, &pp->direct_items)) || (rc = upload(pp, ph.src_xyz, &pp->src_xyz)) ||
       (rc = upload(pp, ph.tgt_xyz, &pp->tgt_xyz)) || (rc = upload(pp, eta, &pp->eta)) ||
       (rc = upload(pp, lam, &pp->lam)))
     return rc;
@@ -285,6 +335,7 @@ int setup(fgt_point_plan_t* pp, hipStream_t stream) {
   int64_t pd = (int64_t)ph.p * ph.p;
   if (ph.d == 3) pd *= ph.p;
   if ((rc = alloc_doubles(pp, (size_t)(npx * pd), &pp->Q)) || (rc = alloc_doubles(pp, (size_t)(npx * pd), &pp->U)) ||
+      (rc = alloc_doubles(pp, (size_t)(ph.n_anterp_slots * pd), &pp->partial)) ||
       (rc = alloc_doubles(pp, (size_t)ph.ntgt, &pp->uw)))
     return rc;
   if (ph.n_pwbox > 0) {
@@ -355,35 +406,39 @@ int fgt_point_execute(fgt_point_plan_t* pp, const double* q, double* u) {
   const int d = ph.d;
   const int64_t npx = (int64_t)ph.px_level.size();
   if (pp->pw && npx > 0) {
+    const unsigned na = (unsigned)(ph.anterp_items.size() / 4), nred = (unsigned)(ph.reduce_items.size() / 3);
     if (d == 3)
-      hipLaunchKernelGGL(fgt::k_anterp<3>, dim3((unsigned)npx), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
-                         pp->px_src, pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->Q);
+      hipLaunchKernelGGL(fgt::k_anterp<3>, dim3(na), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
+                         pp->anterp_items, pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->Q, pp->partial);
     else
-      hipLaunchKernelGGL(fgt::k_anterp<2>, dim3((unsigned)npx), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
-                         pp->px_src, pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->Q);
+      hipLaunchKernelGGL(fgt::k_anterp<2>, dim3(na), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
+                         pp->anterp_items, pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->Q, pp->partial);
+    if (nred > 0)
+      hipLaunchKernelGGL(fgt::k_anterp_reduce, dim3(nred), dim3(fgt::kPT), 0, st, pp->reduce_items, pp->partial,
+                         (int)(d == 3 ? ph.p * ph.p * ph.p : ph.p * ph.p), pp->Q);
     int rc = fgt::execute_args(pp->pw->args, pp->Q, pp->U, st);
     if (rc != FGT_OK) return rc;
-    const unsigned nb = (unsigned)ph.px_tgt_list.size();
+    const unsigned nb = (unsigned)(ph.interp_items.size() / 2);
     if (nb > 0) {
       if (d == 3)
-        hipLaunchKernelGGL(fgt::k_interp<3>, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->px_list, pp->px_tgt,
+        hipLaunchKernelGGL(fgt::k_interp<3>, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->interp_items, pp->px_tgt,
                            pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->tgt_xyz, pp->uw);
       else
-        hipLaunchKernelGGL(fgt::k_interp<2>, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->px_list, pp->px_tgt,
+        hipLaunchKernelGGL(fgt::k_interp<2>, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->interp_items, pp->px_tgt,
                            pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->tgt_xyz, pp->uw);
     }
   }
-  const unsigned ndl = (unsigned)ph.dl_tgt.size();
+  const unsigned ndl = (unsigned)(ph.direct_items.size() / 2);
   if (ndl > 0) {
     const double inv_delta = 1.0 / ph.delta;
     if (d == 3)
       hipLaunchKernelGGL(fgt::k_direct<3>, dim3(ndl), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
                          pp->tgt_xyz, pp->tgt_perm, pp->leaf_src_start, pp->leaf_tgt_start, pp->dl_tgt, pp->dl_haspw,
-                         pp->dl_start, pp->dl_src, inv_delta, pp->uw, u);
+                         pp->dl_start, pp->dl_src, pp->direct_items, inv_delta, pp->uw, u);
     else
       hipLaunchKernelGGL(fgt::k_direct<2>, dim3(ndl), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
                          pp->tgt_xyz, pp->tgt_perm, pp->leaf_src_start, pp->leaf_tgt_start, pp->dl_tgt, pp->dl_haspw,
-                         pp->dl_start, pp->dl_src, inv_delta, pp->uw, u);
+                         pp->dl_start, pp->dl_src, pp->direct_items, inv_delta, pp->uw, u);
   }
   e = hipGetLastError();
   return e == hipSuccess ? FGT_OK : hip_fail(e, "kernel launch");

@@ -471,6 +471,31 @@ int build_point_plan(int d, int64_t nsrc, const double* src, int64_t ntgt, const
     ph.n_direct_terms += terms * ltgt[T];
   }
   ph.dl_start.push_back((int32_t)ph.dl_src.size());
+  constexpr int32_t kChunk = 256;  // threads per workgroup of the device kernels
+  constexpr int32_t kAnterpPart = 1024;
+  for (int64_t x = 0; x < npx; x++) {
+    const int32_t a0 = ph.px_src_start[2 * x], a1 = ph.px_src_start[2 * x + 1];
+    const int32_t parts = std::max<int32_t>(1, (a1 - a0 + kAnterpPart - 1) / kAnterpPart);
+    if (parts == 1) {
+      ph.anterp_items.insert(ph.anterp_items.end(), {(int32_t)x, a0, a1, -1});
+      continue;
+    }
+    const int32_t slot0 = (int32_t)ph.n_anterp_slots;
+    for (int32_t i = 0; i < parts; i++)
+      ph.anterp_items.insert(ph.anterp_items.end(),
+                             {(int32_t)x, a0 + i * kAnterpPart, std::min(a1, a0 + (i + 1) * kAnterpPart),
+                              slot0 + i});
+    ph.reduce_items.insert(ph.reduce_items.end(), {(int32_t)x, slot0, parts});
+    ph.n_anterp_slots += parts;
+  }
+  for (int32_t x : ph.px_tgt_list)
+    for (int32_t tb = ph.px_tgt_start[2 * x]; tb < ph.px_tgt_start[2 * x + 1]; tb += kChunk)
+      ph.interp_items.insert(ph.interp_items.end(), {x, tb});
+  for (size_t k = 0; k < ph.dl_tgt.size(); k++) {
+    const int32_t T = ph.dl_tgt[k];
+    for (int32_t tb = ph.leaf_tgt_start[T]; tb < ph.leaf_tgt_start[T + 1]; tb += kChunk)
+      ph.direct_items.insert(ph.direct_items.end(), {(int32_t)k, tb});
+  }
   return FGT_OK;
 }
 

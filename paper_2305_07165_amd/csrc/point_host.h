@@ -41,6 +41,14 @@ struct PointHost {
                                                     // points of each proxy box (sources: dense
                                                     // boxes only)
   std::vector<int32_t> px_tgt_list;                 // proxy boxes holding targets
+  // work items of 256 targets: (proxy box, first sorted target) for the
+  // interpolation, (D-list entry, first sorted target) for the direct sums
+  std::vector<int32_t> interp_items, direct_items;
+  // anterpolation items (proxy box, first source, end source, partial slot or
+  // -1) with at most kAnterpPart sources each; grids of several parts are
+  // summed by the reduce items (proxy box, first slot, parts)
+  std::vector<int32_t> anterp_items, reduce_items;
+  int64_t n_anterp_slots = 0;
 
   // the plane-wave stages over the proxy boxes (box Gauss transform kernels)
   HostPlan hp;
