@@ -453,6 +453,7 @@ def child_batched(ctx):
             "npoints": npts, "sequential_fp64_ms": 1e3 * dt64, "sequential_same_precision_ms": 1e3 * dtmix,
             "speedup_vs_sequential_fp64": dt64 / dt, "speedup_vs_sequential_same_precision": dtmix / dt,
             "bitwise_equal_to_sequential": same, "schedule": "per-class launches, one stream, one HIP graph",
+            "persistent": "switched off: one persistent launch per kernel class did not finish on the device",
             "nclasses": info["nclasses"], "nlaunches": info["nlaunches"],
             "precisions": {"fp32": sum(t.precision == "fp32" for t in probs),
                            "fp64": sum(t.precision == "fp64" for t in probs)}}

@@ -41,6 +41,12 @@ typedef struct fgt_batch_opts {
                           0 = stage by stage across its classes */
   int32_t form_tile;   /* box-formation tile shape of every d = 3 class: 0 (default) = four
                           16-column slabs per wave, as fgt_execute; 1 = two */
+  int32_t persistent;  /* 1 = one persistent launch per kernel class running every stage of
+                          every transform of the class (a work queue in stage order; a block
+                          waits, with a device-scope acquire, for its transform's previous
+                          stage).  Switched off: fgt_batch_create returns FGT_ERR_UNSUPPORTED
+                          (on the device such a batch did not finish).  0 (default) = one
+                          launch per class and stage */
 } fgt_batch_opts_t;
 
 typedef struct fgt_batch_info {
@@ -51,6 +57,10 @@ typedef struct fgt_batch_info {
   int32_t nstreams, class_major, use_graph;
   double tuned_ms;      /* 0: the autotuner is switched off (fgt_batch_tune) */
   int32_t tile_alt_classes; /* classes whose box formation runs the alternative tile shape */
+  int32_t persistent;       /* classes run as one persistent launch each */
+  int32_t persistent_error; /* 1 if a persistent launch's bounded wait ran out since the batch
+                               was created (read after a device synchronize; its results are
+                               then not to be used) */
 } fgt_batch_info_t;
 
 /* Builds a batch over nplans resident plans (not host-only, all on the current

@@ -114,7 +114,7 @@ class fgt_server_stats_t(ctypes.Structure):
 class fgt_batch_opts_t(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
                 ("nstreams", ctypes.c_int32), ("class_major", ctypes.c_int32),
-                ("form_tile", ctypes.c_int32)]
+                ("form_tile", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class fgt_batch_info_t(ctypes.Structure):
@@ -122,7 +122,8 @@ class fgt_batch_info_t(ctypes.Structure):
                 ("nclasses", ctypes.c_int32), ("nsingle", ctypes.c_int32),
                 ("nlaunches", ctypes.c_int32), ("nstreams", ctypes.c_int32),
                 ("class_major", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("tuned_ms", ctypes.c_double), ("tile_alt_classes", ctypes.c_int32)]
+                ("tuned_ms", ctypes.c_double), ("tile_alt_classes", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("persistent_error", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

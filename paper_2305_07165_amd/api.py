@@ -328,10 +328,11 @@ class Server:
 
 
 def fgt_batch_create(plans, stream: int = 0, use_graph: bool = True, nstreams: int = 1,
-                     class_major: bool = False, form_tile: int = 0) -> int:
+                     class_major: bool = False, form_tile: int = 0, persistent: bool = False) -> int:
     handles = (ctypes.c_void_p * len(plans))(*[int(p) for p in plans])
     opts = _lib.fgt_batch_opts_t(ctypes.c_void_p(int(stream) or None), int(bool(use_graph)),
-                                 int(nstreams), int(bool(class_major)), int(form_tile))
+                                 int(nstreams), int(bool(class_major)), int(form_tile),
+                                 int(bool(persistent)))
     h = ctypes.c_void_p()
     check(_lib.lib().fgt_batch_create(handles, len(plans), ctypes.byref(opts), ctypes.byref(h)),
           "fgt_batch_create")
@@ -370,14 +371,14 @@ class Batch:
     default it runs on torch's current stream."""
 
     def __init__(self, plans, stream=None, use_graph: bool = True, nstreams: int = 1,
-                 class_major: bool = False, form_tile: int = 0):
+                 class_major: bool = False, form_tile: int = 0, persistent: bool = False):
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
         self.plans = list(plans)
         self.handle = 0
         self.handle = fgt_batch_create([p.handle for p in self.plans], int(stream or 0),
-                                       use_graph, nstreams, class_major, form_tile)
+                                       use_graph, nstreams, class_major, form_tile, persistent)
         self._bound = None
 
     def bind(self, sigmas, us):

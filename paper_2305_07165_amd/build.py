@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfgt.so")
 
 HOST_SRC = ["plan.cpp", "tables.cpp", "output_host.cpp", "point_host.cpp"]
-HIP_SRC = ["kernels.hip", "kernels_fast.hip", "api.hip", "serve.hip", "batch.hip", "output.hip", "point.hip"]
+HIP_SRC = ["persist.hip", "kernels.hip", "kernels_fast.hip", "api.hip", "serve.hip", "batch.hip", "output.hip", "point.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -101,6 +101,20 @@ template <typename T>
 void launch_translate_batched(int d, const BatchJob* jobs, const int32_t* start,
                               const int32_t* count, int njobs, int64_t grid, hipStream_t st);
 
+// Persistent batched execution (persist.hip): one launch of `grid` workgroups
+// runs every stage of the njobs transforms of class c.  start/count hold the
+// per-stage block ranges ([kNumStages][njobs], as launch_stage_batched takes
+// them, tile 0), stage_base[s] the first work item of stage s (stage_base
+// [kNumStages] = all items), head the work queue (zero before the launch) and
+// ctl[0] an error flag and ctl[1 + j kNumStages + s] the finished blocks of
+// stage s of job j (zero before the launch).
+bool persistent_supported(const KernelClass& c);
+hipError_t launch_class_persistent(const KernelClass& c, const BatchJob* jobs, const int32_t* start,
+                                   const int32_t* count, int njobs, const int64_t* stage_base, uint64_t* head,
+                                   int32_t* ctl, int spin_limit, int grid, hipStream_t st);
+// Zeroes n int32 by a kernel (graph-capture safe, unlike a memset node).
+hipError_t zero_i32(int32_t* p, int64_t n, hipStream_t st);
+
 // Dynamic LDS bytes of the stages that stage data in LDS.
 size_t lds_form_leaf(int d, int p, int nr, size_t tsize);
 size_t lds_eval_leaf(int d, int p, int nr, size_t tsize);

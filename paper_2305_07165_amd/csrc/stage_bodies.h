@@ -1,0 +1,1027 @@
+// Device bodies of the tuned stages of the box Gauss transform (d = 2, 3),
+// shared by the per-stage kernels (kernels_fast.hip) and the persistent
+// batched kernels (persist.hip).
+//
+// Tile counts are compile time: NT = ceil(nr/16) mode tiles per axis and
+// KS = ceil(p/4) node steps (FP32 always runs 4 node steps, see mfma.h).
+// Node axes are padded to 16 inside a tile.  Chained contractions pass result
+// tiles from one matrix-core product to the next in registers (mfma.h); LDS is
+// used only where a contraction runs across the tiles held by different waves.
+//
+// d = 3:
+//   form3_plane Y_P[j3][r1][r2] = sum_{rows} F1_row[r1][j1] (sum_{s in row} sum_j2 sigma_s[j3][j2][j1] F2_s[r2][j2])
+//   form_box    phi_A[r3][c]    = sum_{P in A} sum_j3 F3_P[r3][j3] Y_P[j3][c]
+//   translate   psi_A = sum_{B in P(A)} Rot(c_B - c_A) phi_B        (kernels.hip)
+//   eval_box    Z_P[i3][c]      = sum_r3 E3_P[i3][r3] psi_A[r3][c]
+//   eval3_plane u_s[i3][i2][i1] = sum_r2 E2_s[i2][r2] (sum_r1 Z_P[i3][r1][r2] E1_row[i1][r1])
+// (P: a plane of leaves sharing level and axis-3 table; row: leaves of a plane
+// sharing the axis-1 table.  Grouping the sums this way is exact: each table
+// factor is applied once to the sum of everything it multiplies.)
+//   near3       u_T (+)= sum_S (V3 (x) V2 (x) V1) sigma_S, grouped by tables
+// The mode tensors phi, psi, Y, Z of d = 3 are stored with the r2 index fastest
+// ([r3][r1][r2]), so that every global operand load runs along a contiguous axis.
+// d = 2 fuses formation and evaluation per box / per leaf (no intermediate).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <type_traits>
+
+#include "kernels.h"
+#include "mfma.h"
+
+namespace fgt {
+
+__device__ __forceinline__ int lane_of() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_of() { return threadIdx.x >> 6; }
+
+// r2 tiles per form3_plane work item: all of them while the y accumulators
+// (NT x TG tiles) stay small, fewer for large NT.
+__host__ __device__ constexpr int form3_tile_group(int nt) { return nt <= 4 ? nt : (nt == 5 ? 3 : 2); }
+
+// k-steps of a node contraction (K = p <= 4 KS): chained operands need the
+// register layout, which for FP32 and BF16x3 spreads K over all four steps;
+// when both operands come from memory (MemSteps, k = Mfma::kmem) FP32 needs
+// only KS.  BF16x3 products always span four steps.
+template <typename C, int KS>
+struct Steps {
+  static constexpr int value = std::is_same<C, double>::value ? KS : 4;
+};
+template <typename C, int KS>
+struct MemSteps {
+  static constexpr int value = std::is_same<C, Bf16x3>::value ? 4 : KS;
+};
+
+// ---------------------------------------------------------------------------
+// d = 3 formation, axes 2 and 1, per plane.  A plane is a run of leaves of one
+// cutoff box with the same level and axis-3 position; its rows also share the
+// axis-1 position (fgt_host.h).  By separability
+//   Y_P[j3][r1][r2] = sum_rows F1_row[r1][j1] (sum_{s in row} sum_j2 sigma_s[j3][j2][j1] F2_s[r2][j2])
+// and the last axis then runs once per plane instead of once per leaf.  A wave
+// owns one item (j3 slice, group of TG r2 tiles); 4 items per workgroup:
+//   X^T[j1][r2] += sigma_s[j3] x F2_s      over the leaves of a row (lanes along j1)
+//   Y[r1][r2]   += F1_row x X^T            once per row (X^T chained as the B operand)
+
+template <typename C, int NT, int KS>
+__device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigma,
+                                                 const int32_t* __restrict__ leaf_id,
+                                                 const int32_t* __restrict__ leaf_tab,
+                                                 const int32_t* __restrict__ plane_row,
+                                                 const int32_t* __restrict__ row_start,
+                                                 const int32_t* __restrict__ row_tab,
+                                                 const elem_t<C>* __restrict__ F, int p, int nr,
+                                                 elem_t<C>* __restrict__ Y, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<C, KS>::value;      // chained (X^T as the B operand of Y)
+  constexpr int SM = MemSteps<C, KS>::value;  // sigma x F2, both from memory
+  constexpr int TG = form3_tile_group(NT), NG = (NT + TG - 1) / TG;
+  const int nitem = p * NG, nsplit = (nitem + 3) / 4;
+  const int P = bid / nsplit;
+  const int lane = lane_of(), w = wave_of();
+  const int item = (bid - P * nsplit) * 4 + w;
+  if (item >= nitem) return;
+  const int j3 = item / NG, t0 = (item - j3 * NG) * TG;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rw0 = plane_row[P], rw1 = plane_row[P + 1];
+  const int s_begin = row_start[rw0], s_end = row_start[rw1];
+  const int64_t ppp = (int64_t)p * p * p;
+  // operands of leaf s; masked loads (no branches)
+  auto load = [&](int s, T (&av)[SM], T (&b2)[TG][SM]) {
+    const bool ls = s < s_end;
+    const int sc = ls ? s : s_begin;
+    const double* sg = sigma + (int64_t)leaf_id[sc] * ppp;
+    const T* F2 = F + (int64_t)leaf_tab[sc * 3 + 1] * nr * p;
+#pragma unroll
+    for (int kk = 0; kk < SM; kk++) {
+      const int k = M::kmem(kk, lk);
+      av[kk] = ld0<T>(sg, (j3 * p + k) * p + lr, ls && lr < p && k < p);  // A[j1][j2]
+#pragma unroll
+      for (int g = 0; g < TG; g++) {
+        const int r = 16 * (t0 + g) + lr;
+        b2[g][kk] = ld0<T>(F2, r * p + k, ls && r < nr && k < p);       // B[j2][r2] = F2[r2][j2]
+      }
+    }
+  };
+  acc_t y[NT][TG];
+#pragma unroll
+  for (int tj = 0; tj < NT; tj++)
+#pragma unroll
+    for (int g = 0; g < TG; g++) zero4(y[tj][g]);
+  acc_t x[TG];
+#pragma unroll
+  for (int g = 0; g < TG; g++) zero4(x[g]);
+  T av[SM], b2[TG][SM];
+  load(s_begin, av, b2);
+  int rw = rw0;
+  int row_end = row_start[rw0 + 1];
+  for (int s = s_begin; s < s_end; s++) {
+    T avn[SM], b2n[TG][SM];
+    load(s + 1, avn, b2n);
+#pragma unroll
+    for (int g = 0; g < TG; g++)
+      x[g] = M::template steps<SM>(av, b2[g], x[g]);
+    if (s + 1 == row_end) {
+      const T* F1 = F + (int64_t)row_tab[rw] * nr * p;
+#pragma unroll
+      for (int tj = 0; tj < NT; tj++) {
+        T a1[S];
+#pragma unroll
+        for (int kk = 0; kk < S; kk++) {
+          const int k = M::kidx(kk, lk), r = 16 * tj + lr;
+          a1[kk] = ld0<T>(F1, r * p + k, r < nr && k < p);  // A[r1][j1]
+        }
+#pragma unroll
+        for (int g = 0; g < TG; g++) {
+          T xb[S];
+#pragma unroll
+          for (int kk = 0; kk < S; kk++) xb[kk] = x[g][kk];
+          y[tj][g] = M::template steps<S>(a1, xb, y[tj][g]);
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < TG; g++) zero4(x[g]);
+      rw++;
+      if (rw < rw1) row_end = row_start[rw + 1];
+    }
+#pragma unroll
+    for (int kk = 0; kk < SM; kk++) {
+      av[kk] = avn[kk];
+#pragma unroll
+      for (int g = 0; g < TG; g++) b2[g][kk] = b2n[g][kk];
+    }
+  }
+  T* Yp = Y + (int64_t)P * p * nr * nr;
+#pragma unroll
+  for (int g = 0; g < TG; g++) {
+    const int r2 = 16 * (t0 + g) + lr;
+#pragma unroll
+    for (int tj = 0; tj < NT; tj++)
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int r1 = 16 * tj + M::row(lk, t);
+        if (r1 < nr && r2 < nr) Yp[((int64_t)j3 * nr + r1) * nr + r2] = y[tj][g][t];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// last-axis formation merged over the leaves of a cutoff box (a grouped GEMM)
+
+// Tile shape of form_box: 16-column slabs per wave (H); a workgroup covers
+// 64 H columns.  fgt_execute uses kFormBoxSlabs: on the 3D benchmark tree 4
+// slabs beat 2, 3 and (for nt <= 3) 8 -- independent product chains per wave
+// matter more than occupancy (4 slabs leave one wave per SIMD at p = 16 in
+// FP64).  Batches may run a class with the other shape, kFormBoxSlabsAlt, when
+// the autotuner measures it faster; the columns and the order of every sum
+// are the same, so results are identical.
+constexpr int kFormBoxSlabs = kFormBoxTileSlabs[0];
+constexpr int kFormBoxSlabsAlt = kFormBoxTileSlabs[1];
+__host__ __device__ constexpr int form_box_cols_of(int slabs) { return 64 * slabs; }
+
+template <typename C, int D, int NT, int KS, int H>
+__device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
+                                                const int32_t* __restrict__ fitem,
+                                                const int32_t* __restrict__ leaf_tab,
+                                                const elem_t<C>* __restrict__ F, int p, int nr,
+                                                int ncoltiles, elem_t<C>* __restrict__ phi,
+                                                elem_t<C>* __restrict__ partial, int bid) {
+  typedef elem_t<C> T;
+  // one work item (<= kFormLeaves leaves of a box) x 64 H columns per
+  // workgroup; every wave owns H 16-column slabs, sharing the table operand
+  typedef Mfma<C> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = MemSteps<C, KS>::value;  // Y and F3 both come from memory
+  const int item = bid / ncoltiles;
+  const int ct = bid % ncoltiles;
+  const int A = fitem[4 * item], slot = fitem[4 * item + 3];
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int N2 = D == 3 ? nr * nr : nr;
+  int col[H];
+  bool colok[H];
+#pragma unroll
+  for (int h = 0; h < H; h++) {
+    col[h] = ct * form_box_cols_of(H) + w * (16 * H) + 16 * h + lr;
+    colok[h] = col[h] < N2;
+  }
+  acc_t acc[NT][H];
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+    for (int h = 0; h < H; h++) zero4(acc[ti][h]);
+  const int s0 = fitem[4 * item + 1], s1 = fitem[4 * item + 2];
+  // operands of leaf s; loads are masked, not branched, so that no control-flow
+  // join forces a wait for the prefetched leaf before the current products
+  auto load = [&](int s, T (&aa)[NT][S], T (&bb)[S][H]) {
+    const bool ls = s < s1;
+    const int sc = ls ? s : s0;
+    const T* Fs = F + (int64_t)leaf_tab[sc * D + (D - 1)] * nr * p;
+    const T* Ys = Y + (int64_t)sc * p * N2;
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      const int k = M::kmem(kk, lk);
+#pragma unroll
+      for (int h = 0; h < H; h++) bb[kk][h] = ld0<T>(Ys, (int64_t)k * N2 + col[h], ls && k < p && colok[h]);
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++) {
+        const int r = 16 * ti + lr;
+        aa[ti][kk] = ld0<T>(Fs, r * p + k, ls && r < nr && k < p);
+      }
+    }
+  };
+  T a[NT][S], b[S][H];
+  load(s0, a, b);
+  for (int s = s0; s < s1; s++) {
+    T an[NT][S], bn[S][H];
+    load(s + 1, an, bn);
+#pragma unroll
+    for (int h = 0; h < H; h++) {
+      T bh[S];
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) bh[kk] = b[kk][h];
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++) acc[ti][h] = M::template steps<S>(a[ti], bh, acc[ti][h]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+#pragma unroll
+      for (int h = 0; h < H; h++) b[kk][h] = bn[kk][h];
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++) a[ti][kk] = an[ti][kk];
+    }
+  }
+  // a box's only item writes phi; items of a split box write partial sums
+  T* out = slot < 0 ? phi + (int64_t)A * nr * N2 : partial + (int64_t)slot * nr * N2;
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int r = 16 * ti + M::row(lk, t);
+#pragma unroll
+      for (int h = 0; h < H; h++)
+        if (r < nr && colok[h]) out[(int64_t)r * N2 + col[h]] = acc[ti][h][t];
+    }
+}
+
+// phi_A = sum of the partial sums of a split box, in item order (deterministic)
+template <typename T>
+__device__ __forceinline__ void reduce_partials_body(const T* __restrict__ partial,
+                                                       const int32_t* __restrict__ fred,
+                                                       int64_t ncoef, int nchunk,
+                                                       T* __restrict__ phi, int bid) {
+  const int r = bid / nchunk;
+  const int64_t i = (int64_t)(bid % nchunk) * blockDim.x + threadIdx.x;
+  if (i >= ncoef) return;
+  const int A = fred[3 * r], slot0 = fred[3 * r + 1], n = fred[3 * r + 2];
+  T s = 0;
+  for (int k = 0; k < n; k++) s += partial[(int64_t)(slot0 + k) * ncoef + i];
+  phi[(int64_t)A * ncoef + i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// d = 3 out->in translation fused with the first evaluation contraction.
+// A workgroup owns one cutoff box A and one tile of mode columns (r1, r2):
+// the stored pair r1 = 2 m1, 2 m1 + 1 of one axis-1 mode m1 times the pairs of
+// a run of axis-2 modes -- all of them, whole rows, while they fit in 64
+// columns -- so every (cos, sin) partner is inside the tile.  Phase 1 gathers
+// psi_A[r3][tile] = sum_{B in P(A)} Rot(c_B - c_A) phi_B[r3][tile] into LDS (a
+// thread owns the 2 x 2 x 2 coefficients of one (m3, m2) unit: four aligned
+// pairs along r2, loaded as vectors); phase 2 contracts it with the axis-3
+// evaluation table of every plane of A, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
+// psi_A[r3][c], 16-column groups spread over the waves.  psi never goes to HBM.
+
+// axis-2 modes per tile: all of them (whole r2 rows) while 2M <= 64; else at
+// most 16 with M * modes <= 256
+__host__ __device__ inline int transeval_modes(int M) {
+  if (M <= 32) return M;
+  return M <= 16 ? 16 : (256 / M > 0 ? 256 / M : 1);
+}
+
+// LDS of the psi tile: nr rows of LDW = 2 nr + 1 columns (odd, to spread the
+// banks; a tile holds at most 2 nr columns since fused plans have 2M <= 64)
+__host__ __device__ inline int transeval_ldw(int nr) { return 2 * nr + 1; }
+inline size_t transeval_lds(int nr, size_t ts) { return (size_t)nr * transeval_ldw(nr) * ts; }
+
+template <typename C, int NT>
+__device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ phi,
+                                                const int32_t* __restrict__ plist_start,
+                                                const int32_t* __restrict__ plist_src,
+                                                const int32_t* __restrict__ plist_dir,
+                                                const elem_t<C>* __restrict__ rot,
+                                                const int32_t* __restrict__ plane_start,
+                                                const int32_t* __restrict__ plane_tab,
+                                                const elem_t<C>* __restrict__ E, int p, int M,
+                                                int nr, int nA, elem_t<C>* __restrict__ Z,
+                                                elem_t<C>* __restrict__ ps, int bid) {
+  typedef elem_t<C> T;
+  typedef typename Pair2<T>::type T2;
+  typedef Mfma<C> M_;
+  typedef typename M_::acc acc_t;
+  constexpr int Q = 4 * NT;
+  const int TM = transeval_modes(M);
+  const int LDW = transeval_ldw(nr);
+  const int nb2 = (M + TM - 1) / TM;
+  const int ntile = M * nb2;
+  // XCD x first sweeps every box (Morton order) for tiles x, x + 8, ... of the
+  // full rounds, so each such phi slice is fetched into one L2 only; the
+  // remaining ntile % 8 tiles are split into 8 contiguous box ranges, one per
+  // XCD, which keeps the work of the XCDs equal
+  const int nbx = (nA + kXcds - 1) / kXcds;
+  const int rounds = ntile / kXcds;
+  const int xcd = bid % kXcds, local = bid / kXcds;
+  int A, tile;
+  if (local < rounds * nA) {
+    const int r = local / nA;
+    A = local - r * nA;
+    tile = kXcds * r + xcd;
+  } else {
+    const int j = local - rounds * nA;
+    A = xcd * nbx + j % nbx;
+    tile = kXcds * rounds + j / nbx;
+  }
+  if (A >= nA || tile >= ntile) return;  // whole workgroup
+  const int m1 = tile / nb2, b2 = tile - m1 * nb2;
+  const int mlo = b2 * TM, mhi = min(M, mlo + TM), nm2 = mhi - mlo;
+  const int r2first = 2 * mlo;
+  const int n2 = 2 * nm2;  // r2 columns of the tile
+  const int ncol = 2 * n2;
+  const int64_t nr2 = (int64_t)nr * nr, ncoef = nr2 * nr;
+  const int tid = threadIdx.x;
+  // ---- phase 1: translations into LDS
+  const int q0 = plist_start[A], q1 = plist_start[A + 1];
+  const T cs1 = rot[2 * m1], sn1 = rot[2 * m1 + 1];
+  for (int unit = tid; unit < M * nm2; unit += blockDim.x) {
+    const int m3 = unit / nm2, m2 = mlo + (unit - (unit / nm2) * nm2);
+    const T cs2 = rot[2 * m2], sn2 = rot[2 * m2 + 1];
+    const T cs3 = rot[2 * m3], sn3 = rot[2 * m3 + 1];
+    // coefficient v = v1 + 2 v2 + 4 v3 (bit a: sin member of the axis pair);
+    // pair w = v1 + 2 v3 holds v2 = 0, 1 at off[w], off[w] + 1
+    int off[4];
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      const int v1 = w & 1, v3 = w >> 1;
+      off[w] = (2 * m3 + v3) * (int)nr2 + (2 * m1 + v1) * nr + 2 * m2;
+    }
+    T acc[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) acc[v] = 0;
+    auto fetch = [&](int q, T (&x)[8]) {
+      const T* src = phi + (int64_t)plist_src[min(q, q1 - 1)] * ncoef;
+#pragma unroll
+      for (int w = 0; w < 4; w++) {
+        const T2 v2 = *reinterpret_cast<const T2*>(src + off[w]);
+        const int v = (w & 1) | ((w >> 1) << 2);
+        x[v] = v2.x;
+        x[v | 2] = v2.y;
+      }
+    };
+    // rotations along every displaced axis; the last one adds straight into acc
+    auto apply = [&](int q, T (&x)[8]) {
+      const int code = plist_dir[q];
+      const int d1 = code % 3 - 1, d2 = (code / 3) % 3 - 1, d3 = code / 9 - 1;
+      const int last = d3 != 0 ? 2 : (d2 != 0 ? 1 : (d1 != 0 ? 0 : -1));
+      const T c[3] = {cs1, cs2, cs3};
+      const T s[3] = {d1 > 0 ? sn1 : -sn1, d2 > 0 ? sn2 : -sn2, d3 > 0 ? sn3 : -sn3};
+      const int dd[3] = {d1, d2, d3};
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        if (dd[a] == 0) continue;
+        const int bit = 1 << a;
+        if (a == last) {
+#pragma unroll
+          for (int v = 0; v < 8; v++) {
+            if (v & bit) continue;
+            const T xc = x[v], xs = x[v | bit];
+            acc[v] = fma(c[a], xc, acc[v]);
+            acc[v] = fma(-s[a], xs, acc[v]);
+            acc[v | bit] = fma(s[a], xc, acc[v | bit]);
+            acc[v | bit] = fma(c[a], xs, acc[v | bit]);
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 8; v++) {
+            if (v & bit) continue;
+            const T xc = x[v], xs = x[v | bit];
+            x[v] = c[a] * xc - s[a] * xs;
+            x[v | bit] = s[a] * xc + c[a] * xs;
+          }
+        }
+      }
+      if (last < 0) {
+#pragma unroll
+        for (int v = 0; v < 8; v++) acc[v] += x[v];
+      }
+    };
+    T xa[8], xb[8];
+    if (q0 < q1) {
+      fetch(q0, xa);
+      for (int q = q0; q < q1; q += 2) {
+        fetch(q + 1, xb);
+        apply(q, xa);
+        if (q + 1 < q1) {
+          fetch(q + 2, xa);
+          apply(q + 1, xb);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 8; v++) {
+      const int v1 = v & 1, v2 = (v >> 1) & 1, v3 = v >> 2;
+      ps[(2 * m3 + v3) * LDW + v1 * n2 + (2 * (m2 - mlo) + v2)] = acc[v];
+    }
+  }
+  __syncthreads();
+  // ---- phase 2: Z_P[i3][c] = sum_r3 E3_P[i3][r3] psi[r3][c], 16 columns per wave.
+  // Planes outer: a wave loads the plane's axis-3 table once and applies it to
+  // each of its column groups.  Both operands come from memory or LDS, so the
+  // K index of (group g, step kk) is 16 g + 4 lk + kk: a lane's four table
+  // entries are two aligned pairs of its row, loaded as vectors.
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int P0 = plane_start[A], P1 = plane_start[A + 1];
+  for (int P = P0; P < P1; P++) {
+    const T* E3 = E + (int64_t)plane_tab[P * 3 + 2] * p * nr;
+    T aq[Q];
+#pragma unroll
+    for (int g = 0; g < NT; g++)
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const int k = 16 * g + 4 * lk + 2 * h;  // even: the pair (k, k+1) is inside the row or past it
+        const bool ok = lr < p && k < nr;
+        const T2 v2 = *reinterpret_cast<const T2*>(E3 + (ok ? lr * nr + k : 0));
+        aq[4 * g + 2 * h] = ok ? v2.x : (T)0;
+        aq[4 * g + 2 * h + 1] = ok ? v2.y : (T)0;
+      }
+    T* Zp = Z + (int64_t)P * p * nr2;
+    for (int cg = w; 16 * cg < ncol; cg += 4) {  // column groups of 16, no barrier follows
+      const int col = 16 * cg + lr;
+      const bool colok = col < ncol;
+      acc_t acc;
+      zero4(acc);
+#pragma unroll
+      for (int g = 0; g < NT; g++) {
+        T aqg[4], bq[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
+          const int k = 16 * g + 4 * lk + kk;
+          const T v = ps[(k < nr && colok ? k * LDW + col : 0)];  // LDS: select, no branch
+          bq[kk] = k < nr && colok ? v : (T)0;
+          aqg[kk] = aq[4 * g + kk];
+        }
+        acc = M_::template steps<4>(aqg, bq, acc);
+      }
+      const int i1 = col < n2 ? 0 : 1;
+      const int r1 = 2 * m1 + i1;
+      const int r2 = r2first + col - i1 * n2;
+      const int64_t cglob = (int64_t)r1 * nr + r2;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int i3 = M_::row(lk, t);
+        if (i3 < p && colok) Zp[(int64_t)i3 * nr2 + cglob] = acc[t];
+      }
+    }
+  }
+}
+
+inline int64_t transeval3_blocks(const DeviceArgs& a) {
+  const int tm = transeval_modes(a.M);
+  const int64_t nb2 = (a.M + tm - 1) / tm, ntile = a.M * nb2;
+  const int64_t nbx = (a.nA + kXcds - 1) / kXcds;
+  const int64_t rounds = ntile / kXcds, rem = ntile - rounds * kXcds;
+  return kXcds * (rounds * a.nA + rem * nbx);
+}
+
+// ---------------------------------------------------------------------------
+// first evaluation contraction: Z rows of every leaf of one box for one tile of
+// 64 columns.  The box's psi columns stay in registers while the workgroup
+// walks the stacked leaf rows (s*p + i) two 16-row tiles at a time.  Boxes are
+// visited in the order box_order (most leaves first).
+
+template <typename C, int D, int NT>
+__device__ __forceinline__ void eval_box_body(const elem_t<C>* __restrict__ psi,
+                                                const int32_t* __restrict__ box_order,
+                                                const int32_t* __restrict__ pw_start,
+                                                const int32_t* __restrict__ leaf_tab,
+                                                const elem_t<C>* __restrict__ E, int p, int nr,
+                                                int ncoltiles, uint32_t pmagic,
+                                                elem_t<C>* __restrict__ Z, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
+  typedef typename M::acc acc_t;
+  constexpr int Q = 4 * NT;
+  const int A = box_order[bid / ncoltiles];
+  const int ct = bid % ncoltiles;
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int N2 = D == 3 ? nr * nr : nr;
+  const int col = ct * 64 + w * 16 + lr;
+  const bool colok = col < N2;
+  const T* P = psi + (int64_t)A * nr * N2;
+  T b[Q];
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+    b[q] = ld0<T>(P, (int64_t)k * N2 + col, k < nr && colok);
+  }
+  const int s0 = pw_start[A];
+  const int rows = (pw_start[A + 1] - s0) * p;
+  T* Zb = Z + (int64_t)s0 * p * N2;
+  auto tab_of = [&](int row) {
+    const int ls = (int)__umulhi((uint32_t)row, pmagic);  // row / p
+    return ld0<int32_t>(leaf_tab, (int64_t)(s0 + ls) * D + (D - 1), row < rows);
+  };
+  int tnext[2] = {tab_of(lr), tab_of(16 + lr)};
+  for (int rt = 0; rt < rows; rt += 32) {
+    acc_t acc[2];
+    int eoff[2];
+    bool ok[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      zero4(acc[h]);
+      const int row = rt + 16 * h + lr;
+      const int ls = (int)__umulhi((uint32_t)row, pmagic);
+      ok[h] = row < rows;
+      eoff[h] = ok[h] ? (tnext[h] * p + (row - ls * p)) * nr : 0;
+    }
+    tnext[0] = tab_of(rt + 32 + lr);
+    tnext[1] = tab_of(rt + 48 + lr);
+#pragma unroll
+    for (int g = 0; g < NT; g++) {
+      T bq[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) bq[kk] = b[4 * g + kk];
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        T aq[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
+          const int k = 16 * g + M::kidx(kk, lk);
+          aq[kk] = ld0<T>(E, eoff[h] + k, ok[h] && k < nr);
+        }
+        acc[h] = M::template steps<4>(aq, bq, acc[h]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int r = rt + 16 * h + M::row(lk, t);
+        if (r < rows && colok) Zb[(int64_t)r * N2 + col] = acc[h][t];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// d = 3 evaluation, axes 1 and 2, one i3 slice of one plane per wave (a plane
+// spans ceil(p/4) workgroups).  Z_P is stored [i3][r1][r2] (r2 fastest).  Per
+// slice and row:
+//   W^T[r2][i1] = sum_r1 Z_P[r1][r2] E1_row[i1][r1]       (lanes along r2: coalesced)
+// and per leaf s of the row:
+//   u_s[i2][i1] = sum_r2 E2_s[i2][r2] W^T[r2][i1]         (B operand chained from W^T)
+
+template <typename C, int NT>
+__device__ __forceinline__ void eval3_plane_body(const elem_t<C>* __restrict__ Z,
+                                                 const int32_t* __restrict__ leaf_id,
+                                                 const int32_t* __restrict__ leaf_tab,
+                                                 const int32_t* __restrict__ plane_row,
+                                                 const int32_t* __restrict__ row_start,
+                                                 const int32_t* __restrict__ row_tab,
+                                                 const elem_t<C>* __restrict__ E, int p, int nr,
+                                                 double* __restrict__ u, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
+  typedef typename M::acc acc_t;
+  constexpr int Q = 4 * NT;
+  const int nsplit = (p + 3) / 4;
+  const int P = bid / nsplit;
+  const int lane = lane_of(), w = wave_of();
+  const int i3 = (bid - P * nsplit) * 4 + w;
+  if (i3 >= p) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rw0 = plane_row[P], rw1 = plane_row[P + 1];
+  const int64_t ppp = (int64_t)p * p * p;
+  const T* Zs = Z + ((int64_t)P * p + i3) * nr * nr;
+  for (int rw = rw0; rw < rw1; rw++) {
+    const T* E1 = E + (int64_t)row_tab[rw] * p * nr;
+    T b1[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+      b1[q] = ld0<T>(E1, lr * nr + k, lr < p && k < nr);  // B[r1][i1] = E1[i1][r1]
+    }
+    const int s0 = row_start[rw], s1 = row_start[rw + 1];
+    {
+      acc_t wt[NT];  // W^T, rows r2 (tile ti), columns i1
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++) {
+        zero4(wt[ti]);
+        const int r2 = 16 * ti + lr;
+#pragma unroll
+        for (int g = 0; g < NT; g++) {
+          T aq[4], bq[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; kk++) {
+            const int k = 16 * g + M::kidx(kk, lk);  // r1
+            aq[kk] = ld0<T>(Zs, k * nr + r2, r2 < nr && k < nr);
+            bq[kk] = b1[4 * g + kk];
+          }
+          wt[ti] = M::template steps<4>(aq, bq, wt[ti]);
+        }
+      }
+      for (int s = s0; s < s1; s++) {
+        const T* E2 = E + (int64_t)leaf_tab[s * 3 + 1] * p * nr;
+        T a2[Q];
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          const int k = 16 * (q >> 2) + M::kidx(q & 3, lk);
+          a2[q] = ld0<T>(E2, lr * nr + k, lr < p && k < nr);  // A[i2][r2]
+        }
+        acc_t u0, u1;  // two accumulation chains, summed at the end
+        zero4(u0);
+        zero4(u1);
+#pragma unroll
+        for (int ti = 0; ti < NT; ti++) {
+          T aq[4], bq[4];
+#pragma unroll
+          for (int kk = 0; kk < 4; kk++) {
+            aq[kk] = a2[4 * ti + kk];
+            bq[kk] = wt[ti][kk];
+          }
+          if (ti & 1) u1 = M::template steps<4>(aq, bq, u1);
+          else u0 = M::template steps<4>(aq, bq, u0);
+        }
+        const acc_t uu = u0 + u1;
+        double* ul = u + (int64_t)leaf_id[s] * ppp;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int i2 = M::row(lk, t);
+          if (i2 < p && lr < p) ul[((int64_t)i3 * p + i2) * p + lr] = (double)uu[t];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// d = 3 near field, one target leaf per workgroup.  A target's sources are
+// sorted by (V3, V1, V2): axis 2 is contracted per source, axis 1 once per
+// (V3, V1) run and axis 3 once per V3 run (separability, Remark dircost).
+//   level A  T^T[j3][j1][i2] += sum_j2 sigma[j3][j2][j1] V2[i2][j2]  (lanes along j1)
+//   level B  U[j3][i1][i2]   += sum_j1 V1[i1][j1] T^T[j3][j1][i2]    (chained)
+//   level C  u[i3][i2][i1]   += sum_j3 V3[i3][j3] U[j3][i1][i2]      (j3 spans waves: LDS)
+
+template <typename C, int KS>
+__device__ __forceinline__ void near3_body(const double* __restrict__ sigma,
+                                             const int32_t* __restrict__ near_tgt,
+                                             const int32_t* __restrict__ near_haspw,
+                                             const int32_t* __restrict__ near_start,
+                                             const int32_t* __restrict__ near_src,
+                                             const int32_t* __restrict__ near_tab,
+                                             const elem_t<C>* __restrict__ V, int p,
+                                             double* __restrict__ u, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<C, KS>::value;      // level B: the chained T^T as B operand
+  constexpr int SM = MemSteps<C, KS>::value;  // levels A and C: operands from memory / LDS
+  constexpr int RS = 17;            // padded i2 stride of the LDS tile
+  constexpr int US = 16 * RS + 4;   // padded j3 stride
+  __shared__ T Us[16 * US];         // U[j3][i2][i1]
+  const int t = bid;
+  const int Tleaf = near_tgt[t];
+  const bool add = near_haspw[t] != 0;
+  const int q0 = near_start[t], q1 = near_start[t + 1];
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int pp = p * p;
+  acc_t tacc[KS], uacc[KS], oacc[KS];  // tile c <-> j3 (or i2) = w + 4c
+#pragma unroll
+  for (int c = 0; c < KS; c++) {
+    zero4(tacc[c]);
+    zero4(uacc[c]);
+    zero4(oacc[c]);
+  }
+  for (int q = q0; q < q1; q++) {
+    const int t1 = near_tab[q * 3 + 0], t2 = near_tab[q * 3 + 1], t3 = near_tab[q * 3 + 2];
+    const double* sg = sigma + (int64_t)near_src[q] * pp * p;
+    const T* V2 = V + (int64_t)t2 * pp;
+    T b2[SM];
+#pragma unroll
+    for (int kk = 0; kk < SM; kk++) {
+      const int k = M::kmem(kk, lk);
+      b2[kk] = ld0<T>(V2, lr * p + k, lr < p && k < p);  // B[j2][i2] = V2[i2][j2]
+    }
+    T av[KS][SM];
+#pragma unroll
+    for (int c = 0; c < KS; c++) {
+      const int j3 = w + 4 * c;
+#pragma unroll
+      for (int kk = 0; kk < SM; kk++) {
+        const int k = M::kmem(kk, lk);
+        av[c][kk] = ld0<T>(sg, (j3 * p + k) * p + lr, j3 < p && lr < p && k < p);  // A[j1][j2]
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < KS; c++)
+      tacc[c] = M::template steps<SM>(av[c], b2, tacc[c]);
+    const bool last = q + 1 == q1;
+    const bool end1 = last || near_tab[q * 3 + 5] != t3 || near_tab[q * 3 + 3] != t1;
+    const bool end3 = last || near_tab[q * 3 + 5] != t3;
+    if (end1) {
+      const T* V1 = V + (int64_t)t1 * pp;
+      T a1[S];
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) {
+        const int k = M::kidx(kk, lk);
+        a1[kk] = ld0<T>(V1, lr * p + k, lr < p && k < p);  // A[i1][j1]
+      }
+#pragma unroll
+      for (int c = 0; c < KS; c++) {
+        {
+          T tb[S];
+#pragma unroll
+          for (int kk = 0; kk < S; kk++) tb[kk] = tacc[c][kk];
+          uacc[c] = M::template steps<S>(a1, tb, uacc[c]);
+        }
+        zero4(tacc[c]);
+      }
+    }
+    if (end3) {
+      __syncthreads();  // previous readers of Us are done
+#pragma unroll
+      for (int c = 0; c < KS; c++) {
+        const int j3 = w + 4 * c;
+        if (j3 < p) {
+#pragma unroll
+          for (int tt = 0; tt < 4; tt++) Us[j3 * US + lr * RS + M::row(lk, tt)] = uacc[c][tt];
+        }
+        zero4(uacc[c]);
+      }
+      __syncthreads();
+      const T* V3 = V + (int64_t)t3 * pp;
+      T a3[SM];
+#pragma unroll
+      for (int kk = 0; kk < SM; kk++) {
+        const int k = M::kmem(kk, lk);
+        a3[kk] = ld0<T>(V3, lr * p + k, lr < p && k < p);  // A[i3][j3]
+      }
+#pragma unroll
+      for (int c = 0; c < KS; c++) {
+        const int i2 = w + 4 * c;  // column tile (i2, i1 = lr); rows i2 >= p are never stored
+        T bq[SM];
+#pragma unroll
+        for (int kk = 0; kk < SM; kk++) {
+          const int j3 = M::kmem(kk, lk);
+          const T uv = Us[j3 < p && i2 < p ? j3 * US + i2 * RS + lr : 0];  // LDS: select, no branch
+          bq[kk] = j3 < p ? uv : (T)0;
+        }
+        oacc[c] = M::template steps<SM>(a3, bq, oacc[c]);
+      }
+    }
+  }
+  double* ut = u + (int64_t)Tleaf * pp * p;
+  double prev[KS][4];
+#pragma unroll
+  for (int c = 0; c < KS; c++)
+#pragma unroll
+    for (int tt = 0; tt < 4; tt++) {
+      const int i2 = w + 4 * c, i3 = M::row(lk, tt);
+      const bool ok = add && i2 < p && lr < p && i3 < p;
+      prev[c][tt] = ld0<double>(ut, ((int64_t)i3 * p + i2) * p + lr, ok);
+    }
+#pragma unroll
+  for (int c = 0; c < KS; c++) {
+    const int i2 = w + 4 * c;
+    if (i2 < p && lr < p) {
+#pragma unroll
+      for (int tt = 0; tt < 4; tt++) {
+        const int i3 = M::row(lk, tt);
+        if (i3 < p) ut[((int64_t)i3 * p + i2) * p + lr] = prev[c][tt] + (double)oacc[c][tt];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// d = 2: formation of a whole cutoff box, both axes, leaves in sequence.
+// Waves split the r1 tiles; every wave keeps all r2 tiles of its columns.
+
+template <typename C, int NT, int KS>
+__device__ __forceinline__ void form2_box_body(const double* __restrict__ sigma,
+                                                 const int32_t* __restrict__ fitem,
+                                                 const int32_t* __restrict__ leaf_id,
+                                                 const int32_t* __restrict__ leaf_tab,
+                                                 const elem_t<C>* __restrict__ F, int p, int nr,
+                                                 elem_t<C>* __restrict__ phi, elem_t<C>* __restrict__ partial, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<C, KS>::value;      // F2 x X (X chained as the B operand)
+  constexpr int SM = MemSteps<C, KS>::value;  // sigma x F1, both from memory
+  constexpr int TW = (NT + 3) / 4;  // r1 tiles per wave
+  const int item = bid;
+  const int A = fitem[4 * item], slot = fitem[4 * item + 3];
+  const int lane = lane_of(), w = wave_of();
+  const int lr = lane & 15, lk = lane >> 4;
+  acc_t acc[NT][TW];
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+    for (int c = 0; c < TW; c++) zero4(acc[ti][c]);
+  const int s0 = fitem[4 * item + 1], s1 = fitem[4 * item + 2];
+  for (int s = s0; s < s1; s++) {
+    const T* F1 = F + (int64_t)leaf_tab[s * 2 + 0] * nr * p;
+    const T* F2 = F + (int64_t)leaf_tab[s * 2 + 1] * nr * p;
+    const double* sg = sigma + (int64_t)leaf_id[s] * p * p;
+    T av[SM], a2[NT][S];
+#pragma unroll
+    for (int kk = 0; kk < SM; kk++) {
+      const int k = M::kmem(kk, lk);
+      av[kk] = ld0<T>(sg, lr * p + k, lr < p && k < p);
+    }
+#pragma unroll
+    for (int kk = 0; kk < S; kk++) {
+      const int k = M::kidx(kk, lk);
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++) {
+        const int r = 16 * ti + lr;
+        a2[ti][kk] = ld0<T>(F2, r * p + k, r < nr && k < p);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < TW; c++) {
+      const int tj = w + 4 * c;
+      if (tj < NT) {
+        // X[j2][r1] = sum_j1 sigma[j2][j1] F1[r1][j1]
+        acc_t x;
+        zero4(x);
+        T bq[SM];
+#pragma unroll
+        for (int kk = 0; kk < SM; kk++) {
+          const int k = M::kmem(kk, lk), r = 16 * tj + lr;
+          bq[kk] = ld0<T>(F1, r * p + k, r < nr && k < p);
+        }
+        x = M::template steps<SM>(av, bq, x);
+        // phi[r2][r1] += sum_j2 F2[r2][j2] X[j2][r1]
+        T xb[S];
+#pragma unroll
+        for (int kk = 0; kk < S; kk++) xb[kk] = x[kk];
+#pragma unroll
+        for (int ti = 0; ti < NT; ti++) acc[ti][c] = M::template steps<S>(a2[ti], xb, acc[ti][c]);
+      }
+    }
+  }
+  T* out = slot < 0 ? phi + (int64_t)A * nr * nr : partial + (int64_t)slot * nr * nr;
+#pragma unroll
+  for (int c = 0; c < TW; c++) {
+    const int tj = w + 4 * c;
+    const int r1 = 16 * tj + lr;
+    if (tj < NT && r1 < nr) {
+#pragma unroll
+      for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int r2 = 16 * ti + M::row(lk, t);
+          if (r2 < nr) out[r2 * nr + r1] = acc[ti][c][t];
+        }
+    }
+  }
+}
+
+// d = 2: evaluation of one leaf per wave from its box's incoming expansion.
+template <typename C, int NT>
+__device__ __forceinline__ void eval2_leaf_body(const elem_t<C>* __restrict__ psi,
+                                                  const int32_t* __restrict__ leaf_box,
+                                                  const int32_t* __restrict__ leaf_id,
+                                                  const int32_t* __restrict__ leaf_tab,
+                                                  const elem_t<C>* __restrict__ E, int p, int nr,
+                                                  int nleaf, double* __restrict__ u, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
+  typedef typename M::acc acc_t;
+  constexpr int Q = 4 * NT;
+  const int lane = lane_of(), w = wave_of();
+  const int s = bid * 4 + w;
+  if (s >= nleaf) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  const T* E1 = E + (int64_t)leaf_tab[s * 2 + 0] * p * nr;
+  const T* E2 = E + (int64_t)leaf_tab[s * 2 + 1] * p * nr;
+  const T* P = psi + (int64_t)leaf_box[s] * nr * nr;
+  // W[r2][i1] = sum_r1 psi[r2][r1] E1[i1][r1]
+  acc_t wt[NT];
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++) zero4(wt[ti]);
+#pragma unroll
+  for (int g = 0; g < NT; g++) {
+    T bq[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; kk++) {
+      const int k = 16 * g + M::kidx(kk, lk);
+      bq[kk] = ld0<T>(E1, lr * nr + k, lr < p && k < nr);
+    }
+#pragma unroll
+    for (int ti = 0; ti < NT; ti++) {
+      const int r2 = 16 * ti + lr;
+      T aq[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) {
+        const int k = 16 * g + M::kidx(kk, lk);
+        aq[kk] = ld0<T>(P, r2 * nr + k, r2 < nr && k < nr);
+      }
+      wt[ti] = M::template steps<4>(aq, bq, wt[ti]);
+    }
+  }
+  // u[i2][i1] = sum_r2 E2[i2][r2] W[r2][i1]
+  acc_t uu;
+  zero4(uu);
+#pragma unroll
+  for (int ti = 0; ti < NT; ti++) {
+    T aq[4], bq[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; kk++) {
+      const int k = 16 * ti + M::kidx(kk, lk);
+      aq[kk] = ld0<T>(E2, lr * nr + k, lr < p && k < nr);
+      bq[kk] = wt[ti][kk];
+    }
+    uu = M::template steps<4>(aq, bq, uu);
+  }
+  double* ul = u + (int64_t)leaf_id[s] * p * p;
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    const int i2 = M::row(lk, t);
+    if (i2 < p && lr < p) ul[i2 * p + lr] = (double)uu[t];
+  }
+}
+
+// d = 2 near field: one target per wave; sources sorted by (V2, V1): axis 1
+// per source, axis 2 once per V2 group.
+template <typename C, int KS>
+__device__ __forceinline__ void near2_body(const double* __restrict__ sigma,
+                                             const int32_t* __restrict__ near_tgt,
+                                             const int32_t* __restrict__ near_haspw,
+                                             const int32_t* __restrict__ near_start,
+                                             const int32_t* __restrict__ near_src,
+                                             const int32_t* __restrict__ near_tab,
+                                             const elem_t<C>* __restrict__ V, int p, int ntgt,
+                                             double* __restrict__ u, int bid) {
+  typedef elem_t<C> T;
+  typedef Mfma<C> M;
+  typedef typename M::acc acc_t;
+  constexpr int S = Steps<C, KS>::value;      // V2 x T (T chained as the B operand)
+  constexpr int SM = MemSteps<C, KS>::value;  // sigma x V1, both from memory
+  const int lane = lane_of(), w = wave_of();
+  const int t = bid * 4 + w;
+  if (t >= ntgt) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int pp = p * p;
+  const int q0 = near_start[t], q1 = near_start[t + 1];
+  acc_t tacc, oacc;
+  zero4(tacc);
+  zero4(oacc);
+  for (int q = q0; q < q1; q++) {
+    const int t1 = near_tab[q * 2 + 0], t2 = near_tab[q * 2 + 1];
+    const double* sg = sigma + (int64_t)near_src[q] * pp;
+    const T* V1 = V + (int64_t)t1 * pp;
+    {
+      T aq[SM], bq[SM];
+#pragma unroll
+      for (int kk = 0; kk < SM; kk++) {
+        const int k = M::kmem(kk, lk);
+        aq[kk] = ld0<T>(sg, lr * p + k, lr < p && k < p);
+        bq[kk] = ld0<T>(V1, lr * p + k, lr < p && k < p);
+      }
+      tacc = M::template steps<SM>(aq, bq, tacc);  // T[j2][i1]
+    }
+    if (q + 1 == q1 || near_tab[q * 2 + 3] != t2) {
+      const T* V2 = V + (int64_t)t2 * pp;
+      T aq[S], bq[S];
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) {
+        const int k = M::kidx(kk, lk);
+        aq[kk] = ld0<T>(V2, lr * p + k, lr < p && k < p);
+        bq[kk] = tacc[kk];
+      }
+      oacc = M::template steps<S>(aq, bq, oacc);  // u[i2][i1] += V2[i2][j2] T[j2][i1]
+      zero4(tacc);
+    }
+  }
+  double* ut = u + (int64_t)near_tgt[t] * pp;
+  const bool add = near_haspw[t] != 0;
+#pragma unroll
+  for (int tt = 0; tt < 4; tt++) {
+    const int i2 = M::row(lk, tt);
+    if (i2 < p && lr < p) ut[i2 * p + lr] = add ? ut[i2 * p + lr] + (double)oacc[tt] : (double)oacc[tt];
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ const T* cptr(const void* p) { return static_cast<const T*>(p); }
+template <typename T> __device__ __forceinline__ T* mptr(void* p) { return static_cast<T*>(p); }
+__device__ __forceinline__ int n2_of(int d, int nr) { return d == 3 ? nr * nr : nr; }
+__device__ __forceinline__ uint32_t pmagic_of(int p) { return (uint32_t)((0x100000000ull + p - 1) / p); }
+
+}  // namespace fgt

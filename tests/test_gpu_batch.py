@@ -6,6 +6,8 @@ under every schedule the autotuner tries, and after rebinding.  Two
 transforms are also checked against the FP64 oracle within their tol.
 """
 
+import time
+
 import numpy as np
 import pytest
 
@@ -82,6 +84,52 @@ def test_batch_equals_alone_graph_and_direct():
                 u.fill_(float("nan"))
             torch.cuda.synchronize()
         b.close()
+
+
+@pytest.mark.skip(reason="persistent batched launches did not finish their first execution within three "
+                         "minutes on the device, twice (acquire-polled waits, then relaxed-polled waits with "
+                         "one acquire); the cause is not established, so fgt_batch_create refuses the option "
+                         "and this case stays off the GPU")
+def test_batch_persistent_equals_alone():
+    """One persistent launch per kernel class (every stage of every transform
+    of the class behind a work queue): bitwise the results alone, in graph
+    replay and direct mode, repeatedly, with eager work between executions;
+    no bounded wait runs out."""
+    probs = _problems()
+    # add a split-bf16 transform: its class keeps the per-stage launches
+    t0 = probs[0]
+    extra = synth.RequestType(102, t0.d, t0.p, t0.delta, 1e-3, "bf16x3", t0.levels, t0.coords, t0.sigma)
+    probs = probs + [extra]
+    plans = _plans(probs)
+    sig = [torch.from_numpy(t.sigma).cuda() for t in probs]
+    ref = _alone(plans, sig)
+    for use_graph in (True, False):
+        b = api.Batch(plans, use_graph=use_graph, persistent=True)
+        us = [torch.full_like(s, float("nan")) for s in sig]
+        b.bind(sig, us)
+        info = b.info()
+        _say(f"persistent graph={use_graph} info {info}")
+        assert 0 < info["persistent"] < info["nclasses"]
+        for rep in range(3):
+            t0 = time.perf_counter()
+            b.execute()
+            torch.cuda.synchronize()
+            _say(f"persistent graph={use_graph} rep {rep}: {1e3 * (time.perf_counter() - t0):.1f} ms")
+            for i, (u, r) in enumerate(zip(us, ref)):
+                assert torch.equal(u, r), f"rep {rep} job {i} differs from its result alone"
+            for u in us:
+                u.fill_(float("nan"))
+            torch.cuda.synchronize()
+        assert b.info()["persistent_error"] == 0
+        b.close()
+
+
+def test_batch_persistent_is_refused():
+    probs = _problems()[:2]
+    plans = _plans(probs)
+    with pytest.raises(api.FgtError) as ei:
+        api.Batch(plans, persistent=True)
+    assert ei.value.code == api.FGT_ERR_UNSUPPORTED
 
 
 def test_batch_rebind_and_tuner_off():
