@@ -95,16 +95,22 @@ int64_t fgt::plan_device_bytes(const HostPlan& hp) {
   return b + plan_workspace_bytes(hp);
 }
 
+// coefficients per box of phi and of the partial sums (tile-major in fused
+// d = 3 plans, kernels.h)
+static int64_t phi_coefs(const fgt::HostPlan& hp) {
+  return fgt::phi_box_coefs(hp.d, hp.pw.M, hp.nrs, hp.d == 3 && hp.fuse_te ? hp.te_tp : 0);
+}
+
 int64_t fgt::plan_workspace_bytes(const HostPlan& hp) {
   const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
   int64_t n2 = 1;
   for (int a = 1; a < hp.d; a++) n2 *= hp.nrs;
-  const int64_t ncoef = n2 * hp.nrs;
+  const int64_t ncoef = n2 * hp.nrs, nphi = phi_coefs(hp);
   const int64_t round = 256 / ts;  // each array starts on a 256-byte boundary
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
   const int64_t nU = hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : hp.n_pwleaf());
-  const int64_t nbox_arrays = hp.fuse_te ? 1 : 2;  // phi, and psi unless fused away
-  return ts * (up(nU * hp.p * n2) + nbox_arrays * up(hp.n_pwbox() * ncoef) + up((int64_t)hp.nslots * ncoef));
+  const int64_t npsi = hp.fuse_te ? 0 : up(hp.n_pwbox() * ncoef);  // no psi when fused away
+  return ts * (up(nU * hp.p * n2) + up(hp.n_pwbox() * nphi) + npsi + up((int64_t)hp.nslots * nphi));
 }
 
 namespace {
@@ -120,6 +126,7 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
   size_t need = std::max(fgt::lds_form_leaf(hp.d, hp.p, hp.nrs, ts),
                          std::max(fgt::lds_eval_leaf(hp.d, hp.p, hp.nrs, ts), fgt::lds_near(hp.d, hp.p, ts)));
+  if (hp.fuse_te) need = std::max(need, fgt::lds_transeval(hp.te_tp, hp.nrs, ts));
   if (need > (size_t)lds_max)
     return fail(FGT_ERR_UNSUPPORTED, "stage needs " + std::to_string(need) + " bytes of LDS, device allows " +
                                          std::to_string(lds_max));
@@ -153,18 +160,25 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
       (rc = upload_i32(pl, hp.near_tab, &a.near_tab)) ||
       (rc = upload_i32(pl, hp.plane_start, &a.plane_start)) ||
       (rc = upload_i32(pl, hp.plane_tab, &a.plane_tab)) || (rc = upload_i32(pl, hp.plane_row, &a.plane_row)) ||
-      (rc = upload_i32(pl, hp.row_start, &a.row_start)) || (rc = upload_i32(pl, hp.row_tab, &a.row_tab)))
+      (rc = upload_i32(pl, hp.row_start, &a.row_start)) || (rc = upload_i32(pl, hp.row_tab, &a.row_tab)) ||
+      (rc = upload_i32(pl, hp.te_start, &a.te_start)) || (rc = upload_i32(pl, hp.te_mem, &a.te_mem)) ||
+      (rc = upload_i32(pl, hp.te_src, &a.te_src)) || (rc = upload_i32(pl, hp.te_dir, &a.te_dir)) ||
+      (rc = upload_i32(pl, hp.te_wg, &a.te_wg)))
     return rc;
+  a.nTG = hp.n_te_group();
+  a.nTW = (int64_t)hp.te_wg.size() / 2;
   a.nPl = hp.n_plane();
   const size_t n2 = (size_t)ipowd(hp.nrs, hp.d - 1);
   const size_t ncoef = n2 * hp.nrs;
+  a.ncoef_phi = phi_coefs(hp);
+  a.phi_tp = hp.d == 3 && hp.fuse_te ? hp.te_tp : 0;
   // the intermediate: per plane for d = 3, none for d = 2 (both axes fused), per leaf for d = 1
   const int64_t nU = hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : a.nL);
   // no psi when the translation is fused with the first evaluation step
   const size_t npsi = hp.fuse_te ? 0 : (size_t)a.nA * ncoef * ts;
   if ((rc = alloc(pl, (size_t)nU * hp.p * n2 * ts, &a.Y)) ||
-      (rc = alloc(pl, (size_t)a.nA * ncoef * ts, &a.phi)) || (rc = alloc(pl, npsi, &a.psi)) ||
-      (rc = alloc(pl, (size_t)hp.nslots * ncoef * ts, &a.partial)))
+      (rc = alloc(pl, (size_t)a.nA * a.ncoef_phi * ts, &a.phi)) || (rc = alloc(pl, npsi, &a.psi)) ||
+      (rc = alloc(pl, (size_t)hp.nslots * a.ncoef_phi * ts, &a.partial)))
     return rc;
   if (opts && opts->own_stream) {
     e = hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking);
@@ -245,13 +259,13 @@ static void carve_workspace(const fgt::HostPlan& hp, void* base, fgt::DeviceArgs
   const int64_t ts = hp.precision != FGT_FP64 ? 4 : 8;
   int64_t n2 = 1;
   for (int a = 1; a < hp.d; a++) n2 *= hp.nrs;
-  const int64_t ncoef = n2 * hp.nrs, round = 256 / ts;
+  const int64_t ncoef = n2 * hp.nrs, nphi = phi_coefs(hp), round = 256 / ts;
   auto up = [&](int64_t n) { return (n + round - 1) / round * round; };
   char* c = static_cast<char*>(base);
   args->Y = c;
   c += ts * up((hp.d == 3 ? hp.n_plane() : (hp.d == 2 ? 0 : hp.n_pwleaf())) * hp.p * n2);
   args->phi = c;
-  c += ts * up(hp.n_pwbox() * ncoef);
+  c += ts * up(hp.n_pwbox() * nphi);
   args->psi = hp.fuse_te ? nullptr : c;
   if (!hp.fuse_te) c += ts * up(hp.n_pwbox() * ncoef);
   args->partial = c;
@@ -511,6 +525,11 @@ int64_t fgt_plan_array(const fgt_plan_t* pl, const char* name, void* dst, int64_
   else if (n == "plist_start") iv = &hp.plist_start;
   else if (n == "plist_src") iv = &hp.plist_src;
   else if (n == "plist_dir") iv = &hp.plist_dir;
+  else if (n == "te_start") iv = &hp.te_start;
+  else if (n == "te_mem") iv = &hp.te_mem;
+  else if (n == "te_src") iv = &hp.te_src;
+  else if (n == "te_dir") iv = &hp.te_dir;
+  else if (n == "te_wg") iv = &hp.te_wg;
   else if (n == "echunk") iv = &hp.echunk;
   else if (n == "fitem") iv = &hp.fitem;
   else if (n == "fred") iv = &hp.fred;

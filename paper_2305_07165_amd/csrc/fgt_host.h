@@ -16,6 +16,9 @@ constexpr double kMinTolBf16x3 = 1e-4 * (1 - 1e-9);
 constexpr int kMaxModes = 128; // stored plane-wave modes per axis (2M)
 constexpr int kFormLeaves = 8; // leaves per formation work item
 constexpr double kFuseBytes = 128e6;  // psi bytes above which the 3D translation is fused
+constexpr int kTeGroup = 8;    // target boxes per fused-translation group (siblings)
+constexpr int kTeNoDir = 0xFF; // group entry: the member does not take this source
+constexpr int kXcdCount = 8;   // XCDs (separate L2s) of the device; workgroup b runs on b % 8
 
 // Plane-wave parameters of Theorem 1 for tolerance eps and range R (units of
 // sqrt(delta)): D0 = sqrt(log(3/eps)), h = 2 pi/(R + D0), M = ceil(D0 (R+D0)/pi).
@@ -68,6 +71,24 @@ struct HostPlan {
   std::vector<int32_t> plist_start;   // [nA+1]
   std::vector<int32_t> plist_src;     // [nP] plane-wave box index
   std::vector<int32_t> plist_dir;     // [nP] sum_a (dir_a+1) 3^a, dir = src - dst
+                                      // (each box's list sorted by source box, then code)
+  // d = 3 fused translation: groups of up to kTeGroup target boxes that share
+  // their parent at level lc - 1, each with the union of its members' P-lists.
+  // Entry e of group g is a source box te_src[e] and, per member slot t, its
+  // direction code in the member's P-list (byte t % 4 of te_dir[2e + t / 4];
+  // kTeNoDir: not in it).  A member meets its own P-list in its own order.
+  std::vector<int32_t> te_start;      // [nG+1] ranges of entries per group
+  std::vector<int32_t> te_mem;        // [nG*kTeGroup] member box per slot, -1 = empty
+  std::vector<int32_t> te_src;        // [nTE]
+  std::vector<int32_t> te_dir;        // [nTE*2] packed direction codes
+  // tiles of the fused translation: te_tp (m1, m2) mode pairs each (kernels.h
+  // keeps phi tile-major with the same tiles); workgroup b of the launch runs
+  // group te_wg[2b] on tile te_wg[2b+1] (-1: nothing).  Tile t of every group
+  // runs on XCD t % 8 (b % 8 is the XCD of workgroup b) so that a source tile
+  // is read into one L2, the tiles past the last multiple of 8 on the least
+  // loaded XCD, and each XCD takes its workgroups longest first.
+  int te_tp = 0;
+  std::vector<int32_t> te_wg;         // [nWG*2]
   // d = 3 only: a plane is a run of pw leaves of one box with the same level and
   // axis-3 position (one axis-3 table); a row is a run of a plane's leaves that
   // also share the axis-1 position (one axis-1 table)
@@ -108,6 +129,7 @@ struct HostPlan {
   int64_t n_pwbox() const { return (int64_t)pwbox_isleaf.size(); }
   int64_t n_pwleaf() const { return (int64_t)pwleaf_id.size(); }
   int64_t n_plist() const { return (int64_t)plist_src.size(); }
+  int64_t n_te_group() const { return te_start.empty() ? 0 : (int64_t)te_start.size() - 1; }
   int64_t n_near_tgt() const { return (int64_t)near_tgt.size(); }
   int64_t n_near_pair() const { return (int64_t)near_src.size(); }
   int64_t n_plane() const { return row_start.empty() ? 0 : (int64_t)plane_row.size() - 1; }
@@ -123,6 +145,10 @@ struct PwLeafRef { int32_t box; uint64_t m; int32_t id; int32_t lv; };
 // nslots) and the evaluation chunks.  level/coord are indexed by id.
 void finish_pw_lists(HostPlan& hp, std::vector<PwLeafRef>& pl, int32_t nA, const int32_t* level,
                      const int32_t* coord, bool allow_fuse);
+
+// Groups the plane-wave boxes of a fused d = 3 plan (te_*) from the P-lists
+// and box_coord [nA*3], the boxes' coordinates at the cutoff level.
+void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord);
 
 // Validates the tree and fills every field above.  Returns an FGT_* code.
 int build_host_plan(int dim, int64_t nleaves, const int32_t* level, const int32_t* coord,

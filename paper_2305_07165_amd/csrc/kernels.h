@@ -10,6 +10,27 @@
 
 namespace fgt {
 
+// phi of a fused d = 3 plan is stored tile-major, so that the translation's
+// workgroup reads one contiguous block per source box: with tp (m1, m2) mode
+// pairs per tile (the plan's te_tp), a box holds ceil(M^2 / tp) blocks of nr
+// rows (r3) by 4 tp columns, and column (r1, r2), pair j = (r1 / 2) M + r2 / 2,
+// sits in block j / tp at (r1 & 1) 2 tp + 2 (j % tp) + (r2 & 1).  Other plans
+// (tp = 0) store [r3][r1][r2] (d = 3).
+__host__ __device__ inline int64_t phi_box_coefs(int d, int M, int nr, int tp) {
+  if (tp <= 0) {
+    int64_t n = nr;
+    for (int a = 1; a < d; a++) n *= nr;
+    return n;
+  }
+  return (int64_t)((M * M + tp - 1) / tp) * nr * 4 * tp;
+}
+// offset of column (r1, r2) of row 0 inside a tiled box; rows are 4 tp apart
+__host__ __device__ inline int64_t phi_tiled_col(int M, int tp, int nr, int r1, int r2) {
+  const int j = (r1 >> 1) * M + (r2 >> 1);
+  const int tile = j / tp;
+  return (int64_t)tile * nr * 4 * tp + (r1 & 1) * 2 * tp + 2 * (j - tile * tp) + (r2 & 1);
+}
+
 struct DeviceArgs {
   int d = 0, p = 0, nr = 0, M = 0;
   bool fp32 = false;  // FP32 storage (FP32 or BF16x3 products)
@@ -23,6 +44,10 @@ struct DeviceArgs {
   const int32_t* pwleaf_box = nullptr;
   const int32_t* box_order = nullptr;  // plane-wave boxes, most leaves first
   const int32_t *plist_start = nullptr, *plist_src = nullptr, *plist_dir = nullptr;
+  // d = 3 fused translation: target groups and workgroups (fgt_host.h te_*)
+  const int32_t *te_start = nullptr, *te_mem = nullptr, *te_src = nullptr, *te_dir = nullptr;
+  const int32_t* te_wg = nullptr;
+  int64_t nTG = 0, nTW = 0;
   const int32_t* echunk = nullptr;
   // formation work items (box, first leaf, end leaf, partial slot or -1) and
   // the reductions of split boxes (box, first slot, slot count)
@@ -35,8 +60,10 @@ struct DeviceArgs {
   const int32_t *near_tgt = nullptr, *near_haspw = nullptr, *near_start = nullptr;
   const int32_t *near_src = nullptr, *near_tab = nullptr;
   // workspace (compute precision): Y/Z [nU][p*nr^(d-1)] (nU = planes for d = 3,
-  // pw leaves otherwise), phi/psi [nA][nr^d]
+  // pw leaves otherwise), phi [nA][ncoef_phi], psi [nA][nr^d]
   void *Y = nullptr, *phi = nullptr, *psi = nullptr;
+  int64_t ncoef_phi = 0;    // coefficients per box of phi and partial (phi_box_coefs)
+  int phi_tp = 0;           // tile-major phi with this many pairs per tile; 0: [r3][r1][r2]
   void* partial = nullptr;  // [nslots][nr^d] partial sums of split boxes
 };
 
@@ -119,6 +146,7 @@ hipError_t zero_i32(int32_t* p, int64_t n, hipStream_t st);
 size_t lds_form_leaf(int d, int p, int nr, size_t tsize);
 size_t lds_eval_leaf(int d, int p, int nr, size_t tsize);
 size_t lds_near(int d, int p, size_t tsize);
+size_t lds_transeval(int tp, int nr, size_t tsize);  // the fused d = 3 translation
 
 // Enqueues every stage on st.  ev (7 events or NULL) brackets the stages.
 hipError_t launch_transform(const DeviceArgs& a, const double* sigma, double* u,

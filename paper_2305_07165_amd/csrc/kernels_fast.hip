@@ -62,10 +62,11 @@ __global__ __launch_bounds__(256) void form3_plane_b(FGT_BATCH_PARAMS) {
 template <typename C, int D, int NT, int KS>
 __global__ __launch_bounds__(256) void form_box(const elem_t<C>* __restrict__ Y, const int32_t* __restrict__ fitem,
                                                 const int32_t* __restrict__ leaf_tab, const elem_t<C>* __restrict__ F,
-                                                int p, int nr, int ncoltiles, elem_t<C>* __restrict__ phi,
-                                                elem_t<C>* __restrict__ partial) {
+                                                int p, int nr, int ncoltiles, int M, int tp, int64_t ncoef_phi,
+                                                elem_t<C>* __restrict__ phi, elem_t<C>* __restrict__ partial) {
   typedef elem_t<C> T;
-  form_box_body<C, D, NT, KS, kFormBoxSlabs>(Y, fitem, leaf_tab, F, p, nr, ncoltiles, phi, partial, blockIdx.x);
+  form_box_body<C, D, NT, KS, kFormBoxSlabs>(Y, fitem, leaf_tab, F, p, nr, ncoltiles, M, tp, ncoef_phi, phi, partial,
+                                             blockIdx.x);
 }
 template <typename C, int D, int NT, int KS, int H>
 __global__ __launch_bounds__(256) void form_box_b(FGT_BATCH_PARAMS) {
@@ -73,8 +74,7 @@ __global__ __launch_bounds__(256) void form_box_b(FGT_BATCH_PARAMS) {
   FGT_BATCH_PROLOGUE
   const int ncol128 = (n2_of(D, a.nr) + form_box_cols_of(H) - 1) / form_box_cols_of(H);
   form_box_body<C, D, NT, KS, H>(cptr<T>(a.Y), a.fitem, D == 3 ? a.plane_tab : a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
-                              ncol128,
-                              mptr<T>(a.phi), mptr<T>(a.partial), bid);
+                                 ncol128, a.M, a.phi_tp, a.ncoef_phi, mptr<T>(a.phi), mptr<T>(a.partial), bid);
 }
 
 template <typename T>
@@ -85,8 +85,7 @@ __global__ __launch_bounds__(256) void reduce_partials(const T* __restrict__ par
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_partials_b(FGT_BATCH_PARAMS) {
   FGT_BATCH_PROLOGUE
-  int64_t ncoef = a.nr;
-  for (int i = 1; i < a.d; i++) ncoef *= a.nr;
+  const int64_t ncoef = a.ncoef_phi;
   reduce_partials_body<T>(cptr<T>(a.partial), a.fred, ncoef, (int)((ncoef + 255) / 256), mptr<T>(a.phi), bid);
 }
 
@@ -194,22 +193,23 @@ __global__ __launch_bounds__(256) void near2_b(FGT_BATCH_PARAMS) {
 
 template <typename C, int NT>
 __global__ __launch_bounds__(256) void transeval3(
-    const elem_t<C>* __restrict__ phi, const int32_t* __restrict__ plist_start, const int32_t* __restrict__ plist_src,
-    const int32_t* __restrict__ plist_dir, const elem_t<C>* __restrict__ rot, const int32_t* __restrict__ plane_start,
-    const int32_t* __restrict__ plane_tab, const elem_t<C>* __restrict__ E, int p, int M, int nr, int nA,
+    const elem_t<C>* __restrict__ phi, const int32_t* __restrict__ te_start, const int32_t* __restrict__ te_mem,
+    const int32_t* __restrict__ te_src, const int32_t* __restrict__ te_dir, const int32_t* __restrict__ te_wg,
+    const elem_t<C>* __restrict__ rot, const int32_t* __restrict__ plane_start,
+    const int32_t* __restrict__ plane_tab, const elem_t<C>* __restrict__ E, int p, int M, int nr, int tp,
     elem_t<C>* __restrict__ Z) {
   extern __shared__ __align__(16) unsigned char te_lds[];
-  transeval3_body<C, NT>(phi, plist_start, plist_src, plist_dir, rot, plane_start, plane_tab, E, p, M, nr, nA, Z,
-                         reinterpret_cast<elem_t<C>*>(te_lds), blockIdx.x);
+  transeval3_body<C, NT>(phi, te_start, te_mem, te_src, te_dir, te_wg, rot, plane_start, plane_tab, E, p, M, nr, tp,
+                         Z, reinterpret_cast<elem_t<C>*>(te_lds), blockIdx.x);
 }
-// batched: the launch provides the LDS of the class's largest nr (16 NT)
+// batched: the launch provides the LDS of the class's largest plan (transeval_lds_max)
 template <typename C, int NT>
 __global__ __launch_bounds__(256) void transeval3_b(FGT_BATCH_PARAMS) {
   extern __shared__ __align__(16) unsigned char te_lds[];
   FGT_BATCH_PROLOGUE
   typedef elem_t<C> T;
-  transeval3_body<C, NT>(cptr<T>(a.phi), a.plist_start, a.plist_src, a.plist_dir, cptr<T>(a.rot), a.plane_start,
-                         a.plane_tab, cptr<T>(a.E), a.p, a.M, a.nr, (int)a.nA, mptr<T>(a.Y),
+  transeval3_body<C, NT>(cptr<T>(a.phi), a.te_start, a.te_mem, a.te_src, a.te_dir, a.te_wg, cptr<T>(a.rot),
+                         a.plane_start, a.plane_tab, cptr<T>(a.E), a.p, a.M, a.nr, a.phi_tp, mptr<T>(a.Y),
                          reinterpret_cast<T*>(te_lds), bid);
 }
 
@@ -218,6 +218,8 @@ __global__ __launch_bounds__(256) void transeval3_b(FGT_BATCH_PARAMS) {
 
 // ---------------------------------------------------------------------------
 // grids
+
+size_t lds_transeval(int tp, int nr, size_t tsize) { return transeval_lds(tp, nr, tsize); }
 
 KernelClass kernel_class(const DeviceArgs& a) {
   KernelClass c;
@@ -248,7 +250,7 @@ int64_t stage_blocks(const DeviceArgs& a, int stage) {
       return a.nPl * ((a.p * ((nt + tg - 1) / tg) + 3) / 4);
     }
     case kFormBox: return form_box_blocks(a, kFormBoxSlabs);
-    case kReduce: return pw && a.nFR > 0 ? a.nFR * ((N2 * nr + 255) / 256) : 0;
+    case kReduce: return pw && a.nFR > 0 ? a.nFR * ((a.ncoef_phi + 255) / 256) : 0;
     case kTranslate: return pw ? (a.d == 3 && a.fuse_te ? transeval3_blocks(a) : translate_blocks(a)) : 0;
     // d = 3: a separate stage unless fused into the translation; d = 2: fused into eval2_leaf
     case kEvalBox: return pw && a.d == 3 && !a.fuse_te ? a.nA * ((N2 + 63) / 64) : 0;
@@ -275,7 +277,7 @@ static void launch_batched_nt(int d, bool fuse, int stage, const BatchJob* jobs,
       case kReduce: hipLaunchKernelGGL((reduce_partials_b<T>), g, b, 0, st, jobs, start, count, njobs); break;
       case kTranslate:
         if (fuse)
-          hipLaunchKernelGGL((transeval3_b<C, NT>), g, b, transeval_lds(16 * NT, sizeof(T)), st, jobs, start, count,
+          hipLaunchKernelGGL((transeval3_b<C, NT>), g, b, transeval_lds_max(NT, sizeof(T)), st, jobs, start, count,
                              njobs);
         else launch_translate_batched<T>(3, jobs, start, count, njobs, grid, st);
         break;
@@ -334,8 +336,7 @@ hipError_t launch_stage_batched(const KernelClass& c, int stage, const BatchJob*
 template <typename T>
 static void launch_reduce(const DeviceArgs& a, hipStream_t st) {
   if (a.nFR == 0) return;
-  int64_t ncoef = a.nr;
-  for (int i = 1; i < a.d; i++) ncoef *= a.nr;
+  const int64_t ncoef = a.ncoef_phi;
   const int nchunk = (int)((ncoef + 255) / 256);
   hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)stage_blocks(a, kReduce)), dim3(256), 0, st,
                      static_cast<const T*>(a.partial), a.fred, ncoef, nchunk, static_cast<T*>(a.phi));
@@ -362,13 +363,14 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
                          a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, F, p, nr, Y);
       rec(1);
       hipLaunchKernelGGL((form_box<C, 3, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, Y,
-                         a.fitem, a.plane_tab, F, p, nr, ncol128, phi, static_cast<T*>(a.partial));
+                         a.fitem, a.plane_tab, F, p, nr, ncol128, a.M, a.phi_tp, a.ncoef_phi, phi, static_cast<T*>(a.partial));
       launch_reduce<T>(a, st);
       rec(2);
       if (a.fuse_te) {
         hipLaunchKernelGGL((transeval3<C, NT>), dim3((unsigned)stage_blocks(a, kTranslate)), dim3(256),
-                           transeval_lds(nr, sizeof(T)), st, static_cast<const T*>(a.phi), a.plist_start, a.plist_src, a.plist_dir,
-                           static_cast<const T*>(a.rot), a.plane_start, a.plane_tab, E, p, a.M, nr, (int)a.nA, Y);
+                           transeval_lds(a.phi_tp, nr, sizeof(T)), st, static_cast<const T*>(a.phi), a.te_start,
+                           a.te_mem, a.te_src, a.te_dir, a.te_wg, static_cast<const T*>(a.rot), a.plane_start,
+                           a.plane_tab, E, p, a.M, nr, a.phi_tp, Y);
         rec(3);
         rec(4);
       } else {

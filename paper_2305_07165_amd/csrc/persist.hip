@@ -89,22 +89,22 @@ __global__ __launch_bounds__(256) void class_persistent(const BatchJob* __restri
         if constexpr (D == 3) {
           const int ncol = (n2_of(D, a.nr) + form_box_cols_of(kFormBoxSlabs) - 1) / form_box_cols_of(kFormBoxSlabs);
           form_box_body<C, D, NT, KS, kFormBoxSlabs>(cptr<T>(a.Y), a.fitem, a.plane_tab, cptr<T>(a.F), a.p, a.nr,
-                                                     ncol, mptr<T>(a.phi), mptr<T>(a.partial), bid);
+                                                     ncol, a.M, a.phi_tp, a.ncoef_phi, mptr<T>(a.phi), mptr<T>(a.partial),
+                                                     bid);
         } else {
           form2_box_body<C, NT, KS>(jobs[j].sigma, a.fitem, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.F), a.p, a.nr,
                                     mptr<T>(a.phi), mptr<T>(a.partial), bid);
         }
         break;
       case kReduce: {
-        int64_t ncoef = a.nr;
-        for (int i = 1; i < D; i++) ncoef *= a.nr;
+        const int64_t ncoef = a.ncoef_phi;
         reduce_partials_body<T>(cptr<T>(a.partial), a.fred, ncoef, (int)((ncoef + 255) / 256), mptr<T>(a.phi), bid);
         break;
       }
       case kTranslate:
         if constexpr (D == 3 && FUSE)
-          transeval3_body<C, NT>(cptr<T>(a.phi), a.plist_start, a.plist_src, a.plist_dir, cptr<T>(a.rot),
-                                 a.plane_start, a.plane_tab, cptr<T>(a.E), a.p, a.M, a.nr, (int)a.nA, mptr<T>(a.Y),
+          transeval3_body<C, NT>(cptr<T>(a.phi), a.te_start, a.te_mem, a.te_src, a.te_dir, a.te_wg, cptr<T>(a.rot),
+                                 a.plane_start, a.plane_tab, cptr<T>(a.E), a.p, a.M, a.nr, a.phi_tp, mptr<T>(a.Y),
                                  reinterpret_cast<T*>(te_lds), bid);
         else
           translate_body<T, D, D == 3>(cptr<T>(a.phi), a.plist_start, a.plist_src, a.plist_dir, cptr<T>(a.rot), a.M,
@@ -145,7 +145,7 @@ void launch_d(bool fuse, const BatchJob* jobs, const int32_t* start, const int32
               const int64_t* stage_base, uint64_t* head, int32_t* ctl, int spin_limit, int grid, hipStream_t st) {
   typedef elem_t<C> T;
   if (D == 3 && fuse)
-    hipLaunchKernelGGL((class_persistent<C, D, NT, KS, true>), dim3(grid), dim3(256), transeval_lds(16 * NT, sizeof(T)),
+    hipLaunchKernelGGL((class_persistent<C, D, NT, KS, true>), dim3(grid), dim3(256), transeval_lds_max(NT, sizeof(T)),
                        st, jobs, start, count, njobs, stage_base, head, ctl, spin_limit);
   else
     hipLaunchKernelGGL((class_persistent<C, D, NT, KS, false>), dim3(grid), dim3(256), 0, st, jobs, start, count,

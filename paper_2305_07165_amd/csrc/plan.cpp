@@ -185,6 +185,116 @@ void finish_pw_lists(HostPlan& hp, std::vector<PwLeafRef>& pl, int32_t nA, const
 
 }
 
+// Fused-translation target groups: the plane-wave boxes that share a parent at
+// level lc - 1 (siblings, contiguous in Morton order).  The entries of a group
+// are the distinct (source box, rank) pairs of its members' P-lists, rank
+// counting repeats of one source in one list (a box that is its own neighbor
+// through two periodic images), sorted by source box then rank.  Since every
+// P-list is sorted by (source box, code), a member meets its sources in its
+// own list's order, so its sum is formed in the same order as on its own.
+void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
+  hp.te_start.assign(1, 0);
+  hp.te_mem.clear();
+  hp.te_src.clear();
+  hp.te_dir.clear();
+  hp.te_wg.clear();
+  const int32_t nA = (int32_t)hp.n_pwbox();
+  std::unordered_map<uint64_t, int32_t> gmap;
+  std::vector<std::vector<int32_t>> groups;
+  for (int32_t a = 0; a < nA; a++) {
+    uint64_t k = 0;
+    for (int ax = 0; ax < 3; ax++) k = (k << 21) | (uint32_t)(box_coord[(size_t)a * 3 + ax] >> 1);
+    auto it = gmap.find(k);
+    if (it == gmap.end()) {
+      gmap.emplace(k, (int32_t)groups.size());
+      groups.push_back({a});
+    } else {
+      groups[it->second].push_back(a);
+    }
+  }
+  struct Ent {
+    int32_t src, rank;
+    uint8_t dir[kTeGroup];
+  };
+  for (const auto& mem : groups) {
+    std::vector<Ent> ents;
+    std::unordered_map<uint64_t, size_t> at;  // (src, rank) -> entry
+    for (size_t t = 0; t < mem.size(); t++) {
+      const int32_t A = mem[t];
+      int32_t prev = -1, rank = 0;
+      for (int32_t q = hp.plist_start[A]; q < hp.plist_start[A + 1]; q++) {
+        const int32_t B = hp.plist_src[q];
+        rank = B == prev ? rank + 1 : 0;
+        prev = B;
+        const uint64_t k = ((uint64_t)(uint32_t)B << 32) | (uint32_t)rank;
+        auto it = at.find(k);
+        size_t e;
+        if (it == at.end()) {
+          e = ents.size();
+          at.emplace(k, e);
+          Ent n{B, rank, {}};
+          for (int s = 0; s < kTeGroup; s++) n.dir[s] = (uint8_t)kTeNoDir;
+          ents.push_back(n);
+        } else {
+          e = it->second;
+        }
+        ents[e].dir[t] = (uint8_t)hp.plist_dir[q];
+      }
+    }
+    std::sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) {
+      return x.src != y.src ? x.src < y.src : x.rank < y.rank;
+    });
+    for (const Ent& e : ents) {
+      hp.te_src.push_back(e.src);
+      for (int w = 0; w < kTeGroup / 4; w++) {
+        uint32_t word = 0;
+        for (int b = 0; b < 4; b++) word |= (uint32_t)e.dir[4 * w + b] << (8 * b);
+        hp.te_dir.push_back((int32_t)word);
+      }
+    }
+    for (int s = 0; s < kTeGroup; s++) hp.te_mem.push_back(s < (int)mem.size() ? mem[s] : -1);
+    hp.te_start.push_back((int32_t)hp.te_src.size());
+  }
+
+  // tiles: a multiple of 4 pairs (16 columns) with M pairs * M units <= 256
+  // threads, at most all M^2 pairs
+  const int M = hp.pw.M;
+  hp.te_tp = std::min(std::max(1, 4 * (256 / (4 * M))), M * M);
+  const int ntile = (M * M + hp.te_tp - 1) / hp.te_tp;
+  // workgroup cost model (units of one source rotation of a tile): the
+  // rotations, one load per entry, and the plane contractions
+  const int32_t ng = (int32_t)groups.size();
+  std::vector<double> work(ng);
+  for (int32_t g = 0; g < ng; g++) {
+    double w = hp.te_start[g + 1] - hp.te_start[g];
+    for (int32_t A : groups[g])
+      w += (hp.plist_start[A + 1] - hp.plist_start[A]) + 4.0 * (hp.plane_start[A + 1] - hp.plane_start[A]);
+    work[g] = w;
+  }
+  std::vector<int32_t> order(ng);
+  for (int32_t g = 0; g < ng; g++) order[g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+  const int fixed = ntile / kXcdCount * kXcdCount;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> q(kXcdCount);
+  std::vector<double> load(kXcdCount, 0.0);
+  for (int32_t g : order)
+    for (int t = 0; t < ntile; t++) {
+      int x = t % kXcdCount;
+      if (t >= fixed)
+        x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      q[x].push_back({g, t});
+      load[x] += work[g];
+    }
+  size_t len = 0;
+  for (auto& v : q) len = std::max(len, v.size());
+  hp.te_wg.assign(2 * len * kXcdCount, -1);
+  for (int x = 0; x < kXcdCount; x++)
+    for (size_t k = 0; k < q[x].size(); k++) {
+      hp.te_wg[2 * (k * kXcdCount + x)] = q[x][k].first;
+      hp.te_wg[2 * (k * kXcdCount + x) + 1] = q[x][k].second;
+    }
+}
+
 int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord, int p,
                     double delta, double tol, int bc, int precision, double eps_internal,
                     int force_lc, bool allow_fuse, HostPlan& hp, std::string& err) {
@@ -408,9 +518,12 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
   // ---- P-lists (Definition before Algorithm 4, read for every box with f = 1):
   // colleagues with f = 1 (images included when periodic), excluding pairs of
   // two leaves, which the near field handles.
+  // Each list is sorted by (source box, code), the order the fused translation's
+  // target groups keep for every member.
   hp.plist_start.assign(nA + 1, 0);
   for (int32_t a = 0; a < nA; a++) {
     const LcBox& A = lcbox[pwb[a]];
+    std::vector<std::pair<int32_t, int32_t>> ents;  // (source box, code)
     for (int code = 0; code < n3; code++) {
       int dir[3];
       dir_of(code, d, dir);
@@ -420,8 +533,7 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
         bool zero = true;
         for (int a = 0; a < d; a++) zero = zero && dir[a] == 0;
         if (!zero) continue;
-        hp.plist_src.push_back(A.idx);
-        hp.plist_dir.push_back(code);
+        ents.push_back({A.idx, code});
         continue;
       }
       if (!neighbor(lc, A.c, dir, q, nullptr)) continue;
@@ -429,10 +541,20 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
       if (it == lcmap.end()) continue;
       const LcBox& B = lcbox[it->second];
       if (!B.f || (A.isleaf && B.isleaf)) continue;
-      hp.plist_src.push_back(B.idx);
-      hp.plist_dir.push_back(code);  // dir = B - A per axis
+      ents.push_back({B.idx, code});  // dir = B - A per axis
+    }
+    std::sort(ents.begin(), ents.end());
+    for (auto& e : ents) {
+      hp.plist_src.push_back(e.first);
+      hp.plist_dir.push_back(e.second);
     }
     hp.plist_start[a + 1] = (int32_t)hp.plist_src.size();
+  }
+  if (d == 3 && hp.fuse_te) {
+    std::vector<int32_t> bc((size_t)nA * 3);
+    for (int32_t a = 0; a < nA; a++)
+      for (int ax = 0; ax < 3; ax++) bc[(size_t)a * 3 + ax] = lcbox[pwb[a]].c[ax];
+    build_te_groups(hp, bc);
   }
 
   // ---- D-lists: every leaf at level <= lc gathers from its leaf neighbors at

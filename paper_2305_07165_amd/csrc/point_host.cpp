@@ -401,16 +401,28 @@ int build_point_plan(int d, int64_t nsrc, const double* src, int64_t ntgt, const
   hp.pwbox_isleaf.assign(nA, 0);
   finish_pw_lists(hp, pl, nA, ph.px_level.data(), ph.px_coord.data(), true);
   // P-lists: the dense colleagues of every plane-wave box, itself included
+  // (each list sorted by source box, then code: see build_te_groups)
   hp.plist_start.assign(nA + 1, 0);
   for (int32_t a = 0; a < nA; a++) {
+    std::vector<std::pair<int32_t, int32_t>> ents;
     for (int code = 0; code < n3; code++) {
       int32_t q[3];
       const int32_t j = colleague(pwbox[a], code, q);
       if (j < 0 || !ph.leaf_dense[j]) continue;
-      hp.plist_src.push_back(pwidx[j]);
-      hp.plist_dir.push_back(code);  // dir = source - target per axis
+      ents.push_back({pwidx[j], code});  // dir = source - target per axis
+    }
+    std::sort(ents.begin(), ents.end());
+    for (auto& e : ents) {
+      hp.plist_src.push_back(e.first);
+      hp.plist_dir.push_back(e.second);
     }
     hp.plist_start[a + 1] = (int32_t)hp.plist_src.size();
+  }
+  if (d == 3 && hp.fuse_te) {
+    std::vector<int32_t> bc((size_t)nA * 3);
+    for (int32_t a = 0; a < nA; a++)
+      for (int ax = 0; ax < 3; ax++) bc[(size_t)a * 3 + ax] = t2.coord[(size_t)pwbox[a] * 3 + ax];
+    build_te_groups(hp, bc);
   }
   hp.nvtab = 0;
   build_tables(hp);

@@ -187,7 +187,8 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
                                                 const int32_t* __restrict__ fitem,
                                                 const int32_t* __restrict__ leaf_tab,
                                                 const elem_t<C>* __restrict__ F, int p, int nr,
-                                                int ncoltiles, elem_t<C>* __restrict__ phi,
+                                                int ncoltiles, int nmodes, int tp, int64_t ncoef_phi,
+                                                elem_t<C>* __restrict__ phi,
                                                 elem_t<C>* __restrict__ partial, int bid) {
   typedef elem_t<C> T;
   // one work item (<= kFormLeaves leaves of a box) x 64 H columns per
@@ -254,8 +255,15 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
       for (int ti = 0; ti < NT; ti++) a[ti][kk] = an[ti][kk];
     }
   }
-  // a box's only item writes phi; items of a split box write partial sums
-  T* out = slot < 0 ? phi + (int64_t)A * nr * N2 : partial + (int64_t)slot * nr * N2;
+  // a box's only item writes phi; items of a split box write partial sums,
+  // tile-major with tp pairs per tile when tp > 0 (d = 3, kernels.h)
+  T* out = slot < 0 ? phi + (int64_t)A * ncoef_phi : partial + (int64_t)slot * ncoef_phi;
+  const bool tiled = D == 3 && tp > 0;
+  const int64_t rstride = tiled ? 4 * tp : N2;
+  int64_t coff[H];
+#pragma unroll
+  for (int h = 0; h < H; h++)
+    coff[h] = tiled && colok[h] ? phi_tiled_col(nmodes, tp, nr, col[h] / nr, col[h] - (col[h] / nr) * nr) : col[h];
 #pragma unroll
   for (int ti = 0; ti < NT; ti++)
 #pragma unroll
@@ -263,7 +271,7 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
       const int r = 16 * ti + M::row(lk, t);
 #pragma unroll
       for (int h = 0; h < H; h++)
-        if (r < nr && colok[h]) out[(int64_t)r * N2 + col[h]] = acc[ti][h][t];
+        if (r < nr && colok[h]) out[(int64_t)r * rstride + coff[h]] = acc[ti][h][t];
     }
 }
 
@@ -284,93 +292,83 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 
 // ---------------------------------------------------------------------------
 // d = 3 out->in translation fused with the first evaluation contraction.
-// A workgroup owns one cutoff box A and one tile of mode columns (r1, r2):
-// the stored pair r1 = 2 m1, 2 m1 + 1 of one axis-1 mode m1 times the pairs of
-// a run of axis-2 modes -- all of them, whole rows, while they fit in 64
-// columns -- so every (cos, sin) partner is inside the tile.  Phase 1 gathers
-// psi_A[r3][tile] = sum_{B in P(A)} Rot(c_B - c_A) phi_B[r3][tile] into LDS (a
-// thread owns the 2 x 2 x 2 coefficients of one (m3, m2) unit: four aligned
-// pairs along r2, loaded as vectors); phase 2 contracts it with the axis-3
-// evaluation table of every plane of A, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
-// psi_A[r3][c], 16-column groups spread over the waves.  psi never goes to HBM.
+// A workgroup owns one target group (up to kTeGroup sibling cutoff boxes, with
+// the union of their P-lists: fgt_host.h te_*) and one tile of mode-column
+// pairs (m1, m2).  Phase 1: a thread owns one unit (m3, pair), the 2 x 2 x 2
+// coefficients of the cos/sin members of m1, m2, m3 (four aligned pairs along
+// r2, loaded as vectors); each source box of the group is loaded once and
+// rotated into the accumulators of every member that takes it,
+// psi_A = sum_{B in P(A)} Rot(c_B - c_A) phi_B.  The members' psi tiles are
+// staged in LDS kTeSlots at a time; phase 2 contracts each with the axis-3
+// evaluation table of every plane of its box, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
+// psi_A[r3][c], the (member, plane, 16-column group) items split evenly over
+// the waves.  psi never goes to HBM.
+constexpr int kTeSlots = 4;  // member tiles held in LDS at once
 
-// axis-2 modes per tile: all of them (whole r2 rows) while 2M <= 64; else at
-// most 16 with M * modes <= 256
-__host__ __device__ inline int transeval_modes(int M) {
-  if (M <= 32) return M;
-  return M <= 16 ? 16 : (256 / M > 0 ? 256 / M : 1);
-}
-
-// LDS of the psi tile: nr rows of LDW = 2 nr + 1 columns (odd, to spread the
-// banks; a tile holds at most 2 nr columns since fused plans have 2M <= 64)
-__host__ __device__ inline int transeval_ldw(int nr) { return 2 * nr + 1; }
-inline size_t transeval_lds(int nr, size_t ts) { return (size_t)nr * transeval_ldw(nr) * ts; }
+// LDS of the psi tiles: kTeSlots tiles of nr rows of 4 tp + 1 columns (odd,
+// to spread the banks)
+inline size_t transeval_lds(int tp, int nr, size_t ts) { return (size_t)kTeSlots * nr * (4 * tp + 1) * ts; }
+// the most any plan of NT 16-row mode tiles needs: nr 4 tp <= 2048 (the tiles'
+// 256 units of 8 coefficients) and nr <= 16 NT
+inline size_t transeval_lds_max(int NT, size_t ts) { return (size_t)kTeSlots * (2048 + 16 * NT) * ts; }
 
 template <typename C, int NT>
 __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ phi,
-                                                const int32_t* __restrict__ plist_start,
-                                                const int32_t* __restrict__ plist_src,
-                                                const int32_t* __restrict__ plist_dir,
+                                                const int32_t* __restrict__ te_start,
+                                                const int32_t* __restrict__ te_mem,
+                                                const int32_t* __restrict__ te_src,
+                                                const int32_t* __restrict__ te_dir,
+                                                const int32_t* __restrict__ te_wg,
                                                 const elem_t<C>* __restrict__ rot,
                                                 const int32_t* __restrict__ plane_start,
                                                 const int32_t* __restrict__ plane_tab,
                                                 const elem_t<C>* __restrict__ E, int p, int M,
-                                                int nr, int nA, elem_t<C>* __restrict__ Z,
+                                                int nr, int TP, elem_t<C>* __restrict__ Z,
                                                 elem_t<C>* __restrict__ ps, int bid) {
   typedef elem_t<C> T;
   typedef typename Pair2<T>::type T2;
   typedef Mfma<C> M_;
   typedef typename M_::acc acc_t;
-  constexpr int Q = 4 * NT;
-  const int TM = transeval_modes(M);
-  const int LDW = transeval_ldw(nr);
-  const int nb2 = (M + TM - 1) / TM;
-  const int ntile = M * nb2;
-  // XCD x first sweeps every box (Morton order) for tiles x, x + 8, ... of the
-  // full rounds, so each such phi slice is fetched into one L2 only; the
-  // remaining ntile % 8 tiles are split into 8 contiguous box ranges, one per
-  // XCD, which keeps the work of the XCDs equal
-  const int nbx = (nA + kXcds - 1) / kXcds;
-  const int rounds = ntile / kXcds;
-  const int xcd = bid % kXcds, local = bid / kXcds;
-  int A, tile;
-  if (local < rounds * nA) {
-    const int r = local / nA;
-    A = local - r * nA;
-    tile = kXcds * r + xcd;
-  } else {
-    const int j = local - rounds * nA;
-    A = xcd * nbx + j % nbx;
-    tile = kXcds * rounds + j / nbx;
-  }
-  if (A >= nA || tile >= ntile) return;  // whole workgroup
-  const int m1 = tile / nb2, b2 = tile - m1 * nb2;
-  const int mlo = b2 * TM, mhi = min(M, mlo + TM), nm2 = mhi - mlo;
-  const int r2first = 2 * mlo;
-  const int n2 = 2 * nm2;  // r2 columns of the tile
-  const int ncol = 2 * n2;
-  const int64_t nr2 = (int64_t)nr * nr, ncoef = nr2 * nr;
+  constexpr int G = kTeGroup, S = kTeSlots, Q = 4 * NT;
+  const int LDW = 4 * TP + 1;
+  const int npair = M * M;
+  const int ntile = (npair + TP - 1) / TP;
+  // the plan's workgroup table: group and tile, longest first per XCD
+  const int g = te_wg[2 * bid], tile = te_wg[2 * bid + 1];
+  if (g < 0) return;  // whole workgroup
+  const int j0 = tile * TP;
+  const int tph = min(TP, npair - j0);  // pairs of this tile
+  const int ncol = 4 * tph;             // column c = v1 (2 tph) + 2 jj + v2
+  const int64_t nr2 = (int64_t)nr * nr;
+  const int64_t ncoef = (int64_t)ntile * nr * 4 * TP;  // tile-major phi (kernels.h)
   const int tid = threadIdx.x;
-  // ---- phase 1: translations into LDS
-  const int q0 = plist_start[A], q1 = plist_start[A + 1];
-  const T cs1 = rot[2 * m1], sn1 = rot[2 * m1 + 1];
-  for (int unit = tid; unit < M * nm2; unit += blockDim.x) {
-    const int m3 = unit / nm2, m2 = mlo + (unit - (unit / nm2) * nm2);
-    const T cs2 = rot[2 * m2], sn2 = rot[2 * m2 + 1];
-    const T cs3 = rot[2 * m3], sn3 = rot[2 * m3 + 1];
-    // coefficient v = v1 + 2 v2 + 4 v3 (bit a: sin member of the axis pair);
-    // pair w = v1 + 2 v3 holds v2 = 0, 1 at off[w], off[w] + 1
+  const bool active = tid < M * tph;
+  const int m3 = active ? tid / tph : 0;
+  const int jj = active ? tid - m3 * tph : 0;
+  const int m1 = (j0 + jj) / M, m2 = (j0 + jj) - m1 * M;
+
+  // ---- phase 1: translations of every member into registers
+  T acc[G][8];
+#pragma unroll
+  for (int t = 0; t < G; t++)
+#pragma unroll
+    for (int v = 0; v < 8; v++) acc[t][v] = 0;
+  const int e0 = te_start[g], e1 = te_start[g + 1];
+  if (active && e0 < e1) {
+    const T cs[3] = {rot[2 * m1], rot[2 * m2], rot[2 * m3]};
+    const T sn[3] = {rot[2 * m1 + 1], rot[2 * m2 + 1], rot[2 * m3 + 1]};
+    // coefficient v = v1 + 2 v2 + 4 v3 (bit a: sin member of the axis-(a+1)
+    // pair); pair w = v1 + 2 v3 holds v2 = 0, 1 at off[w], off[w] + 1 of the
+    // tile's block, whose rows are 4 TP apart
     int off[4];
 #pragma unroll
     for (int w = 0; w < 4; w++) {
       const int v1 = w & 1, v3 = w >> 1;
-      off[w] = (2 * m3 + v3) * (int)nr2 + (2 * m1 + v1) * nr + 2 * m2;
+      off[w] = (2 * m3 + v3) * 4 * TP + v1 * 2 * TP + 2 * jj;
     }
-    T acc[8];
-#pragma unroll
-    for (int v = 0; v < 8; v++) acc[v] = 0;
-    auto fetch = [&](int q, T (&x)[8]) {
-      const T* src = phi + (int64_t)plist_src[min(q, q1 - 1)] * ncoef;
+    const int64_t tile_off = (int64_t)tile * nr * 4 * TP;
+    auto fetch = [&](int e, T (&x)[8]) {
+      const T* src = phi + (int64_t)te_src[min(e, e1 - 1)] * ncoef + tile_off;
 #pragma unroll
       for (int w = 0; w < 4; w++) {
         const T2 v2 = *reinterpret_cast<const T2*>(src + off[w]);
@@ -379,121 +377,173 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
         x[v | 2] = v2.y;
       }
     };
-    // rotations along every displaced axis; the last one adds straight into acc
-    auto apply = [&](int q, T (&x)[8]) {
-      const int code = plist_dir[q];
-      const int d1 = code % 3 - 1, d2 = (code / 3) % 3 - 1, d3 = code / 9 - 1;
-      const int last = d3 != 0 ? 2 : (d2 != 0 ? 1 : (d1 != 0 ? 0 : -1));
-      const T c[3] = {cs1, cs2, cs3};
-      const T s[3] = {d1 > 0 ? sn1 : -sn1, d2 > 0 ? sn2 : -sn2, d3 > 0 ? sn3 : -sn3};
-      const int dd[3] = {d1, d2, d3};
+    // rotations along every displaced axis of direction `code`; the last one
+    // adds straight into a
+    auto apply = [&](int code, const T (&x)[8], T (&a)[8]) {
+      const int dd[3] = {code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1};
+      const int last = dd[2] != 0 ? 2 : (dd[1] != 0 ? 1 : (dd[0] != 0 ? 0 : -1));
+      T y[8];
 #pragma unroll
-      for (int a = 0; a < 3; a++) {
-        if (dd[a] == 0) continue;
-        const int bit = 1 << a;
-        if (a == last) {
+      for (int v = 0; v < 8; v++) y[v] = x[v];
+#pragma unroll
+      for (int ax = 0; ax < 3; ax++) {
+        if (dd[ax] == 0) continue;
+        const T c = cs[ax], s = dd[ax] > 0 ? sn[ax] : -sn[ax];
+        const int bit = 1 << ax;
+        if (ax == last) {
 #pragma unroll
           for (int v = 0; v < 8; v++) {
             if (v & bit) continue;
-            const T xc = x[v], xs = x[v | bit];
-            acc[v] = fma(c[a], xc, acc[v]);
-            acc[v] = fma(-s[a], xs, acc[v]);
-            acc[v | bit] = fma(s[a], xc, acc[v | bit]);
-            acc[v | bit] = fma(c[a], xs, acc[v | bit]);
+            const T xc = y[v], xs = y[v | bit];
+            a[v] = fma(c, xc, a[v]);
+            a[v] = fma(-s, xs, a[v]);
+            a[v | bit] = fma(s, xc, a[v | bit]);
+            a[v | bit] = fma(c, xs, a[v | bit]);
           }
         } else {
 #pragma unroll
           for (int v = 0; v < 8; v++) {
             if (v & bit) continue;
-            const T xc = x[v], xs = x[v | bit];
-            x[v] = c[a] * xc - s[a] * xs;
-            x[v | bit] = s[a] * xc + c[a] * xs;
+            const T xc = y[v], xs = y[v | bit];
+            y[v] = c * xc - s * xs;
+            y[v | bit] = s * xc + c * xs;
           }
         }
       }
       if (last < 0) {
 #pragma unroll
-        for (int v = 0; v < 8; v++) acc[v] += x[v];
+        for (int v = 0; v < 8; v++) a[v] += y[v];
       }
     };
+    auto members = [&](int e, const T (&x)[8]) {
+      const uint32_t w0 = (uint32_t)te_dir[2 * e], w1 = (uint32_t)te_dir[2 * e + 1];
+#pragma unroll
+      for (int t = 0; t < G; t++) {
+        const int code = (int)(((t < 4 ? w0 : w1) >> (8 * (t & 3))) & 0xFF);
+        if (code != kTeNoDir) apply(code, x, acc[t]);
+      }
+    };
+    // two sources in flight: the loads of entry e+1 are issued before the
+    // rotations of entry e (an e past the list reloads the last source)
     T xa[8], xb[8];
-    if (q0 < q1) {
-      fetch(q0, xa);
-      for (int q = q0; q < q1; q += 2) {
-        fetch(q + 1, xb);
-        apply(q, xa);
-        if (q + 1 < q1) {
-          fetch(q + 2, xa);
-          apply(q + 1, xb);
+    fetch(e0, xa);
+    for (int e = e0; e < e1; e += 2) {
+      fetch(e + 1, xb);
+      members(e, xa);
+      if (e + 1 < e1) {
+        fetch(e + 2, xa);
+        members(e + 1, xb);
+      }
+    }
+  }
+
+  // ---- phase 2, kTeSlots members at a time: Z_P[i3][c] = sum_r3 E3_P[i3][r3]
+  // psi_A[r3][c].  A wave takes a contiguous run of (slot, plane, column
+  // group) items and loads a plane's axis-3 table once for its column groups.
+  // The K index of (group g, step kk) is 16 g + 4 lk + kk: a lane's four table
+  // entries are two aligned pairs of its row, loaded as vectors.
+  const int lane = lane_of(), w = wave_of();
+  const int nw = (int)blockDim.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int ncg = (ncol + 15) / 16;
+#pragma unroll
+  for (int pass = 0; pass < G / S; pass++) {
+    int memA[S], P0[S], np[S];
+    bool any = false;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+      memA[s] = te_mem[(int64_t)g * G + pass * S + s];
+      any = any || memA[s] >= 0;
+      P0[s] = memA[s] >= 0 ? plane_start[memA[s]] : 0;
+      np[s] = memA[s] >= 0 ? plane_start[memA[s] + 1] - P0[s] : 0;
+    }
+    if (!any) continue;  // uniform over the workgroup
+    if (pass > 0) __syncthreads();  // the previous pass has read its tiles
+    if (active) {
+#pragma unroll
+      for (int s = 0; s < S; s++) {
+        if (memA[s] < 0) continue;
+        T* pt = ps + s * nr * LDW;
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+          const int v1 = v & 1, v2 = (v >> 1) & 1, v3 = v >> 2;
+          pt[(2 * m3 + v3) * LDW + v1 * 2 * tph + 2 * jj + v2] = acc[pass * S + s][v];
         }
       }
     }
+    __syncthreads();
+    int total = 0;
 #pragma unroll
-    for (int v = 0; v < 8; v++) {
-      const int v1 = v & 1, v2 = (v >> 1) & 1, v3 = v >> 2;
-      ps[(2 * m3 + v3) * LDW + v1 * n2 + (2 * (m2 - mlo) + v2)] = acc[v];
-    }
-  }
-  __syncthreads();
-  // ---- phase 2: Z_P[i3][c] = sum_r3 E3_P[i3][r3] psi[r3][c], 16 columns per wave.
-  // Planes outer: a wave loads the plane's axis-3 table once and applies it to
-  // each of its column groups.  Both operands come from memory or LDS, so the
-  // K index of (group g, step kk) is 16 g + 4 lk + kk: a lane's four table
-  // entries are two aligned pairs of its row, loaded as vectors.
-  const int lane = lane_of(), w = wave_of();
-  const int lr = lane & 15, lk = lane >> 4;
-  const int P0 = plane_start[A], P1 = plane_start[A + 1];
-  for (int P = P0; P < P1; P++) {
-    const T* E3 = E + (int64_t)plane_tab[P * 3 + 2] * p * nr;
+    for (int s = 0; s < S; s++) total += np[s] * ncg;
+    const int it0 = (int)((int64_t)total * w / nw), it1 = (int)((int64_t)total * (w + 1) / nw);
+    int lastP = -1;
     T aq[Q];
 #pragma unroll
-    for (int g = 0; g < NT; g++)
+    for (int i = 0; i < Q; i++) aq[i] = 0;
+    for (int it = it0; it < it1; it++) {
+      int slot = -1, r = it, P = 0;
 #pragma unroll
-      for (int h = 0; h < 2; h++) {
-        const int k = 16 * g + 4 * lk + 2 * h;  // even: the pair (k, k+1) is inside the row or past it
-        const bool ok = lr < p && k < nr;
-        const T2 v2 = *reinterpret_cast<const T2*>(E3 + (ok ? lr * nr + k : 0));
-        aq[4 * g + 2 * h] = ok ? v2.x : (T)0;
-        aq[4 * g + 2 * h + 1] = ok ? v2.y : (T)0;
+      for (int s = 0; s < S; s++) {
+        const int n = np[s] * ncg;
+        if (slot < 0) {
+          if (r < n) {
+            slot = s;
+            P = P0[s];
+          } else {
+            r -= n;
+          }
+        }
       }
-    T* Zp = Z + (int64_t)P * p * nr2;
-    for (int cg = w; 16 * cg < ncol; cg += 4) {  // column groups of 16, no barrier follows
+      const int pq = r / ncg;
+      const int cg = r - pq * ncg;
+      P += pq;
+      if (P != lastP) {
+        lastP = P;
+        const T* E3 = E + (int64_t)plane_tab[P * 3 + 2] * p * nr;
+#pragma unroll
+        for (int gk = 0; gk < NT; gk++)
+#pragma unroll
+          for (int h = 0; h < 2; h++) {
+            const int k = 16 * gk + 4 * lk + 2 * h;  // even: the pair (k, k+1) is inside the row or past it
+            const bool ok = lr < p && k < nr;
+            const T2 v2 = *reinterpret_cast<const T2*>(E3 + (ok ? lr * nr + k : 0));
+            aq[4 * gk + 2 * h] = ok ? v2.x : (T)0;
+            aq[4 * gk + 2 * h + 1] = ok ? v2.y : (T)0;
+          }
+      }
+      const T* pt = ps + slot * nr * LDW;
       const int col = 16 * cg + lr;
       const bool colok = col < ncol;
-      acc_t acc;
-      zero4(acc);
+      acc_t d;
+      zero4(d);
 #pragma unroll
-      for (int g = 0; g < NT; g++) {
+      for (int gk = 0; gk < NT; gk++) {
         T aqg[4], bq[4];
 #pragma unroll
         for (int kk = 0; kk < 4; kk++) {
-          const int k = 16 * g + 4 * lk + kk;
-          const T v = ps[(k < nr && colok ? k * LDW + col : 0)];  // LDS: select, no branch
+          const int k = 16 * gk + 4 * lk + kk;
+          const T v = pt[(k < nr && colok ? k * LDW + col : 0)];  // LDS: select, no branch
           bq[kk] = k < nr && colok ? v : (T)0;
-          aqg[kk] = aq[4 * g + kk];
+          aqg[kk] = aq[4 * gk + kk];
         }
-        acc = M_::template steps<4>(aqg, bq, acc);
+        d = M_::template steps<4>(aqg, bq, d);
       }
-      const int i1 = col < n2 ? 0 : 1;
-      const int r1 = 2 * m1 + i1;
-      const int r2 = r2first + col - i1 * n2;
-      const int64_t cglob = (int64_t)r1 * nr + r2;
+      const int v1 = col >= 2 * tph ? 1 : 0;
+      const int rem = col - v1 * 2 * tph;
+      const int jc = j0 + (rem >> 1);
+      const int mc1 = jc / M, mc2 = jc - mc1 * M;
+      const int64_t cglob = (int64_t)(2 * mc1 + v1) * nr + 2 * mc2 + (rem & 1);
+      T* Zp = Z + (int64_t)P * p * nr2;
 #pragma unroll
       for (int t = 0; t < 4; t++) {
         const int i3 = M_::row(lk, t);
-        if (i3 < p && colok) Zp[(int64_t)i3 * nr2 + cglob] = acc[t];
+        if (i3 < p && colok) Zp[(int64_t)i3 * nr2 + cglob] = d[t];
       }
     }
   }
 }
 
-inline int64_t transeval3_blocks(const DeviceArgs& a) {
-  const int tm = transeval_modes(a.M);
-  const int64_t nb2 = (a.M + tm - 1) / tm, ntile = a.M * nb2;
-  const int64_t nbx = (a.nA + kXcds - 1) / kXcds;
-  const int64_t rounds = ntile / kXcds, rem = ntile - rounds * kXcds;
-  return kXcds * (rounds * a.nA + rem * nbx);
-}
+inline int64_t transeval3_blocks(const DeviceArgs& a) { return a.nTW; }
 
 // ---------------------------------------------------------------------------
 // first evaluation contraction: Z rows of every leaf of one box for one tile of

@@ -557,3 +557,86 @@ def test_tree_entry_points_validate_arguments_before_any_device_call():
     assert L.fgt_sample_gaussians(ctypes.byref(g), ctypes.byref(tree), 8, None, None) == _lib.FGT_ERR_INVALID_ARG
     assert out.value is None
     del keep, keep2, gk
+
+
+# ---------------------------------------------------------------------------
+# target groups of the fused 3D translation (fgt_host.h te_*)
+
+
+def _two_level_tree(seed, frac):
+    """Level-4 boxes of the unit cube, a random fraction of them split into
+    their eight level-5 children (always 2:1 balanced)."""
+    rng = np.random.default_rng(seed)
+    lv, cs = [], []
+    for c in np.ndindex(16, 16, 16):
+        if rng.random() < frac:
+            for ch in np.ndindex(2, 2, 2):
+                lv.append(5)
+                cs.append([2 * c[0] + ch[0], 2 * c[1] + ch[1], 2 * c[2] + ch[2]])
+        else:
+            lv.append(4)
+            cs.append(list(c))
+    return np.array(lv, np.int32), np.array(cs, np.int32)
+
+
+@pytest.mark.parametrize("frac,periodic", [(0.05, False), (0.05, True), (1.0, False)])
+def test_fused_translation_groups(frac, periodic):
+    lv, cs = _two_level_tree(7, frac)
+    pl = _plan(lv, cs, 4, 1e-4, 1e-6, periodic=periodic)
+    info = pl.info()
+    assert info["fused_translate"] == 1 and info["lc"] == 4
+    lc = info["lc"]
+    pws, pid = pl.array("pw_start"), pl.array("pwleaf_id")
+    nA = len(pws) - 1
+    bc = np.array([cs[pid[pws[a]]] >> (lv[pid[pws[a]]] - lc) for a in range(nA)])
+    ps, src, code = pl.array("plist_start"), pl.array("plist_src"), pl.array("plist_dir")
+    ts, mem = pl.array("te_start"), pl.array("te_mem").reshape(-1, 8)
+    tsrc, tdir = pl.array("te_src"), pl.array("te_dir").view(np.uint32).reshape(-1, 2)
+    assert len(ts) == len(mem) + 1 and ts[0] == 0 and ts[-1] == len(tsrc) == len(tdir)
+    # every P-list sorted by (source box, code)
+    for A in range(nA):
+        pairs = list(zip(src[ps[A]:ps[A + 1]].tolist(), code[ps[A]:ps[A + 1]].tolist()))
+        assert pairs == sorted(pairs)
+    seen = np.zeros(nA, int)
+    sizes = []
+    for g in range(len(mem)):
+        members = [int(m) for m in mem[g] if m >= 0]
+        assert members == [int(m) for m in mem[g][:len(members)]]  # filled from slot 0
+        sizes.append(len(members))
+        seen[members] += 1
+        # siblings: one parent at level lc - 1
+        assert len({tuple(bc[m] >> 1) for m in members}) == 1
+        es = range(ts[g], ts[g + 1])
+        assert [int(tsrc[e]) for e in es] == sorted(int(tsrc[e]) for e in es)
+        for t in range(8):
+            got = []
+            for e in es:
+                c = int(tdir[e][t // 4] >> (8 * (t % 4))) & 0xFF
+                if c != 0xFF:
+                    assert t < len(members)
+                    got.append((int(tsrc[e]), c))
+            if t < len(members):
+                A = members[t]
+                # the member meets exactly its P-list, in its order
+                assert got == list(zip(src[ps[A]:ps[A + 1]].tolist(), code[ps[A]:ps[A + 1]].tolist()))
+        # every entry serves some member
+        assert all(any((int(tdir[e][t // 4] >> (8 * (t % 4))) & 0xFF) != 0xFF for t in range(8)) for e in es)
+    assert np.all(seen == 1)
+    # groups share sources: fewer entries than P-list pairs
+    assert len(tsrc) < len(src)
+    # workgroups: every (group, tile) once; tile t runs on XCD t % 8 except
+    # the tiles past the last multiple of 8
+    wg = pl.array("te_wg").reshape(-1, 2)
+    ntile = int(wg[:, 1].max()) + 1
+    assert len(wg) % 8 == 0
+    live = wg[wg[:, 0] >= 0]
+    assert len(live) == len(mem) * ntile
+    assert len({(int(a), int(b)) for a, b in live}) == len(live)
+    fixed = ntile // 8 * 8
+    for b, (g, t) in enumerate(wg):
+        if g >= 0 and t < fixed:
+            assert b % 8 == t % 8
+    if frac == 1.0:
+        assert set(sizes) == {8}
+    else:
+        assert min(sizes) < 8
