@@ -197,9 +197,10 @@ int fgt_periodic_terms(double eps, double delta);
  * "plist_src", "plist_dir", "echunk", "fitem", "fred", "near_tgt",
  * "near_haspw", "near_start", "near_src", "near_tab", "ftab_meta", "vtab_meta",
  * "plane_start", "plane_tab", "plane_row", "row_start", "row_tab", and the
- * fused translation's target groups "te_start", "te_mem" (8 member boxes per
- * group, -1 = empty), "te_src", "te_dir" (two words per entry, byte t the
- * direction code of member t, 0xFF = not a source of it) (int32).
+ * fused translation's target groups "te_start", "te_mem" (4 member boxes per
+ * group, -1 = empty), "te_src", "te_dir" (one word per entry, byte t the
+ * direction code of member t, 0xFF = not a source of it) and its workgroups
+ * "te_wg" (group, tile) (int32).
  * Writes at most cap elements to dst (may be NULL to query) and returns the
  * array's length, or a negative code.
  */

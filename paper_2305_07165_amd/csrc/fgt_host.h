@@ -16,7 +16,7 @@ constexpr double kMinTolBf16x3 = 1e-4 * (1 - 1e-9);
 constexpr int kMaxModes = 128; // stored plane-wave modes per axis (2M)
 constexpr int kFormLeaves = 8; // leaves per formation work item
 constexpr double kFuseBytes = 128e6;  // psi bytes above which the 3D translation is fused
-constexpr int kTeGroup = 8;    // target boxes per fused-translation group (siblings)
+constexpr int kTeGroup = 4;    // target boxes per fused-translation group (siblings)
 constexpr int kTeNoDir = 0xFF; // group entry: the member does not take this source
 constexpr int kXcdCount = 8;   // XCDs (separate L2s) of the device; workgroup b runs on b % 8
 
@@ -72,8 +72,9 @@ struct HostPlan {
   std::vector<int32_t> plist_src;     // [nP] plane-wave box index
   std::vector<int32_t> plist_dir;     // [nP] sum_a (dir_a+1) 3^a, dir = src - dst
                                       // (each box's list sorted by source box, then code)
-  // d = 3 fused translation: groups of up to kTeGroup target boxes that share
-  // their parent at level lc - 1, each with the union of its members' P-lists.
+  // d = 3 fused translation: groups of up to kTeGroup target boxes, the
+  // children of one parent at level lc - 1 that share their position along
+  // axis 3, each with the union of its members' P-lists.
   // Entry e of group g is a source box te_src[e] and, per member slot t, its
   // direction code in the member's P-list (byte t % 4 of te_dir[2e + t / 4];
   // kTeNoDir: not in it).  A member meets its own P-list in its own order.

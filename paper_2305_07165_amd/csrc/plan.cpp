@@ -186,12 +186,13 @@ void finish_pw_lists(HostPlan& hp, std::vector<PwLeafRef>& pl, int32_t nA, const
 }
 
 // Fused-translation target groups: the plane-wave boxes that share a parent at
-// level lc - 1 (siblings, contiguous in Morton order).  The entries of a group
-// are the distinct (source box, rank) pairs of its members' P-lists, rank
-// counting repeats of one source in one list (a box that is its own neighbor
-// through two periodic images), sorted by source box then rank.  Since every
-// P-list is sorted by (source box, code), a member meets its sources in its
-// own list's order, so its sum is formed in the same order as on its own.
+// level lc - 1 and their position along axis 3 (at most four, contiguous in
+// Morton order).  The entries of a group are the distinct (source box, rank)
+// pairs of its members' P-lists, rank counting repeats of one source in one
+// list (a box that is its own neighbor through two periodic images), sorted by
+// source box then rank.  Since every P-list is sorted by (source box, code), a
+// member meets its sources in its own list's order, so its sum is formed in
+// the same order as on its own.
 void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
   hp.te_start.assign(1, 0);
   hp.te_mem.clear();
@@ -202,8 +203,9 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
   std::unordered_map<uint64_t, int32_t> gmap;
   std::vector<std::vector<int32_t>> groups;
   for (int32_t a = 0; a < nA; a++) {
-    uint64_t k = 0;
-    for (int ax = 0; ax < 3; ax++) k = (k << 21) | (uint32_t)(box_coord[(size_t)a * 3 + ax] >> 1);
+    const int32_t* c = &box_coord[(size_t)a * 3];
+    const uint64_t k = ((uint64_t)(uint32_t)(c[0] >> 1) << 42) | ((uint64_t)(uint32_t)(c[1] >> 1) << 21) |
+                       (uint64_t)(uint32_t)c[2];
     auto it = gmap.find(k);
     if (it == gmap.end()) {
       gmap.emplace(k, (int32_t)groups.size());
@@ -216,7 +218,8 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
     int32_t src, rank;
     uint8_t dir[kTeGroup];
   };
-  for (const auto& mem : groups) {
+  // the entries of a member set, sorted
+  auto entries_of = [&](const std::vector<int32_t>& mem) {
     std::vector<Ent> ents;
     std::unordered_map<uint64_t, size_t> at;  // (src, rank) -> entry
     for (size_t t = 0; t < mem.size(); t++) {
@@ -244,6 +247,13 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
     std::sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) {
       return x.src != y.src ? x.src < y.src : x.rank < y.rank;
     });
+    return ents;
+  };
+  const int32_t ng = (int32_t)groups.size();
+  std::vector<double> work(ng);
+  for (int32_t g = 0; g < ng; g++) {
+    const auto& mem = groups[g];
+    const std::vector<Ent> ents = entries_of(mem);
     for (const Ent& e : ents) {
       hp.te_src.push_back(e.src);
       for (int w = 0; w < kTeGroup / 4; w++) {
@@ -254,6 +264,12 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
     }
     for (int s = 0; s < kTeGroup; s++) hp.te_mem.push_back(s < (int)mem.size() ? mem[s] : -1);
     hp.te_start.push_back((int32_t)hp.te_src.size());
+    // workgroup cost model (units of one source rotation of a tile): one load
+    // per entry, the rotations, and the plane contractions
+    double w = (double)ents.size();
+    for (int32_t A : mem)
+      w += (hp.plist_start[A + 1] - hp.plist_start[A]) + 4.0 * (hp.plane_start[A + 1] - hp.plane_start[A]);
+    work[g] = w;
   }
 
   // tiles: a multiple of 4 pairs (16 columns) with M pairs * M units <= 256
@@ -261,27 +277,19 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
   const int M = hp.pw.M;
   hp.te_tp = std::min(std::max(1, 4 * (256 / (4 * M))), M * M);
   const int ntile = (M * M + hp.te_tp - 1) / hp.te_tp;
-  // workgroup cost model (units of one source rotation of a tile): the
-  // rotations, one load per entry, and the plane contractions
-  const int32_t ng = (int32_t)groups.size();
-  std::vector<double> work(ng);
-  for (int32_t g = 0; g < ng; g++) {
-    double w = hp.te_start[g + 1] - hp.te_start[g];
-    for (int32_t A : groups[g])
-      w += (hp.plist_start[A + 1] - hp.plist_start[A]) + 4.0 * (hp.plane_start[A + 1] - hp.plane_start[A]);
-    work[g] = w;
-  }
+  // tile t of every group runs on XCD t % 8, so that a source tile is read
+  // into one L2; the tiles past the last multiple of 8 on the least loaded
+  // XCD; each XCD takes its workgroups longest first
+  const int fixed = ntile / kXcdCount * kXcdCount;
   std::vector<int32_t> order(ng);
   for (int32_t g = 0; g < ng; g++) order[g] = g;
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
-  const int fixed = ntile / kXcdCount * kXcdCount;
   std::vector<std::vector<std::pair<int32_t, int32_t>>> q(kXcdCount);
   std::vector<double> load(kXcdCount, 0.0);
   for (int32_t g : order)
     for (int t = 0; t < ntile; t++) {
       int x = t % kXcdCount;
-      if (t >= fixed)
-        x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      if (t >= fixed) x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
       q[x].push_back({g, t});
       load[x] += work[g];
     }

@@ -292,8 +292,8 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 
 // ---------------------------------------------------------------------------
 // d = 3 out->in translation fused with the first evaluation contraction.
-// A workgroup owns one target group (up to kTeGroup sibling cutoff boxes, with
-// the union of their P-lists: fgt_host.h te_*) and one tile of mode-column
+// A workgroup owns one target group (up to kTeGroup neighboring cutoff boxes,
+// with the union of their P-lists: fgt_host.h te_*) and one tile of mode-column
 // pairs (m1, m2).  Phase 1: a thread owns one unit (m3, pair), the 2 x 2 x 2
 // coefficients of the cos/sin members of m1, m2, m3 (four aligned pairs along
 // r2, loaded as vectors); each source box of the group is loaded once and
@@ -303,7 +303,7 @@ __device__ __forceinline__ void reduce_partials_body(const T* __restrict__ parti
 // evaluation table of every plane of its box, Z_P[i3][c] = sum_r3 E3_P[i3][r3]
 // psi_A[r3][c], the (member, plane, 16-column group) items split evenly over
 // the waves.  psi never goes to HBM.
-constexpr int kTeSlots = 4;  // member tiles held in LDS at once
+constexpr int kTeSlots = 2;  // member tiles held in LDS at once
 
 // LDS of the psi tiles: kTeSlots tiles of nr rows of 4 tp + 1 columns (odd,
 // to spread the banks)
@@ -416,7 +416,8 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
       }
     };
     auto members = [&](int e, const T (&x)[8]) {
-      const uint32_t w0 = (uint32_t)te_dir[2 * e], w1 = (uint32_t)te_dir[2 * e + 1];
+      constexpr int W = (G + 3) / 4;  // direction words per entry
+      const uint32_t w0 = (uint32_t)te_dir[W * e], w1 = W > 1 ? (uint32_t)te_dir[W * e + 1] : 0u;
 #pragma unroll
       for (int t = 0; t < G; t++) {
         const int code = (int)(((t < 4 ? w0 : w1) >> (8 * (t & 3))) & 0xFF);
@@ -430,10 +431,8 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
     for (int e = e0; e < e1; e += 2) {
       fetch(e + 1, xb);
       members(e, xa);
-      if (e + 1 < e1) {
-        fetch(e + 2, xa);
-        members(e + 1, xb);
-      }
+      fetch(e + 2, xa);
+      if (e + 1 < e1) members(e + 1, xb);
     }
   }
 
