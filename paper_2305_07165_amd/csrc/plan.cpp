@@ -256,9 +256,10 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
     const std::vector<Ent> ents = entries_of(mem);
     for (const Ent& e : ents) {
       hp.te_src.push_back(e.src);
-      for (int w = 0; w < kTeGroup / 4; w++) {
+      for (int w = 0; w < (kTeGroup + 3) / 4; w++) {  // as many words as the kernel reads
         uint32_t word = 0;
-        for (int b = 0; b < 4; b++) word |= (uint32_t)e.dir[4 * w + b] << (8 * b);
+        for (int b = 0; b < 4; b++)
+          word |= (uint32_t)(4 * w + b < kTeGroup ? e.dir[4 * w + b] : (uint8_t)kTeNoDir) << (8 * b);
         hp.te_dir.push_back((int32_t)word);
       }
     }
