@@ -114,7 +114,8 @@ def stage_work(info: dict, runs=None) -> dict:
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels_fast.hip", "kernels.h", "mfma.h"):
+    for f in ("kernels.hip", "kernels_fast.hip", "kernels.h", "mfma.h", "stage_bodies.h", "translate.h",
+              "plan.cpp"):
         with open(os.path.join(ROOT, "paper_2305_07165_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
