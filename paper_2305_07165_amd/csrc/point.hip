@@ -15,6 +15,7 @@
 
 #include "../../include/fgt.h"
 #include "../../include/fgt_point.h"
+#include "mfma.h"
 #include "plan_internal.h"
 #include "point_host.h"
 
@@ -120,6 +121,69 @@ __global__ __launch_bounds__(kPT) void k_anterp(const double* __restrict__ q, co
   }
 }
 
+// 1 (d = 3). The same proxy charges on the matrix cores: per item,
+//   Q[k1][(k2, k3)] = sum_s l_{k1}(s) G[s][(k2, k3)],  G[s][(k2, k3)] = q_s l_{k2}(s) l_{k3}(s),
+// a 16 x K x 256 product over the item's sources (K = its source count).  Wave
+// w owns the columns k3 = 4w..4w+3 (four 16 x 16 result tiles, k2 along the
+// lanes); a k-step takes four sources of the chunk, whose weights sit in LDS.
+// Rows, columns and sources past p or past the item read zero weights.
+__global__ __launch_bounds__(kPT) void k_anterp3(const double* __restrict__ q, const int32_t* __restrict__ src_perm,
+                                                 const double* __restrict__ src_xyz,
+                                                 const int32_t* __restrict__ items,
+                                                 const int32_t* __restrict__ px_coord, int lp, int p,
+                                                 const double* __restrict__ eta, const double* __restrict__ lam,
+                                                 double* __restrict__ Q, double* __restrict__ partial) {
+  typedef Mfma<double> MF;
+  constexpr int CH = 64;
+  __shared__ __align__(16) double W[CH][3][kPMax];
+  __shared__ double qs[CH];
+  const int b = items[4 * blockIdx.x], slot = items[4 * blockIdx.x + 3], tid = threadIdx.x;
+  const int s0 = items[4 * blockIdx.x + 1], s1 = items[4 * blockIdx.x + 2];
+  const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  MF::acc acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; j++) acc[j] = MF::acc{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = s0; c0 < s1; c0 += CH) {
+    const int nc = min(CH, s1 - c0);
+    if (tid < CH * 3) {
+      const int s = tid / 3, a = tid - (tid / 3) * 3;
+      double wv[kPMax];
+      if (s < nc) {
+        lagrange(p, local_coord(src_xyz[(int64_t)(c0 + s) * 3 + a], lp, px_coord[(int64_t)b * 3 + a]), eta, lam, wv);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kPMax; k++) wv[k] = 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kPMax; k++) W[s][a][k] = wv[k];
+    }
+    if (tid < CH) qs[tid] = tid < nc ? q[src_perm[c0 + tid]] : 0.0;
+    __syncthreads();
+    const int nk = (nc + 3) / 4;
+#pragma unroll 4
+    for (int kk = 0; kk < nk; kk++) {
+      const int s = 4 * kk + lk;
+      const double a1 = W[s][0][lr];
+      const double wq = qs[s] * W[s][1][lr];
+#pragma unroll
+      for (int j = 0; j < 4; j++) acc[j] = MF::step(a1, wq * W[s][2][4 * w + j], acc[j]);
+    }
+    __syncthreads();
+  }
+  // lane (lk, lr) holds rows k1 = 4t + lk of column k2 = lr in tile k3 = 4w + j
+  const int64_t pd = (int64_t)p * p * p;
+  double* out = slot >= 0 ? partial + (int64_t)slot * pd : Q + (int64_t)b * pd;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int k3 = 4 * w + j;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int k1 = MF::row(lk, t);
+      if (k1 < p && lr < p && k3 < p) out[k1 + (int64_t)p * lr + (int64_t)p * p * k3] = acc[j][t];
+    }
+  }
+}
+
 // Q of a grid split into parts: the parts' sums added in part order.  Item =
 // (grid, first slot, parts).
 __global__ __launch_bounds__(kPT) void k_anterp_reduce(const int32_t* __restrict__ items,
@@ -187,6 +251,82 @@ __global__ __launch_bounds__(kPT) void k_interp(const double* __restrict__ U, co
     u += wk3 * s3;
   }
   uw[pos] = u;
+}
+
+// 3 (d = 3). The same grid potentials on the matrix cores, per tile of 16
+// targets t:
+//   V[t][(k2, k3)] = sum_k1 l_{k1}(t) U[k1][k2][k3]      (16 x 16 x 256, k1 the K axis)
+//   u_t = sum_{k2, k3} V[t][(k2, k3)] l_{k2}(t) l_{k3}(t)  (in the lanes, then across them)
+// Work item = (grid, chunk of kPT targets): wave w takes the tiles of targets
+// 64w + 16i, i = 0..3, all waves in step (the tile's weights are written to
+// LDS between barriers).  The grid sits in LDS with the k2 stride padded to 17
+// so that the 16 lanes reading one k1 row hit distinct banks.
+__global__ __launch_bounds__(kPT) void k_interp3(const double* __restrict__ U, const int32_t* __restrict__ items,
+                                                 const int32_t* __restrict__ px_tgt,
+                                                 const int32_t* __restrict__ px_coord, int lp, int p,
+                                                 const double* __restrict__ eta, const double* __restrict__ lam,
+                                                 const double* __restrict__ tgt_xyz, double* __restrict__ uw) {
+  typedef Mfma<double> MF;
+  constexpr int S2 = kPMax + 1, S3 = kPMax * S2;  // LDS strides of k2 and k3
+  __shared__ __align__(16) double Us[kPMax * S3];
+  __shared__ double Wt[4][16][3][kPMax + 1];
+  const int b = items[2 * blockIdx.x], tb = items[2 * blockIdx.x + 1], tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  const int64_t pd = (int64_t)p * p * p;
+  for (int e = tid; e < kPMax * kPMax * kPMax; e += kPT) {
+    const int k1 = e % kPMax, k2 = (e / kPMax) % kPMax, k3 = e / (kPMax * kPMax);
+    const bool in = k1 < p && k2 < p && k3 < p;
+    Us[k1 + S2 * k2 + S3 * k3] = in ? U[(int64_t)b * pd + k1 + p * k2 + p * p * k3] : 0.0;
+  }
+  const int t1 = px_tgt[2 * b + 1];
+  for (int i = 0; i < 4; i++) {
+    const int base = tb + 64 * w + 16 * i;
+    if (lane < 48) {
+      const int tt = lane & 15, a = lane >> 4;
+      const int pos = base + tt;
+      double wv[kPMax];
+      if (pos < t1) {
+        lagrange(p, local_coord(tgt_xyz[(int64_t)pos * 3 + a], lp, px_coord[(int64_t)b * 3 + a]), eta, lam, wv);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kPMax; k++) wv[k] = 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kPMax; k++) Wt[w][tt][a][k] = wv[k];
+    }
+    __syncthreads();  // the grid (first pass) and this tile's weights are in LDS
+    if (base < t1) {  // uniform over the wave
+      double a1[4], w2[4], part[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) a1[kk] = Wt[w][lr][0][4 * kk + lk];  // A[t = lr][k1 = 4kk + lk]
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        w2[j] = Wt[w][MF::row(lk, j)][1][lr];  // l_{k2 = lr} of target 4j + lk
+        part[j] = 0.0;
+      }
+#pragma unroll 4
+      for (int k3 = 0; k3 < p; k3++) {
+        MF::acc v = MF::acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) v = MF::step(a1[kk], Us[(4 * kk + lk) + S2 * lr + S3 * k3], v);
+#pragma unroll
+        for (int j = 0; j < 4; j++) part[j] += v[j] * w2[j] * Wt[w][MF::row(lk, j)][2][k3];
+      }
+      // sum over k2: the 16 lanes lr of each row
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+        for (int j = 0; j < 4; j++) part[j] += __shfl_xor(part[j], off);
+      if (lr == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int pos = base + MF::row(lk, j);
+          if (pos < t1) uw[pos] = part[j];
+        }
+      }
+    }
+    __syncthreads();  // the tile's weights have been read
+  }
 }
 
 // 4. One chunk of kPT targets of a leaf (work item = (leaf, first target)):
@@ -408,7 +548,7 @@ int fgt_point_execute(fgt_point_plan_t* pp, const double* q, double* u) {
   if (pp->pw && npx > 0) {
     const unsigned na = (unsigned)(ph.anterp_items.size() / 4), nred = (unsigned)(ph.reduce_items.size() / 3);
     if (d == 3)
-      hipLaunchKernelGGL(fgt::k_anterp<3>, dim3(na), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
+      hipLaunchKernelGGL(fgt::k_anterp3, dim3(na), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
                          pp->anterp_items, pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->Q, pp->partial);
     else
       hipLaunchKernelGGL(fgt::k_anterp<2>, dim3(na), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
@@ -421,7 +561,7 @@ int fgt_point_execute(fgt_point_plan_t* pp, const double* q, double* u) {
     const unsigned nb = (unsigned)(ph.interp_items.size() / 2);
     if (nb > 0) {
       if (d == 3)
-        hipLaunchKernelGGL(fgt::k_interp<3>, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->interp_items, pp->px_tgt,
+        hipLaunchKernelGGL(fgt::k_interp3, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->interp_items, pp->px_tgt,
                            pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->tgt_xyz, pp->uw);
       else
         hipLaunchKernelGGL(fgt::k_interp<2>, dim3(nb), dim3(fgt::kPT), 0, st, pp->U, pp->interp_items, pp->px_tgt,
