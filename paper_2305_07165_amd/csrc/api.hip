@@ -161,6 +161,7 @@ int setup_device(fgt_plan_t* pl, const fgt_opts_t* opts) {
       (rc = upload_i32(pl, hp.plane_start, &a.plane_start)) ||
       (rc = upload_i32(pl, hp.plane_tab, &a.plane_tab)) || (rc = upload_i32(pl, hp.plane_row, &a.plane_row)) ||
       (rc = upload_i32(pl, hp.row_start, &a.row_start)) || (rc = upload_i32(pl, hp.row_tab, &a.row_tab)) ||
+      (rc = upload_i32(pl, hp.plane_order, &a.plane_order)) ||
       (rc = upload_i32(pl, hp.te_start, &a.te_start)) || (rc = upload_i32(pl, hp.te_mem, &a.te_mem)) ||
       (rc = upload_i32(pl, hp.te_src, &a.te_src)) || (rc = upload_i32(pl, hp.te_dir, &a.te_dir)) ||
       (rc = upload_i32(pl, hp.te_wg, &a.te_wg)))
@@ -545,6 +546,7 @@ int64_t fgt_plan_array(const fgt_plan_t* pl, const char* name, void* dst, int64_
   else if (n == "plane_row") iv = &hp.plane_row;
   else if (n == "row_start") iv = &hp.row_start;
   else if (n == "row_tab") iv = &hp.row_tab;
+  else if (n == "plane_order") iv = &hp.plane_order;
   else return fail(FGT_ERR_INVALID_ARG, "unknown array name");
   if (dv) {
     if (dst && cap > 0) std::memcpy(dst, dv->data(), sizeof(double) * std::min<int64_t>(cap, dv->size()));

@@ -98,6 +98,7 @@ struct HostPlan {
   std::vector<int32_t> plane_row;     // [nPl+1] ranges of rows per plane
   std::vector<int32_t> row_start;     // [nR+1] ranges of pw leaves per row
   std::vector<int32_t> row_tab;       // [nR] the row's axis-1 table
+  std::vector<int32_t> plane_order;   // [nPl] dispatch order of the per-plane stages: most work first
   // evaluation work items: (box, first pw leaf, count) with count*p <= 64 rows
   std::vector<int32_t> echunk;        // [nE*3]
   // formation work items: (box, first unit, end unit, partial slot or -1), a unit

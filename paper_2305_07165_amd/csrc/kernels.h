@@ -57,6 +57,7 @@ struct DeviceArgs {
   int64_t nPl = 0;
   const int32_t *plane_start = nullptr, *plane_tab = nullptr, *plane_row = nullptr;
   const int32_t *row_start = nullptr, *row_tab = nullptr;
+  const int32_t* plane_order = nullptr;  // planes, most work first
   const int32_t *near_tgt = nullptr, *near_haspw = nullptr, *near_start = nullptr;
   const int32_t *near_src = nullptr, *near_tab = nullptr;
   // workspace (compute precision): Y/Z [nU][p*nr^(d-1)] (nU = planes for d = 3,

@@ -46,16 +46,19 @@ namespace fgt {
 template <typename C, int NT, int KS>
 __global__ __launch_bounds__(256) void form3_plane(
     const double* __restrict__ sigma, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
-    const int32_t* __restrict__ plane_row, const int32_t* __restrict__ row_start,
-    const int32_t* __restrict__ row_tab, const elem_t<C>* __restrict__ F, int p, int nr, elem_t<C>* __restrict__ Y) {
+    const int32_t* __restrict__ plane_order, const int32_t* __restrict__ plane_row,
+    const int32_t* __restrict__ row_start, const int32_t* __restrict__ row_tab, const elem_t<C>* __restrict__ F,
+    int p, int nr, elem_t<C>* __restrict__ Y) {
   typedef elem_t<C> T;
-  form3_plane_body<C, NT, KS>(sigma, leaf_id, leaf_tab, plane_row, row_start, row_tab, F, p, nr, Y, blockIdx.x);
+  form3_plane_body<C, NT, KS>(sigma, leaf_id, leaf_tab, plane_order, plane_row, row_start, row_tab, F, p, nr, Y,
+                              blockIdx.x);
 }
 template <typename C, int NT, int KS>
 __global__ __launch_bounds__(256) void form3_plane_b(FGT_BATCH_PARAMS) {
   typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  form3_plane_body<C, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
+  form3_plane_body<C, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, a.plane_order, a.plane_row, a.row_start,
+                              a.row_tab,
                               cptr<T>(a.F), a.p, a.nr, mptr<T>(a.Y), bid);
 }
 
@@ -111,17 +114,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 4 ? 2
 template <typename C, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1))) void eval3_plane(
     const elem_t<C>* __restrict__ Z, const int32_t* __restrict__ leaf_id, const int32_t* __restrict__ leaf_tab,
-    const int32_t* __restrict__ plane_row, const int32_t* __restrict__ row_start,
-    const int32_t* __restrict__ row_tab, const elem_t<C>* __restrict__ E, int p, int nr, double* __restrict__ u) {
+    const int32_t* __restrict__ plane_order, const int32_t* __restrict__ plane_row,
+    const int32_t* __restrict__ row_start, const int32_t* __restrict__ row_tab, const elem_t<C>* __restrict__ E,
+    int p, int nr, double* __restrict__ u) {
   typedef elem_t<C> T;
-  eval3_plane_body<C, NT>(Z, leaf_id, leaf_tab, plane_row, row_start, row_tab, E, p, nr, u, blockIdx.x);
+  eval3_plane_body<C, NT>(Z, leaf_id, leaf_tab, plane_order, plane_row, row_start, row_tab, E, p, nr, u, blockIdx.x);
 }
 template <typename C, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 3 ? 2 : 1))) void eval3_plane_b(
     FGT_BATCH_PARAMS) {
   typedef elem_t<C> T;
   FGT_BATCH_PROLOGUE
-  eval3_plane_body<C, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
+  eval3_plane_body<C, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, a.plane_order, a.plane_row, a.row_start,
+                          a.row_tab,
                           cptr<T>(a.E), a.p, a.nr, jobs[j].u, bid);
 }
 
@@ -360,7 +365,7 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
       const int N2 = nr * nr, ncol = (N2 + 63) / 64;
       const int ncol128 = (N2 + form_box_cols_of(kFormBoxSlabs) - 1) / form_box_cols_of(kFormBoxSlabs);
       hipLaunchKernelGGL((form3_plane<C, NT, KS>), dim3((unsigned)stage_blocks(a, kFormLeaf)), dim3(256), 0, st, sigma,
-                         a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, F, p, nr, Y);
+                         a.pwleaf_id, a.pwleaf_tab, a.plane_order, a.plane_row, a.row_start, a.row_tab, F, p, nr, Y);
       rec(1);
       hipLaunchKernelGGL((form_box<C, 3, NT, KS>), dim3((unsigned)stage_blocks(a, kFormBox)), dim3(256), 0, st, Y,
                          a.fitem, a.plane_tab, F, p, nr, ncol128, a.M, a.phi_tp, a.ncoef_phi, phi, static_cast<T*>(a.partial));
@@ -382,7 +387,7 @@ static void launch_nt(const DeviceArgs& a, const double* sigma, double* u, hipSt
         rec(4);
       }
       hipLaunchKernelGGL((eval3_plane<C, NT>), dim3((unsigned)stage_blocks(a, kEvalLeaf)), dim3(256), 0, st, Y,
-                         a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab, E, p, nr, u);
+                         a.pwleaf_id, a.pwleaf_tab, a.plane_order, a.plane_row, a.row_start, a.row_tab, E, p, nr, u);
       rec(5);
     } else {
       rec(1);

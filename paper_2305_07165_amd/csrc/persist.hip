@@ -82,7 +82,8 @@ __global__ __launch_bounds__(256) void class_persistent(const BatchJob* __restri
     switch (stage) {
       case kFormLeaf:
         if constexpr (D == 3)
-          form3_plane_body<C, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start,
+          form3_plane_body<C, NT, KS>(jobs[j].sigma, a.pwleaf_id, a.pwleaf_tab, a.plane_order, a.plane_row,
+                                      a.row_start,
                                       a.row_tab, cptr<T>(a.F), a.p, a.nr, mptr<T>(a.Y), bid);
         break;
       case kFormBox:
@@ -117,7 +118,8 @@ __global__ __launch_bounds__(256) void class_persistent(const BatchJob* __restri
         break;
       case kEvalLeaf:
         if constexpr (D == 3)
-          eval3_plane_body<C, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, a.plane_row, a.row_start, a.row_tab,
+          eval3_plane_body<C, NT>(cptr<T>(a.Y), a.pwleaf_id, a.pwleaf_tab, a.plane_order, a.plane_row, a.row_start,
+                                  a.row_tab,
                                   cptr<T>(a.E), a.p, a.nr, jobs[j].u, bid);
         else
           eval2_leaf_body<C, NT>(cptr<T>(a.psi), a.pwleaf_box, a.pwleaf_id, a.pwleaf_tab, cptr<T>(a.E), a.p, a.nr,

@@ -130,6 +130,18 @@ void finish_pw_lists(HostPlan& hp, std::vector<PwLeafRef>& pl, int32_t nA, const
     }
     hp.plane_row.push_back((int32_t)hp.row_tab.size());
     hp.row_start.push_back((int32_t)pl.size());
+    // planes dispatched longest first: leaves (one axis-2 product each) and
+    // rows (three times the products each, the axis-1 step) of the plane
+    const int32_t npl = (int32_t)hp.plane_row.size() - 1;
+    std::vector<int32_t> work(npl);
+    for (int32_t P = 0; P < npl; P++) {
+      const int32_t r0 = hp.plane_row[P], r1 = hp.plane_row[P + 1];
+      work[P] = (hp.row_start[r1] - hp.row_start[r0]) + 3 * (r1 - r0);
+    }
+    hp.plane_order.resize(npl);
+    for (int32_t P = 0; P < npl; P++) hp.plane_order[P] = P;
+    std::stable_sort(hp.plane_order.begin(), hp.plane_order.end(),
+                     [&](int32_t x, int32_t y) { return work[x] > work[y]; });
   }
   if (d == 3) {
     // measured: the fused kernel wins while psi is large and n_r <= 64 (up to

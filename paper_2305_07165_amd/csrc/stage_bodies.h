@@ -68,6 +68,7 @@ template <typename C, int NT, int KS>
 __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigma,
                                                  const int32_t* __restrict__ leaf_id,
                                                  const int32_t* __restrict__ leaf_tab,
+                                                 const int32_t* __restrict__ plane_order,
                                                  const int32_t* __restrict__ plane_row,
                                                  const int32_t* __restrict__ row_start,
                                                  const int32_t* __restrict__ row_tab,
@@ -80,9 +81,9 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
   constexpr int SM = MemSteps<C, KS>::value;  // sigma x F2, both from memory
   constexpr int TG = form3_tile_group(NT), NG = (NT + TG - 1) / TG;
   const int nitem = p * NG, nsplit = (nitem + 3) / 4;
-  const int P = bid / nsplit;
+  const int P = plane_order[bid / nsplit];  // planes with most work first
   const int lane = lane_of(), w = wave_of();
-  const int item = (bid - P * nsplit) * 4 + w;
+  const int item = (bid - (bid / nsplit) * nsplit) * 4 + w;
   if (item >= nitem) return;
   const int j3 = item / NG, t0 = (item - j3 * NG) * TG;
   const int lr = lane & 15, lk = lane >> 4;
@@ -636,6 +637,7 @@ template <typename C, int NT>
 __device__ __forceinline__ void eval3_plane_body(const elem_t<C>* __restrict__ Z,
                                                  const int32_t* __restrict__ leaf_id,
                                                  const int32_t* __restrict__ leaf_tab,
+                                                 const int32_t* __restrict__ plane_order,
                                                  const int32_t* __restrict__ plane_row,
                                                  const int32_t* __restrict__ row_start,
                                                  const int32_t* __restrict__ row_tab,
@@ -646,9 +648,9 @@ __device__ __forceinline__ void eval3_plane_body(const elem_t<C>* __restrict__ Z
   typedef typename M::acc acc_t;
   constexpr int Q = 4 * NT;
   const int nsplit = (p + 3) / 4;
-  const int P = bid / nsplit;
+  const int P = plane_order[bid / nsplit];  // planes with most work first
   const int lane = lane_of(), w = wave_of();
-  const int i3 = (bid - P * nsplit) * 4 + w;
+  const int i3 = (bid - (bid / nsplit) * nsplit) * 4 + w;
   if (i3 >= p) return;
   const int lr = lane & 15, lk = lane >> 4;
   const int rw0 = plane_row[P], rw1 = plane_row[P + 1];

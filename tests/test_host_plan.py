@@ -468,6 +468,11 @@ def test_planes_and_rows_partition_the_pw_leaves():
                 assert all(lv[pid[s]] == meta[0, pt[P, 2]] for s in leaves)  # one level
         assert len(keys) == ps[A + 1] - ps[A]  # planes of a box are distinct
     assert info["lc"] < lv.max() - 1
+    # dispatch order of the per-plane stages: a permutation, most work first
+    order = pl.array("plane_order")
+    assert sorted(order) == list(range(len(pr) - 1))
+    work = [(rs[pr[P + 1]] - rs[pr[P]]) + 3 * (pr[P + 1] - pr[P]) for P in order]
+    assert all(a >= b for a, b in zip(work, work[1:]))
 
 
 def test_grouped_walk_equals_per_leaf_walk():
