@@ -185,16 +185,18 @@ __global__ __launch_bounds__(kPT) void k_anterp3(const double* __restrict__ q, c
 }
 
 // Q of a grid split into parts: the parts' sums added in part order.  Item =
-// (grid, first slot, parts).
+// (grid, first slot, parts); a workgroup takes kPT nodes of one item.
 __global__ __launch_bounds__(kPT) void k_anterp_reduce(const int32_t* __restrict__ items,
                                                        const double* __restrict__ partial, int pd,
                                                        double* __restrict__ Q) {
-  const int b = items[3 * blockIdx.x], slot0 = items[3 * blockIdx.x + 1], n = items[3 * blockIdx.x + 2];
-  for (int e = threadIdx.x; e < pd; e += kPT) {
-    double sum = 0.0;
-    for (int i = 0; i < n; i++) sum += partial[(int64_t)(slot0 + i) * pd + e];
-    Q[(int64_t)b * pd + e] = sum;
-  }
+  const int nchunk = (pd + kPT - 1) / kPT;
+  const int r = blockIdx.x / nchunk;
+  const int e = (blockIdx.x - r * nchunk) * kPT + threadIdx.x;
+  if (e >= pd) return;
+  const int b = items[3 * r], slot0 = items[3 * r + 1], n = items[3 * r + 2];
+  double sum = 0.0;
+  for (int i = 0; i < n; i++) sum += partial[(int64_t)(slot0 + i) * pd + e];
+  Q[(int64_t)b * pd + e] = sum;
 }
 
 // 3. The grid potential of one plane-wave box's grid at one chunk of its
@@ -356,7 +358,7 @@ __global__ __launch_bounds__(kPT) void k_direct(const double* __restrict__ q, co
     const int pos = tb + tid;
     const bool mine = pos < t1;
     double x[3] = {0.0, 0.0, 0.0};
-    if (mine)
+    if (mine && e0 < e1)  // coordinates only where there is a direct part
       for (int a = 0; a < D; a++) x[a] = tgt_xyz[(int64_t)pos * D + a];
     double acc = 0.0;
     for (int e = e0; e < e1; e++) {
@@ -553,9 +555,12 @@ int fgt_point_execute(fgt_point_plan_t* pp, const double* q, double* u) {
     else
       hipLaunchKernelGGL(fgt::k_anterp<2>, dim3(na), dim3(fgt::kPT), 0, st, q, pp->src_perm, pp->src_xyz,
                          pp->anterp_items, pp->px_coord, ph.lp, ph.p, pp->eta, pp->lam, pp->Q, pp->partial);
-    if (nred > 0)
-      hipLaunchKernelGGL(fgt::k_anterp_reduce, dim3(nred), dim3(fgt::kPT), 0, st, pp->reduce_items, pp->partial,
-                         (int)(d == 3 ? ph.p * ph.p * ph.p : ph.p * ph.p), pp->Q);
+    if (nred > 0) {
+      const int pd = d == 3 ? ph.p * ph.p * ph.p : ph.p * ph.p;
+      const unsigned nchunk = (unsigned)((pd + fgt::kPT - 1) / fgt::kPT);
+      hipLaunchKernelGGL(fgt::k_anterp_reduce, dim3(nred * nchunk), dim3(fgt::kPT), 0, st, pp->reduce_items,
+                         pp->partial, pd, pp->Q);
+    }
     int rc = fgt::execute_args(pp->pw->args, pp->Q, pp->U, st);
     if (rc != FGT_OK) return rc;
     const unsigned nb = (unsigned)(ph.interp_items.size() / 2);
