@@ -4,7 +4,8 @@
 // KS = ceil(p/4) node steps (FP32 always runs 4 node steps, see mfma.h).
 // Node axes are padded to 16 inside a tile.  Chained contractions pass result
 // tiles from one matrix-core product to the next in registers (mfma.h); LDS is
-// used only where a contraction runs across the tiles held by different waves.
+// used where a contraction runs across the tiles held by different waves, and
+// to share one plane's 1D tables among the waves of the plane formation.
 //
 // d = 3:
 //   form3_plane Y_P[j3][r1][r2] = sum_{rows} F1_row[r1][j1] (sum_{s in row} sum_j2 sigma_s[j3][j2][j1] F2_s[r2][j2])

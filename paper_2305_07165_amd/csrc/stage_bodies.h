@@ -60,7 +60,8 @@ struct MemSteps {
 // axis-1 position (fgt_host.h).  By separability
 //   Y_P[j3][r1][r2] = sum_rows F1_row[r1][j1] (sum_{s in row} sum_j2 sigma_s[j3][j2][j1] F2_s[r2][j2])
 // and the last axis then runs once per plane instead of once per leaf.  A wave
-// owns one item (j3 slice, group of TG r2 tiles); 4 items per workgroup:
+// owns one item (j3 slice, group of TG r2 tiles); 4 items per workgroup, which
+// share the plane's F2 and F1 tables through LDS:
 //   X^T[j1][r2] += sigma_s[j3] x F2_s      over the leaves of a row (lanes along j1)
 //   Y[r1][r2]   += F1_row x X^T            once per row (X^T chained as the B operand)
 
@@ -80,31 +81,36 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
   constexpr int S = Steps<C, KS>::value;      // chained (X^T as the B operand of Y)
   constexpr int SM = MemSteps<C, KS>::value;  // sigma x F2, both from memory
   constexpr int TG = form3_tile_group(NT), NG = (NT + TG - 1) / TG;
+  // the plane's tables, shared by the four waves, staged in LDS: F2 of the
+  // current and next leaf, F1 of the current row ([r][k], k stride 17)
+  constexpr int KP = 17, TR = 16 * NT, TSZ = TR * KP;
+  __shared__ T tabs[3 * TSZ];
   const int nitem = p * NG, nsplit = (nitem + 3) / 4;
   const int P = plane_order[bid / nsplit];  // planes with most work first
   const int lane = lane_of(), w = wave_of();
   const int item = (bid - (bid / nsplit) * nsplit) * 4 + w;
-  if (item >= nitem) return;
-  const int j3 = item / NG, t0 = (item - j3 * NG) * TG;
+  const bool active = item < nitem;  // inactive waves still stage tables and meet the barriers
+  const int j3 = active ? item / NG : 0, t0 = active ? (item - j3 * NG) * TG : 0;
   const int lr = lane & 15, lk = lane >> 4;
   const int rw0 = plane_row[P], rw1 = plane_row[P + 1];
   const int s_begin = row_start[rw0], s_end = row_start[rw1];
   const int64_t ppp = (int64_t)p * p * p;
-  // operands of leaf s; masked loads (no branches)
-  auto load = [&](int s, T (&av)[SM], T (&b2)[TG][SM]) {
+  const int tid = threadIdx.x;
+  // table t (nr x p) into LDS buffer buf, zero past nr / p
+  auto stage = [&](const T* tab, int buf) {
+    for (int e = tid; e < TR * 16; e += (int)blockDim.x) {
+      const int r = e >> 4, k = e & 15;
+      tabs[buf * TSZ + r * KP + k] = ld0<T>(tab, r * p + k, r < nr && k < p);
+    }
+  };
+  auto load_av = [&](int s, T (&av)[SM]) {
     const bool ls = s < s_end;
     const int sc = ls ? s : s_begin;
     const double* sg = sigma + (int64_t)leaf_id[sc] * ppp;
-    const T* F2 = F + (int64_t)leaf_tab[sc * 3 + 1] * nr * p;
 #pragma unroll
     for (int kk = 0; kk < SM; kk++) {
       const int k = M::kmem(kk, lk);
-      av[kk] = ld0<T>(sg, (j3 * p + k) * p + lr, ls && lr < p && k < p);  // A[j1][j2]
-#pragma unroll
-      for (int g = 0; g < TG; g++) {
-        const int r = 16 * (t0 + g) + lr;
-        b2[g][kk] = ld0<T>(F2, r * p + k, ls && r < nr && k < p);       // B[j2][r2] = F2[r2][j2]
-      }
+      av[kk] = ld0<T>(sg, (j3 * p + k) * p + lr, ls && active && lr < p && k < p);  // A[j1][j2]
     }
   };
   acc_t y[NT][TG];
@@ -115,32 +121,45 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
   acc_t x[TG];
 #pragma unroll
   for (int g = 0; g < TG; g++) zero4(x[g]);
-  T av[SM], b2[TG][SM];
-  load(s_begin, av, b2);
+  T av[SM];
+  load_av(s_begin, av);
+  stage(F + (int64_t)leaf_tab[s_begin * 3 + 1] * nr * p, 0);
+  __syncthreads();
   int rw = rw0;
   int row_end = row_start[rw0 + 1];
   for (int s = s_begin; s < s_end; s++) {
-    T avn[SM], b2n[TG][SM];
-    load(s + 1, avn, b2n);
+    const int cur = (s - s_begin) & 1;
+    T avn[SM];
+    load_av(s + 1, avn);
+    if (s + 1 < s_end) stage(F + (int64_t)leaf_tab[(s + 1) * 3 + 1] * nr * p, cur ^ 1);
+    if (active) {
 #pragma unroll
-    for (int g = 0; g < TG; g++)
-      x[g] = M::template steps<SM>(av, b2[g], x[g]);
-    if (s + 1 == row_end) {
-      const T* F1 = F + (int64_t)row_tab[rw] * nr * p;
+      for (int g = 0; g < TG; g++) {
+        T b2[SM];
 #pragma unroll
-      for (int tj = 0; tj < NT; tj++) {
-        T a1[S];
-#pragma unroll
-        for (int kk = 0; kk < S; kk++) {
-          const int k = M::kidx(kk, lk), r = 16 * tj + lr;
-          a1[kk] = ld0<T>(F1, r * p + k, r < nr && k < p);  // A[r1][j1]
+        for (int kk = 0; kk < SM; kk++) {
+          const int k = M::kmem(kk, lk);
+          b2[kk] = tabs[cur * TSZ + (16 * (t0 + g) + lr) * KP + k];  // B[j2][r2] = F2[r2][j2]
         }
+        x[g] = M::template steps<SM>(av, b2, x[g]);
+      }
+    }
+    if (s + 1 == row_end) {
+      stage(F + (int64_t)row_tab[rw] * nr * p, 2);
+      __syncthreads();
+      if (active) {
 #pragma unroll
-        for (int g = 0; g < TG; g++) {
-          T xb[S];
+        for (int tj = 0; tj < NT; tj++) {
+          T a1[S];
 #pragma unroll
-          for (int kk = 0; kk < S; kk++) xb[kk] = x[g][kk];
-          y[tj][g] = M::template steps<S>(a1, xb, y[tj][g]);
+          for (int kk = 0; kk < S; kk++) a1[kk] = tabs[2 * TSZ + (16 * tj + lr) * KP + M::kidx(kk, lk)];  // A[r1][j1]
+#pragma unroll
+          for (int g = 0; g < TG; g++) {
+            T xb[S];
+#pragma unroll
+            for (int kk = 0; kk < S; kk++) xb[kk] = x[g][kk];
+            y[tj][g] = M::template steps<S>(a1, xb, y[tj][g]);
+          }
         }
       }
 #pragma unroll
@@ -148,13 +167,11 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
       rw++;
       if (rw < rw1) row_end = row_start[rw + 1];
     }
+    __syncthreads();  // the next leaf's table is staged; this leaf's and row's are read
 #pragma unroll
-    for (int kk = 0; kk < SM; kk++) {
-      av[kk] = avn[kk];
-#pragma unroll
-      for (int g = 0; g < TG; g++) b2[g][kk] = b2n[g][kk];
-    }
+    for (int kk = 0; kk < SM; kk++) av[kk] = avn[kk];
   }
+  if (!active) return;
   T* Yp = Y + (int64_t)P * p * nr * nr;
 #pragma unroll
   for (int g = 0; g < TG; g++) {
