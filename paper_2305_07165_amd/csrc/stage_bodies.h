@@ -209,8 +209,9 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
                                                 elem_t<C>* __restrict__ phi,
                                                 elem_t<C>* __restrict__ partial, int bid) {
   typedef elem_t<C> T;
-  // one work item (<= kFormLeaves leaves of a box) x 64 H columns per
+  // one work item (<= kFormLeaves units of a box) x 64 H columns per
   // workgroup; every wave owns H 16-column slabs, sharing the table operand
+  // (staged in LDS)
   typedef Mfma<C> M;
   typedef typename M::acc acc_t;
   constexpr int S = MemSteps<C, KS>::value;  // Y and F3 both come from memory
@@ -233,30 +234,45 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
 #pragma unroll
     for (int h = 0; h < H; h++) zero4(acc[ti][h]);
   const int s0 = fitem[4 * item + 1], s1 = fitem[4 * item + 2];
-  // operands of leaf s; loads are masked, not branched, so that no control-flow
-  // join forces a wait for the prefetched leaf before the current products
-  auto load = [&](int s, T (&aa)[NT][S], T (&bb)[S][H]) {
+  // the units' last-axis tables, shared by the four waves, staged in LDS ([r][k],
+  // k stride 17), two buffers: the next unit's is written during the products
+  constexpr int KP = 17, TSZ = 16 * NT * KP;
+  __shared__ T tabs[2 * TSZ];
+  const int tid = threadIdx.x;
+  auto stage = [&](int s, int buf) {
+    const T* Fs = F + (int64_t)leaf_tab[s * D + (D - 1)] * nr * p;
+    for (int e = tid; e < 16 * NT * 16; e += (int)blockDim.x) {
+      const int r = e >> 4, k = e & 15;
+      tabs[buf * TSZ + r * KP + k] = ld0<T>(Fs, r * p + k, r < nr && k < p);
+    }
+  };
+  // Y operands of unit s; loads are masked, not branched, so that no
+  // control-flow join forces a wait for the prefetched unit before the products
+  auto load = [&](int s, T (&bb)[S][H]) {
     const bool ls = s < s1;
     const int sc = ls ? s : s0;
-    const T* Fs = F + (int64_t)leaf_tab[sc * D + (D - 1)] * nr * p;
     const T* Ys = Y + (int64_t)sc * p * N2;
 #pragma unroll
     for (int kk = 0; kk < S; kk++) {
       const int k = M::kmem(kk, lk);
 #pragma unroll
       for (int h = 0; h < H; h++) bb[kk][h] = ld0<T>(Ys, (int64_t)k * N2 + col[h], ls && k < p && colok[h]);
-#pragma unroll
-      for (int ti = 0; ti < NT; ti++) {
-        const int r = 16 * ti + lr;
-        aa[ti][kk] = ld0<T>(Fs, r * p + k, ls && r < nr && k < p);
-      }
     }
   };
-  T a[NT][S], b[S][H];
-  load(s0, a, b);
+  T b[S][H];
+  load(s0, b);
+  stage(s0, 0);
+  __syncthreads();
   for (int s = s0; s < s1; s++) {
-    T an[NT][S], bn[S][H];
-    load(s + 1, an, bn);
+    const int cur = (s - s0) & 1;
+    T bn[S][H];
+    load(s + 1, bn);
+    if (s + 1 < s1) stage(s + 1, cur ^ 1);
+    T a[NT][S];
+#pragma unroll
+    for (int ti = 0; ti < NT; ti++)
+#pragma unroll
+      for (int kk = 0; kk < S; kk++) a[ti][kk] = tabs[cur * TSZ + (16 * ti + lr) * KP + M::kmem(kk, lk)];
 #pragma unroll
     for (int h = 0; h < H; h++) {
       T bh[S];
@@ -265,13 +281,11 @@ __device__ __forceinline__ void form_box_body(const elem_t<C>* __restrict__ Y,
 #pragma unroll
       for (int ti = 0; ti < NT; ti++) acc[ti][h] = M::template steps<S>(a[ti], bh, acc[ti][h]);
     }
+    __syncthreads();  // the next unit's table is staged; this one's is read
 #pragma unroll
-    for (int kk = 0; kk < S; kk++) {
+    for (int kk = 0; kk < S; kk++)
 #pragma unroll
       for (int h = 0; h < H; h++) b[kk][h] = bn[kk][h];
-#pragma unroll
-      for (int ti = 0; ti < NT; ti++) a[ti][kk] = an[ti][kk];
-    }
   }
   // a box's only item writes phi; items of a split box write partial sums,
   // tile-major with tp pairs per tile when tp > 0 (d = 3, kernels.h)
