@@ -101,10 +101,10 @@ KernelClass kernel_class(const DeviceArgs& a);
 int64_t stage_blocks(const DeviceArgs& a, int stage);
 int64_t translate_blocks(const DeviceArgs& a);
 // Workgroups of the d = 3 box formation with `slabs` 16-column slabs per wave
-// (tile 0 of a batched launch: 4 slabs, as fgt_execute; tile 1: 2 slabs).
+// (tile 0 of a batched launch: 2 slabs, as fgt_execute; tile 1: 4 slabs).
 int64_t form_box_blocks(const DeviceArgs& a, int slabs);
 constexpr int kFormBoxTiles = 2;
-constexpr int kFormBoxTileSlabs[kFormBoxTiles] = {4, 2};
+constexpr int kFormBoxTileSlabs[kFormBoxTiles] = {2, 4};
 
 // Block b of a batched launch belongs to the last job j with start[j] <= b.
 __device__ __forceinline__ int batch_job_of(const int32_t* __restrict__ start, int njobs, int b) {

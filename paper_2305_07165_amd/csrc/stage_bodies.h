@@ -190,12 +190,11 @@ __device__ __forceinline__ void form3_plane_body(const double* __restrict__ sigm
 // last-axis formation merged over the leaves of a cutoff box (a grouped GEMM)
 
 // Tile shape of form_box: 16-column slabs per wave (H); a workgroup covers
-// 64 H columns.  fgt_execute uses kFormBoxSlabs: on the 3D benchmark tree 4
-// slabs beat 2, 3 and (for nt <= 3) 8 -- independent product chains per wave
-// matter more than occupancy (4 slabs leave one wave per SIMD at p = 16 in
-// FP64).  Batches may run a class with the other shape, kFormBoxSlabsAlt, when
-// the autotuner measures it faster; the columns and the order of every sum
-// are the same, so results are identical.
+// 64 H columns.  fgt_execute uses kFormBoxSlabs = 2: with the table operand
+// shared through LDS, 2 slabs (more waves per SIMD) beat 4 on the 3D benchmark
+// tree; with the table loaded by every wave, 4 had beaten 2, 3 and 8.  The
+// other shape, kFormBoxSlabsAlt, is kept for batched launches; the columns and
+// the order of every sum are the same, so results are identical.
 constexpr int kFormBoxSlabs = kFormBoxTileSlabs[0];
 constexpr int kFormBoxSlabsAlt = kFormBoxTileSlabs[1];
 __host__ __device__ constexpr int form_box_cols_of(int slabs) { return 64 * slabs; }
