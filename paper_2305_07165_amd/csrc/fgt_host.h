@@ -18,6 +18,8 @@ constexpr int kFormLeaves = 8; // leaves per formation work item
 constexpr double kFuseBytes = 128e6;  // psi bytes above which the 3D translation is fused
 constexpr int kTeGroup = 4;    // target boxes per fused-translation group (siblings)
 constexpr int kTeNoDir = 0xFF; // group entry: the member does not take this source
+constexpr int kTeTail = 288;   // fused translation: workgroups per XCD run longest first at the end
+                               // (three rounds of 32 CUs x 3 resident workgroups)
 constexpr int kXcdCount = 8;   // XCDs (separate L2s) of the device; workgroup b runs on b % 8
 
 // Plane-wave parameters of Theorem 1 for tolerance eps and range R (units of
@@ -76,18 +78,22 @@ struct HostPlan {
   // children of one parent at level lc - 1 that share their position along
   // axis 3, each with the union of its members' P-lists.
   // Entry e of group g is a source box te_src[e] and, per member slot t, its
-  // direction code in the member's P-list (byte t % 4 of te_dir[2e + t / 4];
-  // kTeNoDir: not in it).  A member meets its own P-list in its own order.
+  // direction code in the member's P-list (byte t % 4 of te_dir[W e + t / 4],
+  // W = (kTeGroup + 3) / 4 words per entry; kTeNoDir: not in it).  A member
+  // meets its own P-list in its own order, and the members of an entry share
+  // the axis-3 part of their codes (code / 9).
   std::vector<int32_t> te_start;      // [nG+1] ranges of entries per group
   std::vector<int32_t> te_mem;        // [nG*kTeGroup] member box per slot, -1 = empty
   std::vector<int32_t> te_src;        // [nTE]
-  std::vector<int32_t> te_dir;        // [nTE*2] packed direction codes
+  std::vector<int32_t> te_dir;        // [nTE*W] packed direction codes
   // tiles of the fused translation: te_tp (m1, m2) mode pairs each (kernels.h
   // keeps phi tile-major with the same tiles); workgroup b of the launch runs
   // group te_wg[2b] on tile te_wg[2b+1] (-1: nothing).  Tile t of every group
   // runs on XCD t % 8 (b % 8 is the XCD of workgroup b) so that a source tile
-  // is read into one L2, the tiles past the last multiple of 8 on the least
-  // loaded XCD, and each XCD takes its workgroups longest first.
+  // is read into one L2; each XCD sweeps its tiles in turn, the groups of a
+  // sweep in Morton order; the tiles past the last multiple of 8 are one sweep
+  // cut into eight runs of equal work; the last kTeTail workgroups of an XCD
+  // run longest first.
   int te_tp = 0;
   std::vector<int32_t> te_wg;         // [nWG*2]
   // d = 3 only: a plane is a run of pw leaves of one box with the same level and

@@ -227,13 +227,17 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
     }
   }
   struct Ent {
-    int32_t src, rank;
+    int32_t src, rank, d3;
     uint8_t dir[kTeGroup];
   };
-  // the entries of a member set, sorted
+  // the entries of a member set, sorted.  An entry also keys on the axis-3
+  // part of the code, so that its members share it (the kernel rotates the
+  // source along axis 3 once per entry); members at one axis-3 position meet
+  // a source box at one axis-3 offset anyway, so this splits nothing unless a
+  // box repeats in a list
   auto entries_of = [&](const std::vector<int32_t>& mem) {
     std::vector<Ent> ents;
-    std::unordered_map<uint64_t, size_t> at;  // (src, rank) -> entry
+    std::unordered_map<uint64_t, size_t> at;  // (src, rank, d3) -> entry
     for (size_t t = 0; t < mem.size(); t++) {
       const int32_t A = mem[t];
       int32_t prev = -1, rank = 0;
@@ -241,13 +245,14 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
         const int32_t B = hp.plist_src[q];
         rank = B == prev ? rank + 1 : 0;
         prev = B;
-        const uint64_t k = ((uint64_t)(uint32_t)B << 32) | (uint32_t)rank;
+        const int32_t d3 = hp.plist_dir[q] / 9;
+        const uint64_t k = ((uint64_t)(uint32_t)B << 32) | ((uint64_t)(uint32_t)rank << 2) | (uint32_t)d3;
         auto it = at.find(k);
         size_t e;
         if (it == at.end()) {
           e = ents.size();
           at.emplace(k, e);
-          Ent n{B, rank, {}};
+          Ent n{B, rank, d3, {}};
           for (int s = 0; s < kTeGroup; s++) n.dir[s] = (uint8_t)kTeNoDir;
           ents.push_back(n);
         } else {
@@ -257,7 +262,7 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
       }
     }
     std::sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) {
-      return x.src != y.src ? x.src < y.src : x.rank < y.rank;
+      return x.src != y.src ? x.src < y.src : (x.rank != y.rank ? x.rank < y.rank : x.d3 < y.d3);
     });
     return ents;
   };
@@ -290,22 +295,47 @@ void build_te_groups(HostPlan& hp, const std::vector<int32_t>& box_coord) {
   const int M = hp.pw.M;
   hp.te_tp = std::min(std::max(1, 4 * (256 / (4 * M))), M * M);
   const int ntile = (M * M + hp.te_tp - 1) / hp.te_tp;
-  // tile t of every group runs on XCD t % 8, so that a source tile is read
-  // into one L2; the tiles past the last multiple of 8 on the least loaded
-  // XCD; each XCD takes its workgroups longest first
-  const int fixed = ntile / kXcdCount * kXcdCount;
+  // Workgroup order.  Tile t of every group runs on XCD t % 8, so that a
+  // source tile is read into one L2, and each XCD sweeps its tiles one after
+  // the other with the groups in Morton order, so that the groups resident
+  // at one time share most of their sources in that L2.  The tiles past the
+  // last multiple of 8 are one such sweep cut into eight runs of equal work,
+  // one per XCD.  The last kTeTail workgroups of every XCD run longest first,
+  // so that no long group starts late.
+  auto spread = [](uint32_t v) {  // bit i of v to bit 3 i
+    uint64_t r = 0;
+    for (int i = 0; i < 21; i++) r |= (uint64_t)((v >> i) & 1u) << (3 * i);
+    return r;
+  };
+  std::vector<uint64_t> mkey(ng);
+  for (int32_t g = 0; g < ng; g++) {
+    const int32_t* c = &box_coord[(size_t)groups[g][0] * 3];
+    mkey[g] = spread((uint32_t)(c[0] >> 1)) | spread((uint32_t)(c[1] >> 1)) << 1 | spread((uint32_t)c[2]) << 2;
+  }
   std::vector<int32_t> order(ng);
   for (int32_t g = 0; g < ng; g++) order[g] = g;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return mkey[x] < mkey[y]; });
+  const int fixed = ntile / kXcdCount * kXcdCount;
   std::vector<std::vector<std::pair<int32_t, int32_t>>> q(kXcdCount);
-  std::vector<double> load(kXcdCount, 0.0);
-  for (int32_t g : order)
-    for (int t = 0; t < ntile; t++) {
-      int x = t % kXcdCount;
-      if (t >= fixed) x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+  for (int t = 0; t < fixed; t++)
+    for (int32_t g : order) q[t % kXcdCount].push_back({g, t});
+  double rest = 0;
+  for (int t = fixed; t < ntile; t++)
+    for (int32_t g : order) rest += work[g];
+  double done = 0;
+  for (int t = fixed; t < ntile; t++)
+    for (int32_t g : order) {
+      const int x = std::min(kXcdCount - 1, (int)(kXcdCount * (done + 0.5 * work[g]) / rest));
       q[x].push_back({g, t});
-      load[x] += work[g];
+      done += work[g];
     }
+  for (auto& v : q) {
+    const size_t k0 = v.size() > (size_t)kTeTail ? v.size() - kTeTail : 0;
+    std::stable_sort(v.begin() + k0, v.end(), [&](const std::pair<int32_t, int32_t>& x,
+                                                  const std::pair<int32_t, int32_t>& y) {
+      return work[x.first] > work[y.first];
+    });
+  }
   size_t len = 0;
   for (auto& v : q) len = std::max(len, v.size());
   hp.te_wg.assign(2 * len * kXcdCount, -1);

@@ -343,6 +343,58 @@ inline size_t transeval_lds(int tp, int nr, size_t ts) { return (size_t)kTeSlots
 // 256 units of 8 coefficients) and nr <= 16 NT
 inline size_t transeval_lds_max(int NT, size_t ts) { return (size_t)kTeSlots * (2048 + 16 * NT) * ts; }
 
+// Translation of one unit's 8 coefficients (v = v1 + 2 v2 + 4 v3, bit a the
+// sin member along axis a + 1) by one box along axis AX + 1 in direction DD:
+// each (cos, sin) pair of that axis turns by the angle of its mode, the
+// real form of the diagonal translation T_{out->in} of Eq. (diagonaltranslation)
+// (c, s: cosine and sine of that angle for the unit's mode on the axis).  In
+// place:
+template <int AX, int DD, typename T>
+__device__ __forceinline__ void te_rotate(T c, T sn, T (&y)[8]) {
+  const T s = DD > 0 ? sn : -sn;
+  constexpr int bit = 1 << AX;
+#pragma unroll
+  for (int v = 0; v < 8; v++) {
+    if (v & bit) continue;
+    const T xc = y[v], xs = y[v | bit];
+    y[v] = c * xc - s * xs;
+    y[v | bit] = s * xc + c * xs;
+  }
+}
+// ... and accumulated: a += R y
+template <int AX, int DD, typename T>
+__device__ __forceinline__ void te_rotate_acc(T c, T sn, const T (&y)[8], T (&a)[8]) {
+  const T s = DD > 0 ? sn : -sn;
+  constexpr int bit = 1 << AX;
+#pragma unroll
+  for (int v = 0; v < 8; v++) {
+    if (v & bit) continue;
+    const T xc = y[v], xs = y[v | bit];
+    a[v] = fma(c, xc, a[v]);
+    a[v] = fma(-s, xs, a[v]);
+    a[v | bit] = fma(s, xc, a[v | bit]);
+    a[v | bit] = fma(c, xs, a[v | bit]);
+  }
+}
+// a member's share of a source already turned along axis 3: a += R2 R1 y
+template <int D1, int D2, typename T>
+__device__ __forceinline__ void te_member(const T (&cs)[3], const T (&sn)[3], const T (&y)[8], T (&a)[8]) {
+  if constexpr (D1 != 0 && D2 != 0) {
+    T z[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) z[v] = y[v];
+    te_rotate<0, D1>(cs[0], sn[0], z);
+    te_rotate_acc<1, D2>(cs[1], sn[1], z, a);
+  } else if constexpr (D1 != 0) {
+    te_rotate_acc<0, D1>(cs[0], sn[0], y, a);
+  } else if constexpr (D2 != 0) {
+    te_rotate_acc<1, D2>(cs[1], sn[1], y, a);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 8; v++) a[v] += y[v];
+  }
+}
+
 template <typename C, int NT>
 __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ phi,
                                                 const int32_t* __restrict__ te_start,
@@ -408,51 +460,37 @@ __device__ __forceinline__ void transeval3_body(const elem_t<C>* __restrict__ ph
         x[v | 2] = v2.y;
       }
     };
-    // rotations along every displaced axis of direction `code`; the last one
-    // adds straight into a
-    auto apply = [&](int code, const T (&x)[8], T (&a)[8]) {
-      const int dd[3] = {code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1};
-      const int last = dd[2] != 0 ? 2 : (dd[1] != 0 ? 1 : (dd[0] != 0 ? 0 : -1));
-      T y[8];
-#pragma unroll
-      for (int v = 0; v < 8; v++) y[v] = x[v];
-#pragma unroll
-      for (int ax = 0; ax < 3; ax++) {
-        if (dd[ax] == 0) continue;
-        const T c = cs[ax], s = dd[ax] > 0 ? sn[ax] : -sn[ax];
-        const int bit = 1 << ax;
-        if (ax == last) {
-#pragma unroll
-          for (int v = 0; v < 8; v++) {
-            if (v & bit) continue;
-            const T xc = y[v], xs = y[v | bit];
-            a[v] = fma(c, xc, a[v]);
-            a[v] = fma(-s, xs, a[v]);
-            a[v | bit] = fma(s, xc, a[v | bit]);
-            a[v | bit] = fma(c, xs, a[v | bit]);
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < 8; v++) {
-            if (v & bit) continue;
-            const T xc = y[v], xs = y[v | bit];
-            y[v] = c * xc - s * xs;
-            y[v | bit] = s * xc + c * xs;
-          }
-        }
-      }
-      if (last < 0) {
-#pragma unroll
-        for (int v = 0; v < 8; v++) a[v] += y[v];
-      }
-    };
-    auto members = [&](int e, const T (&x)[8]) {
+    // Members share the axis-3 offset of an entry's source (fgt_host.h), so
+    // the source is rotated along axis 3 once, in place, and every member
+    // then applies only its own axis-1 and axis-2 rotations, the last of them
+    // straight into its accumulators; the offsets are compile-time constants
+    // of te_member, selected by one uniform branch per member.
+    auto members = [&](int e, T (&x)[8]) {
       constexpr int W = (G + 3) / 4;  // direction words per entry
-      const uint32_t w0 = (uint32_t)te_dir[W * e], w1 = W > 1 ? (uint32_t)te_dir[W * e + 1] : 0u;
+      uint32_t wd[W];
+#pragma unroll
+      for (int i = 0; i < W; i++) wd[i] = (uint32_t)te_dir[W * e + i];
+      uint32_t cmin = 0xFFu;  // any present member's code
+#pragma unroll
+      for (int t = 0; t < G; t++) cmin = min(cmin, (wd[t >> 2] >> (8 * (t & 3))) & 0xFFu);
+      const int d3 = (int)(cmin / 9) - 1;
+      if (d3 > 0) te_rotate<2, 1>(cs[2], sn[2], x);
+      if (d3 < 0) te_rotate<2, -1>(cs[2], sn[2], x);
 #pragma unroll
       for (int t = 0; t < G; t++) {
-        const int code = (int)(((t < 4 ? w0 : w1) >> (8 * (t & 3))) & 0xFF);
-        if (code != kTeNoDir) apply(code, x, acc[t]);
+        const int code = (int)((wd[t >> 2] >> (8 * (t & 3))) & 0xFFu);
+        if (code == kTeNoDir) continue;
+        switch (code % 9) {  // (d1 + 1) + 3 (d2 + 1)
+          case 0: te_member<-1, -1>(cs, sn, x, acc[t]); break;
+          case 1: te_member<0, -1>(cs, sn, x, acc[t]); break;
+          case 2: te_member<1, -1>(cs, sn, x, acc[t]); break;
+          case 3: te_member<-1, 0>(cs, sn, x, acc[t]); break;
+          case 4: te_member<0, 0>(cs, sn, x, acc[t]); break;
+          case 5: te_member<1, 0>(cs, sn, x, acc[t]); break;
+          case 6: te_member<-1, 1>(cs, sn, x, acc[t]); break;
+          case 7: te_member<0, 1>(cs, sn, x, acc[t]); break;
+          default: te_member<1, 1>(cs, sn, x, acc[t]); break;
+        }
       }
     };
     // two sources in flight: the loads of entry e+1 are issued before the

@@ -626,8 +626,12 @@ def test_fused_translation_groups(frac, periodic):
                 A = members[t]
                 # the member meets exactly its P-list, in its order
                 assert got == list(zip(src[ps[A]:ps[A + 1]].tolist(), code[ps[A]:ps[A + 1]].tolist()))
-        # every entry serves some member
-        assert all(any((int(tdir[e][t // 4] >> (8 * (t % 4))) & 0xFF) != 0xFF for t in range(G)) for e in es)
+        # every entry serves some member, and its members share the axis-3
+        # part of their codes (the kernel turns the source along axis 3 once)
+        for e in es:
+            codes = [int(tdir[e][t // 4] >> (8 * (t % 4))) & 0xFF for t in range(G)]
+            present = [c for c in codes if c != 0xFF]
+            assert present and len({c // 9 for c in present}) == 1
     assert np.all(seen == 1)
     # groups share sources: fewer entries than P-list pairs
     assert len(tsrc) < len(src)
