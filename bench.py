@@ -430,8 +430,7 @@ def child_batched(ctx):
     for pl in plans64:
         pl.close()
     del plans64
-    # the batch's plans never fuse the 3D translation (measured faster in a batch)
-    plans, us_seq, dtmix = seq(lambda t: t.precision, no_fuse=True)
+    plans, us_seq, dtmix = seq(lambda t: t.precision)
     ctx.log(f"{npts} points; sequential fp64 {1e3 * dt64:.2f} ms, sequential mixed {1e3 * dtmix:.2f} ms")
     b = api.Batch(plans)
     us = [torch.empty_like(s) for s in sig]

@@ -20,6 +20,8 @@ constexpr int kTeGroup = 4;    // target boxes per fused-translation group (sibl
 constexpr int kTeNoDir = 0xFF; // group entry: the member does not take this source
 constexpr int kTeTail = 288;   // fused translation: workgroups per XCD run longest first at the end
                                // (three rounds of 32 CUs x 3 resident workgroups)
+constexpr int kNearTail = 64;  // near field: targets per XCD run most sources first at the end
+                               // (one round of 32 CUs x 2 resident workgroups)
 constexpr int kXcdCount = 8;   // XCDs (separate L2s) of the device; workgroup b runs on b % 8
 
 // Plane-wave parameters of Theorem 1 for tolerance eps and range R (units of

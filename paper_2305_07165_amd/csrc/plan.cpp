@@ -732,13 +732,44 @@ int build_host_plan(int d, int64_t n, const int32_t* level, const int32_t* coord
     hp.near_start.push_back((int32_t)hp.near_src.size());
   }
   {
-    // dispatch order of the near targets: most sources first
+    // dispatch order of the near targets (workgroup b runs on XCD b % 8): the
+    // targets in Morton order are cut into eight runs of equal count, run x on
+    // XCD x, so that the targets resident on an XCD at one time are neighbors
+    // and find most of their sources' sigma in its L2; the last kNearTail of
+    // a run go most sources first, so that no long target starts late
     const int64_t nt = (int64_t)hp.near_tgt.size();
-    std::vector<int32_t> ord(nt);
-    for (int64_t i = 0; i < nt; i++) ord[i] = (int32_t)i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
-      return hp.near_start[x + 1] - hp.near_start[x] > hp.near_start[y + 1] - hp.near_start[y];
-    });
+    int lmax = 0;
+    for (int64_t i = 0; i < n; i++) lmax = std::max(lmax, (int)level[i]);
+    std::vector<uint64_t> mk(nt, 0);
+    for (int64_t i = 0; i < nt; i++) {
+      const int32_t T = hp.near_tgt[i];
+      for (int a = 0; a < d; a++) {
+        const uint32_t c = (uint32_t)coord[(int64_t)T * d + a] << (lmax - level[T]);
+        for (int b = 0; b < 32 && d * b + a < 64; b++) mk[i] |= (uint64_t)((c >> b) & 1u) << (d * b + a);
+      }
+    }
+    std::vector<int32_t> mo(nt);
+    for (int64_t i = 0; i < nt; i++) mo[i] = (int32_t)i;
+    std::stable_sort(mo.begin(), mo.end(), [&](int32_t x, int32_t y) { return mk[x] < mk[y]; });
+    auto nsrc = [&](int32_t i) { return hp.near_start[i + 1] - hp.near_start[i]; };
+    std::vector<std::vector<int32_t>> run(kXcdCount);
+    {
+      const int64_t base = nt / kXcdCount, extra = nt % kXcdCount;
+      int64_t at = 0;
+      for (int x = 0; x < kXcdCount; x++) {
+        const int64_t len = base + (x < extra ? 1 : 0);
+        run[x].assign(mo.begin() + at, mo.begin() + at + len);
+        at += len;
+        const size_t k0 = run[x].size() > (size_t)kNearTail ? run[x].size() - kNearTail : 0;
+        std::stable_sort(run[x].begin() + k0, run[x].end(),
+                         [&](int32_t u, int32_t v) { return nsrc(u) > nsrc(v); });
+      }
+    }
+    std::vector<int32_t> ord;
+    ord.reserve(nt);
+    for (size_t k = 0; k < run[0].size(); k++)  // run 0 is a longest one
+      for (int x = 0; x < kXcdCount; x++)
+        if (k < run[x].size()) ord.push_back(run[x][k]);
     std::vector<int32_t> tg, hpw, st{0}, src, tab;
     for (int32_t i : ord) {
       tg.push_back(hp.near_tgt[i]);

@@ -651,3 +651,37 @@ def test_fused_translation_groups(frac, periodic):
         assert set(sizes) == {G}
     else:
         assert min(sizes) < 8
+
+
+@pytest.mark.parametrize("frac,periodic", [(0.05, False), (0.3, True)])
+def test_near_target_order(frac, periodic):
+    """Near targets: every target once with its own list; the targets of XCD x
+    (positions b with b % 8 == x) are the x-th of eight equal-count runs of the
+    targets in Morton order; the last 64 of a run go most sources first."""
+    lv, cs = _two_level_tree(3, frac)
+    pl = _plan(lv, cs, 4, 1e-4, 1e-6, periodic=periodic)
+    tg, st = pl.array("near_tgt"), pl.array("near_start")
+    nt = len(tg)
+    assert nt > 8 * 64 and len(set(tg.tolist())) == nt and st[0] == 0
+    lmax = int(lv.max())
+
+    def morton(T):
+        v = 0
+        for a in range(3):
+            c = int(cs[T][a]) << (lmax - int(lv[T]))
+            for b in range(21):
+                v |= ((c >> b) & 1) << (3 * b + a)
+        return v
+
+    mk = sorted((morton(T), T) for T in tg.tolist())
+    base, extra = divmod(nt, 8)
+    at = 0
+    for x in range(8):
+        n_x = base + (1 if x < extra else 0)
+        run = tg[x::8]
+        assert len(run) == n_x
+        assert {T for _, T in mk[at:at + n_x]} == set(run.tolist())
+        at += n_x
+        ns = [int(st[b + 1] - st[b]) for b in range(x, nt, 8)]
+        tail = ns[max(0, n_x - 64):]
+        assert tail == sorted(tail, reverse=True)
