@@ -196,7 +196,8 @@ int fgt_periodic_terms(double eps, double delta);
  * "pwleaf_id", "pwleaf_tab", "pwleaf_box", "box_order", "plist_start",
  * "plist_src", "plist_dir", "echunk", "fitem", "fred", "near_tgt",
  * "near_haspw", "near_start", "near_src", "near_tab", "ftab_meta", "vtab_meta",
- * "plane_start", "plane_tab", "plane_row", "row_start", "row_tab", and the
+ * "plane_start", "plane_tab", "plane_row", "row_start", "row_tab",
+ * "plane_order" (planes in dispatch order), and the
  * fused translation's target groups "te_start", "te_mem" (4 member boxes per
  * group, -1 = empty), "te_src", "te_dir" (one word per entry, byte t the
  * direction code of member t, 0xFF = not a source of it) and its workgroups
